@@ -1,0 +1,267 @@
+/*
+ * Adaptive sparse matrix-vector multiply for AMD Instinct MI355X (gfx950).
+ *
+ * The caller hands over one matrix in CSR form; the library measures its
+ * structure on the GPU, picks a storage format (CSR, COO, ELL or DIA) and a
+ * kernel for it, converts the matrix into plan-owned device memory and then
+ * computes y = A x as often as asked.  This is the input-adaptive auto-tuner
+ * of Li, Zhang, Tan and Chen, "SMAT: An Input Adaptive Sparse Matrix-Vector
+ * Multiplication Auto-Tuner" (arXiv 1210.2536): a CSR-based interface
+ * (Section 3), the four basic formats (Section 2.1), the feature parameters
+ * of Table 3 (Section 4), a learned format model (Section 5) and the runtime
+ * search with execute-and-measure refinement (Section 6).
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named *_dev are device pointers (HIP device memory of the
+ *     current device); all other pointers are host pointers.
+ *   - `stream` is a hipStream_t handle passed as void* (NULL = the null
+ *     stream).  Work is enqueued on it; functions that must read results
+ *     back synchronise that stream and say so.
+ *   - Indices are 0-based int32.  nnz and every padded slot count must stay
+ *     below 2^31 for the int32 paths (else SPMV_EUNSUPPORTED).
+ *   - Values are float32 (SPMV_F32) or float64 (SPMV_F64).  float32 kernels
+ *     multiply and accumulate in float64 and round once per output.
+ *   - Errors: every function returns a spmv_status; a negative value is an
+ *     error and spmv_last_error() then describes it (thread-local string).
+ *     Launch failures are SPMV_EDEVICE; faults inside a kernel surface at the
+ *     caller's next synchronisation.
+ *   - Thread safety: distinct plans may be used from distinct threads; one
+ *     plan must not run on two streams at the same time (its COO carry and
+ *     batch ticket scratch are per plan).
+ */
+#ifndef SMAT_SPMV_H
+#define SMAT_SPMV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { SPMV_F32 = 0, SPMV_F64 = 1 } spmv_dtype;
+
+typedef enum {
+    SPMV_OK = 0,
+    SPMV_EINVAL = -1,        /* bad argument or non-canonical CSR */
+    SPMV_ENOMEM = -2,        /* device allocation failed */
+    SPMV_EDEVICE = -3,       /* HIP runtime / launch error */
+    SPMV_EUNSUPPORTED = -4   /* size beyond the int32 paths, or a kernel that
+                                cannot represent this matrix */
+} spmv_status;
+
+/* Storage formats (Section 2.1). */
+typedef enum { SPMV_FMT_CSR = 0, SPMV_FMT_COO = 1, SPMV_FMT_ELL = 2, SPMV_FMT_DIA = 3 } spmv_format;
+
+/* Kernel classes: a format plus an implementation (the paper's "best
+ * implementation" per format, Section 3).  These are also the classes the
+ * learned selector scores. */
+typedef enum {
+    SPMV_K_CSR_SCALAR = 0,    /* CSR, one thread per row (plain baseline)      */
+    SPMV_K_CSR_VECTOR = 1,    /* CSR, one lane group of fixed width per row     */
+    SPMV_K_CSR_ADAPTIVE = 2,  /* CSR, rows binned by length, width per bin,
+                                 whole workgroups for long rows               */
+    SPMV_K_ELL = 3,           /* ELL, slot-major, one thread per row            */
+    SPMV_K_DIA = 4,           /* DIA, x windows staged in LDS                   */
+    SPMV_K_DIA_DIRECT = 5,    /* DIA, x read through the caches                 */
+    SPMV_K_COO = 6,           /* COO, wavefront segmented reduction             */
+    SPMV_K_COUNT = 7
+} spmv_kernel;
+
+/* How plan creation chooses the kernel (Section 6). */
+typedef enum {
+    SPMV_SELECT_RULES = 0,      /* the Section 4 thresholds, no measurement   */
+    SPMV_SELECT_MLP = 1,        /* learned model; measures the top-k when the
+                                   model's confidence margin is below tau     */
+    SPMV_SELECT_EXHAUSTIVE = 2, /* measure every feasible kernel (brute force) */
+    SPMV_SELECT_FORCED = 3      /* use opts.force_kernel                      */
+} spmv_selector_mode;
+
+/* A CSR matrix in device memory (Section 3: the unified input format).
+ * Canonical form is required: row_ptr[0] = 0, non-decreasing, row_ptr[m] =
+ * nnz; 0 <= col < n; columns strictly increasing inside each row.  Explicit
+ * zero values are allowed and kept. */
+typedef struct {
+    int64_t m, n, nnz;
+    const int32_t *row_ptr_dev;   /* m + 1 entries */
+    const int32_t *col_dev;       /* nnz entries   */
+    const void *val_dev;          /* nnz values of `dtype` */
+    int32_t dtype;                /* spmv_dtype */
+} spmv_csr;
+
+/* Tunable kernel parameters (the paper's offline "kernel search", Section 3,
+ * done here per matrix by the autotuner).  Zero means "library default". */
+typedef struct {
+    int32_t block;              /* threads per workgroup, row-parallel kernels */
+    int32_t vector_lanes;       /* CSR_VECTOR lanes per row: 1..64, power of 2 */
+    int32_t adaptive_rows_per_lane; /* CSR_ADAPTIVE: a bin of width L takes
+                                   rows of up to L * this many entries        */
+    int32_t adaptive_wg_min;    /* CSR_ADAPTIVE: rows longer than this get a
+                                   whole workgroup                            */
+    int32_t dia_rows_per_thread;/* DIA: rows per thread (tile = block * this) */
+    int32_t dia_span;           /* DIA: max offset span staged per LDS window */
+    int32_t coo_chunk;          /* COO: entries per lane per wavefront chunk  */
+    int32_t ell_unroll;         /* ELL: slots fetched per loop trip (1, 2, 4) */
+} spmv_params;
+
+typedef struct spmv_selector_s *spmv_selector_t;
+
+typedef struct {
+    int32_t selector;           /* spmv_selector_mode; default MLP when a model
+                                   is given, RULES otherwise                  */
+    int32_t force_kernel;       /* spmv_kernel for SPMV_SELECT_FORCED         */
+    float confidence_tau;       /* MLP margin (predicted log slowdown between
+                                   best and runner-up) below which candidates
+                                   are measured; default 0.1                  */
+    int32_t measure_topk;       /* candidates measured when unsure; default 3 */
+    int32_t timing_reps;        /* timed repetitions per candidate; default 5 */
+    uint32_t disable_mask;      /* bit k set: never pick kernel k             */
+    uint64_t mem_cap_bytes;     /* cap on padded ELL / DIA storage; 0 = 1/4 of
+                                   free device memory                        */
+    spmv_selector_t model;      /* learned model (NULL: rules)                */
+    int32_t autotune;           /* 1: time a few parameter points for the
+                                   chosen kernel and keep the fastest        */
+    int32_t use_params;         /* 1: take `params` as given                  */
+    spmv_params params;
+} spmv_plan_opts;
+
+/* Feature parameters of Table 3 (Section 4) plus the selector's extras.
+ * Readings: ER_DIA = NNZ / (Ndiags M), ER_ELL = NNZ / (max_RD M); var_RD is
+ * the population variance; a diagonal is "true" when 5 count > 3 length;
+ * R is the least-squares power-law exponent of the row degrees.  The
+ * diagonal census is only taken while DIA can still be feasible
+ * (max_RD M <= 20 NNZ); otherwise ndiags = -1. */
+typedef struct {
+    int64_t m, n, nnz;
+    int64_t sum_rd, sum_rd2, max_rd, min_rd;
+    int64_t ndiags, ntdiags, bandwidth, blocks4;
+    double aver_rd, var_rd, std_rd, er_dia, er_ell, ntdiags_ratio, R, block_fill;
+    int32_t dia_feasible, ell_feasible;
+} spmv_features;
+
+typedef struct {
+    int64_t m, n, nnz;
+    int32_t dtype, kernel, format, selector_used;
+    float confidence;                   /* MLP margin, -1 if not used          */
+    float mlp_scores[SPMV_K_COUNT];     /* predicted log slowdowns            */
+    int32_t n_measured;                 /* candidates timed at plan time      */
+    int32_t measured_kernel[SPMV_K_COUNT];
+    double measured_ms[SPMV_K_COUNT];   /* median run time per measured kernel */
+    uint32_t feasible_mask;             /* bit k: kernel k could be used      */
+    spmv_features features;
+    spmv_params params;                 /* parameters in effect               */
+    int32_t ell_width, dia_ndiags, dia_windows;
+    int64_t m_pad;
+    uint64_t device_bytes;              /* plan-owned device memory           */
+    double t_validate_ms, t_features_ms, t_select_ms, t_convert_ms, t_plan_ms;
+} spmv_plan_info;
+
+typedef struct spmv_plan_s *spmv_plan_t;
+typedef struct spmv_batch_s *spmv_batch_t;
+
+/* Fill `opts` with defaults.  Always OK. */
+spmv_status spmv_plan_opts_default(spmv_plan_opts *opts);
+
+/* Validate the CSR (Section 3 input), extract features (Section 4), choose a
+ * kernel (Sections 5-6), convert into plan-owned device buffers and return
+ * the plan.  The caller's CSR is only read; it may be freed after return.
+ * Synchronises `stream`.  Errors: EINVAL (NULL pointers, m/n/nnz < 0,
+ * non-canonical CSR, force_kernel out of range or infeasible), EUNSUPPORTED
+ * (nnz >= 2^31 or m, n >= 2^31), ENOMEM, EDEVICE.  On error *out = NULL. */
+spmv_status spmv_plan_create(const spmv_csr *csr, const spmv_plan_opts *opts,
+                             void *stream, spmv_plan_t *out);
+
+/* y_dev[0..m) = A x_dev[0..n) (y overwritten, never accumulated into).
+ * Asynchronous on `stream`, no allocation, no synchronisation.  x and y
+ * must not overlap (EINVAL).  m = 0 is a no-op; n = 0 allows x_dev = NULL. */
+spmv_status spmv_run(spmv_plan_t plan, const void *x_dev, void *y_dev, void *stream);
+
+/* Copy the plan's report into *out (host). */
+spmv_status spmv_plan_info_get(spmv_plan_t plan, spmv_plan_info *out);
+
+/* Release the plan and its device memory.  NULL is accepted (OK). */
+spmv_status spmv_plan_destroy(spmv_plan_t plan);
+
+/* Features only (validation included).  Synchronises `stream`. */
+spmv_status spmv_features_compute(const spmv_csr *csr, spmv_features *out, void *stream);
+
+/* Test hook: rebuild CSR from the plan's internal format (CSR->X->CSR must be
+ * the identity bit for bit).  Outputs are caller-owned device buffers of
+ * m+1, nnz and nnz elements.  Synchronises `stream`. */
+spmv_status spmv_convert_roundtrip(spmv_plan_t plan, int32_t *row_ptr_dev, int32_t *col_dev,
+                                   void *val_dev, void *stream);
+
+/* Layout export for parity tests: copy one internal array of the plan into
+ * the caller's device buffer `dst_dev` of `bytes` bytes.  `which`:
+ *   0 COO row indices (int32, nnz)     1 ELL columns (int32, K*m_pad)
+ *   2 ELL values (K*m_pad)             3 DIA offsets (int32, D)
+ *   4 DIA values (D*m_pad)             5 DIA presence bits (uint32 words)
+ *   6 CSR-adaptive row order (int32, m)
+ * EINVAL if the plan has no such array or `bytes` is too small.  On success
+ * *bytes_out (if not NULL) receives the array size.  Synchronises. */
+spmv_status spmv_plan_export(spmv_plan_t plan, int32_t which, void *dst_dev, size_t bytes,
+                             size_t *bytes_out, void *stream);
+
+/* Learned selector (the Section 5 data-mining model, here a 12-64-64-C
+ * multilayer perceptron).  `params` holds n_params float32 weights in the
+ * order W1 (64x12), b1, W2 (64x64), b2, W3 (Cx64), b3, row-major, with C =
+ * SPMV_K_COUNT; `mean` and `std` are the 12 input standardisation constants.
+ * Inputs are the raw features [m, nnz, aver_RD, max_RD, std_RD, Ndiags (nnz
+ * when not taken), NNZ/(Ndiags m), 1 - ER_ELL, R, bandwidth, block_fill,
+ * is_f64] with log1p applied to indices 0-5 and 9 before standardisation.
+ * Copies everything to the device.  Synchronous. */
+spmv_status spmv_selector_create(const float *params, int64_t n_params, const float *mean,
+                                 const float *std, spmv_selector_t *out);
+spmv_status spmv_selector_destroy(spmv_selector_t sel);
+
+/* Score raw feature rows with the selector on the GPU (inference kernel):
+ * raw_dev is float32 [rows x 12], scores_dev float32 [rows x SPMV_K_COUNT]. */
+spmv_status spmv_selector_score(spmv_selector_t sel, const float *raw_dev, int64_t rows,
+                                float *scores_dev, void *stream);
+
+/* Selector training kernels (float32, batch-major).  Shapes: x_dev [B x 12]
+ * already standardised, target_dev and mask_dev [B x C], params_dev / grad_dev
+ * / adam_m_dev / adam_v_dev [n_params] in the spmv_selector_create order,
+ * scores_dev [B x C], workspace_dev of spmv_mlp_workspace_floats(B) floats.
+ * spmv_mlp_forward   : scores = net(x)
+ * spmv_mlp_backward  : grad = d loss / d params of the masked mean squared
+ *                      error sum mask (s - t)^2 / max(1, sum mask); also
+ *                      writes the loss to *loss_dev (one float)
+ * spmv_mlp_adam      : Adam step t >= 1 with bias correction.
+ * All asynchronous on `stream`. */
+int64_t spmv_mlp_param_count(int32_t n_out);
+int64_t spmv_mlp_workspace_floats(int64_t batch);
+spmv_status spmv_mlp_forward(const float *params_dev, int32_t n_out, const float *x_dev,
+                             int64_t batch, float *scores_dev, float *workspace_dev, void *stream);
+spmv_status spmv_mlp_backward(const float *params_dev, int32_t n_out, const float *x_dev,
+                              const float *target_dev, const float *mask_dev, int64_t batch,
+                              float *grad_dev, float *loss_dev, float *workspace_dev, void *stream);
+spmv_status spmv_mlp_adam(float *params_dev, const float *grad_dev, float *adam_m_dev,
+                          float *adam_v_dev, int64_t n_params, int32_t step, float lr,
+                          float beta1, float beta2, float eps, void *stream);
+
+/* Multilevel batch (the AMG setting of Section 1): run y_l = A_l x_l for all
+ * plans in one launch (mode 0, persistent work-queue kernel) or as one
+ * captured HIP graph (mode 1).  Plans stay owned by the caller and must
+ * outlive the batch.  Persistent mode covers CSR_SCALAR, CSR_VECTOR, ELL,
+ * DIA and DIA_DIRECT levels; levels with other kernels are launched
+ * separately on the same stream, after the persistent kernel. */
+spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplans, int32_t mode,
+                              spmv_batch_t *out);
+spmv_status spmv_batch_run(spmv_batch_t batch, const void *const *xs_dev, void *const *ys_dev,
+                           void *stream);
+spmv_status spmv_batch_destroy(spmv_batch_t batch);
+
+/* Achievable-bandwidth probe: dst_dev[i] = src_dev[i] for `bytes` bytes
+ * (multiple of 16, 16-byte aligned).  Asynchronous. */
+spmv_status spmv_stream_copy(void *dst_dev, const void *src_dev, size_t bytes, void *stream);
+
+/* Readable name of a status, and the calling thread's last error text. */
+const char *spmv_status_string(spmv_status s);
+const char *spmv_last_error(void);
+const char *spmv_kernel_name(int32_t kernel);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SMAT_SPMV_H */

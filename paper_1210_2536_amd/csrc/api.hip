@@ -1,0 +1,1049 @@
+// C-ABI of the adaptive SpMV library: plan creation (validation, feature
+// extraction, kernel selection, conversion) and the run entry point.
+//
+// Plan creation follows the runtime stage of the paper (Section 6): extract
+// features (Section 4), search the format (rules in the order DIA, ELL, CSR,
+// COO, or the learned model of Section 5), execute-and-measure candidates
+// when the model is not confident, then keep the chosen format and kernel
+// ("kernel library" of Section 3) in plan-owned device memory.
+#include "plan.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+
+namespace smat {
+
+namespace {
+thread_local char g_err[1024] = "";
+}
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+}
+
+spmv_status hip_fail(hipError_t e, const char *what) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return e == hipErrorOutOfMemory ? SPMV_ENOMEM : SPMV_EDEVICE;
+}
+
+namespace {
+
+int elt_of(int dtype) { return dtype == SPMV_F64 ? 8 : 4; }
+
+int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
+
+int pow2_ceil(int64_t v) {
+    int p = 1;
+    while (p < v && p < (1 << 30)) p <<= 1;
+    return p;
+}
+
+int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+#define SMAT_TRY(expr)                              \
+    do {                                            \
+        spmv_status _s = (expr);                    \
+        if (_s != SPMV_OK) return _s;               \
+    } while (0)
+
+__global__ void k_gather_rowptr(int64_t count, const int32_t *__restrict__ rows,
+                                const int32_t *__restrict__ rp, int64_t *__restrict__ out) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    int32_t r = rows[i];
+    out[2 * i] = rp[r];
+    out[2 * i + 1] = rp[r + 1];
+}
+
+__global__ void k_fill_one(int64_t n, int elt, void *x) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (elt == 8)
+        ((double *)x)[i] = 1.0;
+    else
+        ((float *)x)[i] = 1.0f;
+}
+
+}  // namespace
+}  // namespace smat
+
+using namespace smat;
+
+namespace smat {
+namespace {
+
+// ------------------------------------------------------------------ features
+
+struct FeatureWork {
+    Dev scratch;   // RowStats + EntryStats + DiagStats + flags + fit sums
+    Dev row_hist;
+    Dev diag_hist; // m + n - 1 bins; later the diagonal -> slot map
+    bool census = false;
+};
+
+struct Scratch {
+    RowStats rs;
+    EntryStats es;
+    DiagStats ds;
+    uint32_t flags;
+    uint32_t pad;
+    double fit[5];
+};
+
+spmv_status validate_and_extract(const spmv_csr &A, hipStream_t s, spmv_features &F,
+                                 FeatureWork &W, bool keep_census, double *t_val,
+                                 double *t_feat) {
+    auto t0 = std::chrono::steady_clock::now();
+    const int64_t m = A.m, n = A.n, nnz = A.nnz;
+    SMAT_TRY(W.scratch.alloc(sizeof(Scratch)));
+    Scratch *d = W.scratch.as<Scratch>();
+    Scratch h{};
+    h.rs.min_rd = INT_MAX;
+    SMAT_HIP(hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, s));
+    SMAT_TRY(launch_validate_rows(m, nnz, A.row_ptr_dev, &d->flags, s));
+    SMAT_HIP(hipMemcpyAsync(&h.flags, &d->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SMAT_HIP(hipStreamSynchronize(s));
+    if (h.flags) {
+        set_error("invalid CSR row_ptr (flags 0x%x: %s%s%s)", h.flags,
+                  (h.flags & kBadRowPtr0) ? "row_ptr[0] != 0 " : "",
+                  (h.flags & kBadRowPtrEnd) ? "row_ptr[m] != nnz " : "",
+                  (h.flags & kBadRowPtrOrder) ? "row_ptr decreasing or out of range" : "");
+        return SPMV_EINVAL;
+    }
+    SMAT_TRY(launch_validate_entries(m, n, nnz, A.row_ptr_dev, A.col_dev, &d->flags, s));
+    SMAT_HIP(hipMemcpyAsync(&h.flags, &d->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SMAT_HIP(hipStreamSynchronize(s));
+    if (h.flags) {
+        set_error("invalid CSR columns (flags 0x%x: %s%s)", h.flags,
+                  (h.flags & kBadColRange) ? "column out of [0, n) " : "",
+                  (h.flags & kBadColOrder) ? "columns not strictly increasing in a row" : "");
+        return SPMV_EINVAL;
+    }
+    auto t1 = std::chrono::steady_clock::now();
+    // ---- row pass
+    SMAT_TRY(launch_row_stats(m, A.row_ptr_dev, &d->rs, s));
+    SMAT_HIP(hipMemcpyAsync(&h.rs, &d->rs, sizeof(RowStats), hipMemcpyDeviceToHost, s));
+    SMAT_HIP(hipStreamSynchronize(s));
+    F = spmv_features{};
+    F.m = m;
+    F.n = n;
+    F.nnz = nnz;
+    F.sum_rd = (int64_t)h.rs.sum_rd;
+    F.sum_rd2 = (int64_t)h.rs.sum_rd2;
+    F.max_rd = m ? h.rs.max_rd : 0;
+    F.min_rd = m ? h.rs.min_rd : 0;
+    F.aver_rd = m ? (double)nnz / (double)m : 0.0;
+    if (m) {
+        __int128 num = (__int128)m * (__int128)F.sum_rd2 - (__int128)F.sum_rd * F.sum_rd;
+        F.var_rd = (double)num / ((double)m * (double)m);
+    }
+    F.std_rd = std::sqrt(F.var_rd);
+    F.er_ell = F.max_rd ? (double)nnz / ((double)F.max_rd * (double)m) : 0.0;
+    F.ell_feasible = m && (__int128)F.max_rd * m <= (__int128)20 * nnz;
+    // ---- power-law fit over the row-degree histogram
+    if (m && F.max_rd >= 1) {
+        SMAT_TRY(W.row_hist.alloc(sizeof(unsigned) * (size_t)(F.max_rd + 1)));
+        SMAT_HIP(hipMemsetAsync(W.row_hist.p, 0, W.row_hist.bytes, s));
+        SMAT_TRY(launch_row_hist(m, A.row_ptr_dev, (int)F.max_rd, W.row_hist.as<unsigned>(), s));
+        SMAT_TRY(launch_powerlaw_fit(W.row_hist.as<unsigned>(), (int)F.max_rd, m, d->fit, s));
+    }
+    // ---- entry pass (+ diagonal census while DIA may still be feasible)
+    W.census = F.ell_feasible && nnz > 0;
+    if (W.census) {
+        SMAT_TRY(W.diag_hist.alloc(sizeof(unsigned) * (size_t)(m + n - 1)));
+        SMAT_HIP(hipMemsetAsync(W.diag_hist.p, 0, W.diag_hist.bytes, s));
+    }
+    SMAT_TRY(launch_entry_stats(m, n, nnz, A.row_ptr_dev, A.col_dev, &d->es,
+                                W.census ? W.diag_hist.as<unsigned>() : nullptr, s));
+    if (W.census) SMAT_TRY(launch_diag_stats(m, n, W.diag_hist.as<unsigned>(), &d->ds, s));
+    SMAT_HIP(hipMemcpyAsync(&h, d, sizeof(Scratch), hipMemcpyDeviceToHost, s));
+    SMAT_HIP(hipStreamSynchronize(s));
+    F.bandwidth = h.es.bandwidth;
+    F.blocks4 = (int64_t)h.es.blocks4;
+    F.block_fill = F.blocks4 ? (double)nnz / (16.0 * (double)F.blocks4) : 0.0;
+    F.R = (m && F.max_rd >= 1 && h.fit[0] >= 2.0 && h.fit[4] > 0) ? -h.fit[3] / h.fit[4] : 0.0;
+    if (W.census) {
+        F.ndiags = (int64_t)h.ds.ndiags;
+        F.ntdiags = (int64_t)h.ds.ntrue;
+        F.ntdiags_ratio = F.ndiags ? (double)F.ntdiags / (double)F.ndiags : 0.0;
+        F.er_dia = F.ndiags ? (double)nnz / ((double)F.ndiags * (double)m) : 0.0;
+        F.dia_feasible = (__int128)F.ndiags * m <= (__int128)20 * nnz;
+    } else {
+        F.ndiags = -1;
+        F.ntdiags = 0;
+        F.ntdiags_ratio = 0.0;
+        F.er_dia = 0.0;
+        F.dia_feasible = 0;
+    }
+    if (!keep_census || !F.dia_feasible) W.diag_hist.release();
+    W.row_hist.release();
+    auto t2 = std::chrono::steady_clock::now();
+    if (t_val) *t_val = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    if (t_feat) *t_feat = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    return SPMV_OK;
+}
+
+// ------------------------------------------------------------------ params
+
+int default_lanes(const spmv_features &F) {
+    // about two entries per lane for a row of mean length
+    int L = pow2_ceil((int64_t)std::ceil(F.aver_rd)) / 2;
+    return std::max(1, std::min(64, L));
+}
+
+spmv_params default_params(int kernel, const spmv_features &F) {
+    spmv_params p{};
+    p.block = 256;
+    p.vector_lanes = default_lanes(F);
+    p.adaptive_rows_per_lane = 2;
+    p.adaptive_wg_min = 4096;
+    p.dia_rows_per_thread = 4;
+    p.dia_span = 64;
+    p.coo_chunk = 8;
+    p.ell_unroll = 4;
+    (void)kernel;
+    return p;
+}
+
+void merge_params(spmv_params &p, const spmv_params &u) {
+    if (u.block > 0) p.block = u.block;
+    if (u.vector_lanes > 0) p.vector_lanes = u.vector_lanes;
+    if (u.adaptive_rows_per_lane > 0) p.adaptive_rows_per_lane = u.adaptive_rows_per_lane;
+    if (u.adaptive_wg_min > 0) p.adaptive_wg_min = u.adaptive_wg_min;
+    if (u.dia_rows_per_thread > 0) p.dia_rows_per_thread = u.dia_rows_per_thread;
+    if (u.dia_span > 0) p.dia_span = u.dia_span;
+    if (u.coo_chunk > 0) p.coo_chunk = u.coo_chunk;
+    if (u.ell_unroll > 0) p.ell_unroll = u.ell_unroll;
+}
+
+spmv_status check_params(const spmv_params &p) {
+    auto pow2 = [](int v) { return v > 0 && (v & (v - 1)) == 0; };
+    if (!(p.block >= 64 && p.block <= 1024 && p.block % 64 == 0)) {
+        set_error("params.block must be a multiple of 64 in [64, 1024]");
+        return SPMV_EINVAL;
+    }
+    if (!(pow2(p.vector_lanes) && p.vector_lanes <= 64)) {
+        set_error("params.vector_lanes must be a power of two <= 64");
+        return SPMV_EINVAL;
+    }
+    if (p.adaptive_rows_per_lane < 1 || p.adaptive_rows_per_lane > 64 ||
+        p.adaptive_wg_min < 64 || p.adaptive_wg_min > (1 << 20)) {
+        set_error("params.adaptive_* out of range");
+        return SPMV_EINVAL;
+    }
+    if (!(p.dia_rows_per_thread == 1 || p.dia_rows_per_thread == 2 ||
+          p.dia_rows_per_thread == 4 || p.dia_rows_per_thread == 8) ||
+        p.dia_span < 0 || p.dia_span > 8192) {
+        set_error("params.dia_rows_per_thread must be 1, 2, 4 or 8 and dia_span in [0, 8192]");
+        return SPMV_EINVAL;
+    }
+    if (p.coo_chunk < 1 || p.coo_chunk > 64) {
+        set_error("params.coo_chunk must be in [1, 64]");
+        return SPMV_EINVAL;
+    }
+    if (!(p.ell_unroll == 1 || p.ell_unroll == 2 || p.ell_unroll == 4)) {
+        set_error("params.ell_unroll must be 1, 2 or 4");
+        return SPMV_EINVAL;
+    }
+    return SPMV_OK;
+}
+
+// Longest COO chain: a row spans at most this many chunks in float64.
+constexpr int64_t kCooMaxChunksPerRow = 3000;
+constexpr int64_t kSplitSegment = 512 * 2048;          // entries per split segment
+constexpr int64_t kSplitMin = 512 * 3584;              // rows longer than this are split
+
+// Kernels that can hold this matrix (zero-fill rule, storage cap) and, when
+// `accuracy` is set, also keep every float64 summation chain short enough for
+// the 1e-12 (|A||x|)_i bound.  A forced kernel is only held to the first part.
+uint32_t feasible_mask(const spmv_features &F, int dtype, int64_t m_pad, uint64_t cap,
+                       const spmv_params &p, bool accuracy = true) {
+    const int elt = elt_of(dtype);
+    uint32_t mask = 0;
+    const bool f64 = dtype == SPMV_F64 && accuracy;
+    // CSR scalar: the sequential chain is the whole row
+    if (!f64 || F.max_rd <= kFp64MaxDepth) mask |= 1u << SPMV_K_CSR_SCALAR;
+    // CSR vector: chain ceil(max/L) + log2 L
+    {
+        int L = p.vector_lanes;
+        if (!f64 || (F.max_rd + L - 1) / L + ilog2(L) <= kFp64MaxDepth)
+            mask |= 1u << SPMV_K_CSR_VECTOR;
+    }
+    mask |= 1u << SPMV_K_CSR_ADAPTIVE;
+    if (F.ell_feasible) {
+        uint64_t bytes = (uint64_t)F.max_rd * (uint64_t)m_pad * (uint64_t)(elt + 4);
+        if (bytes <= cap && (!f64 || F.max_rd <= kFp64MaxDepth)) mask |= 1u << SPMV_K_ELL;
+    }
+    if (F.dia_feasible && F.ndiags >= 0) {
+        uint64_t bytes = (uint64_t)F.ndiags * (uint64_t)m_pad * (uint64_t)elt +
+                         (uint64_t)F.ndiags * (uint64_t)m_pad / 8;
+        if (bytes <= cap && (!f64 || F.ndiags <= kFp64MaxDepth))
+            mask |= (1u << SPMV_K_DIA) | (1u << SPMV_K_DIA_DIRECT);
+    }
+    {
+        int64_t per = (int64_t)p.coo_chunk * kWave;
+        if (!f64 || F.max_rd <= kCooMaxChunksPerRow * per) mask |= 1u << SPMV_K_COO;
+    }
+    return mask;
+}
+
+// The method without the learned part: Section 4 observations as IF-THEN
+// rules, tried in the Section 6 order (DIA, ELL, then COO on its only
+// trigger R, CSR by default).  Integer forms of every threshold.
+int rules_choose(const spmv_features &F, uint32_t feas) {
+    const __int128 M = F.m, NNZ = F.nnz;
+    const int64_t nd = F.ndiags;
+    if ((feas & (1u << SPMV_K_DIA)) && nd >= 0 && nd <= 500) {
+        if (nd < 25 || 5 * NNZ > (__int128)3 * nd * M || 5 * (__int128)F.ntdiags > 2 * (__int128)nd)
+            return SPMV_K_DIA;
+    }
+    if (feas & (1u << SPMV_K_ELL)) {
+        const __int128 mx = F.max_rd;
+        bool er_ok = 10 * NNZ > 9 * mx * M;
+        bool var_ok = 2 * (M * (__int128)F.sum_rd2 - (__int128)F.sum_rd * F.sum_rd) < M * M;
+        if (er_ok && (var_ok || F.max_rd < 5)) return SPMV_K_ELL;
+    }
+    if (F.R >= 1.0 && F.R < 4.0 && (feas & (1u << SPMV_K_COO))) return SPMV_K_COO;
+    // CSR: a fixed lane width suits rows of similar length, binning otherwise
+    if ((double)F.max_rd <= 8.0 * std::max(1.0, F.aver_rd) && (feas & (1u << SPMV_K_CSR_VECTOR)))
+        return SPMV_K_CSR_VECTOR;
+    return SPMV_K_CSR_ADAPTIVE;
+}
+
+void raw_features(const spmv_features &F, int dtype, float out[12]) {
+    double nd = F.ndiags >= 0 ? (double)F.ndiags : (double)F.nnz;
+    double dia_fill = (nd > 0 && F.m > 0) ? (double)F.nnz / (nd * (double)F.m) : 0.0;
+    double v[12] = {(double)F.m, (double)F.nnz, F.aver_rd, (double)F.max_rd, F.std_rd, nd,
+                    dia_fill, 1.0 - F.er_ell, F.R, (double)F.bandwidth, F.block_fill,
+                    dtype == SPMV_F64 ? 1.0 : 0.0};
+    for (int i = 0; i < 12; ++i) out[i] = (float)v[i];
+}
+
+// ------------------------------------------------------------------ conversion
+
+spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W, int kernel,
+                          const spmv_params &prm, hipStream_t s, Variant &V) {
+    V.kernel = kernel;
+    V.prm = prm;
+    const int64_t m = P.m, n = P.n, nnz = P.nnz;
+    const int elt = P.elt;
+    switch (kernel) {
+    case SPMV_K_CSR_SCALAR:
+    case SPMV_K_CSR_VECTOR:
+        return SPMV_OK;
+    case SPMV_K_COO: {
+        SMAT_TRY(V.row_idx.alloc(sizeof(int32_t) * (size_t)nnz));
+        SMAT_TRY(launch_csr_to_coo(m, nnz, P.rp.as<int32_t>(), V.row_idx.as<int32_t>(), s));
+        int64_t per = (int64_t)prm.coo_chunk * kWave;
+        int64_t nch = std::max<int64_t>(1, (nnz + per - 1) / per);
+        SMAT_TRY(V.coo_head.alloc(sizeof(double) * nch));
+        SMAT_TRY(V.coo_tail.alloc(sizeof(double) * nch));
+        SMAT_TRY(V.coo_flags.alloc(sizeof(uint32_t) * nch));
+        return SPMV_OK;
+    }
+    case SPMV_K_ELL: {
+        V.K = (int)F.max_rd;
+        size_t slots = (size_t)V.K * (size_t)P.m_pad;
+        SMAT_TRY(V.ecol.alloc(sizeof(int32_t) * slots));
+        SMAT_TRY(V.eval.alloc((size_t)elt * slots));
+        SMAT_TRY(launch_csr_to_ell(m, P.m_pad, V.K, P.rp.as<int32_t>(), P.col.as<int32_t>(),
+                                   P.val.p, elt, V.ecol.as<int32_t>(), V.eval.p, s));
+        return SPMV_OK;
+    }
+    case SPMV_K_DIA:
+    case SPMV_K_DIA_DIRECT: {
+        if (!W.diag_hist.p) {
+            set_error("DIA conversion needs the diagonal census");
+            return SPMV_EUNSUPPORTED;
+        }
+        V.D = (int)F.ndiags;
+        SMAT_TRY(V.dia_off.alloc(sizeof(int32_t) * std::max(1, V.D)));
+        if (P.dia_offsets.empty() && V.D > 0) {
+            // compact the census into ascending offsets; bins become slot ids
+            int64_t nbins = m + n - 1;
+            int64_t nblk = (nbins + 4095) / 4096;
+            Dev blk;
+            SMAT_TRY(blk.alloc(sizeof(unsigned) * (size_t)nblk));
+            SMAT_TRY(launch_diag_compact(m, n, W.diag_hist.as<unsigned>(), V.dia_off.as<int32_t>(),
+                                         blk.as<unsigned>(), s));
+            P.dia_offsets.resize(V.D);
+            SMAT_HIP(hipMemcpyAsync(P.dia_offsets.data(), V.dia_off.p, sizeof(int32_t) * V.D,
+                                    hipMemcpyDeviceToHost, s));
+            SMAT_HIP(hipStreamSynchronize(s));
+        } else if (V.D > 0) {
+            SMAT_HIP(hipMemcpyAsync(V.dia_off.p, P.dia_offsets.data(), sizeof(int32_t) * V.D,
+                                    hipMemcpyHostToDevice, s));
+        }
+        size_t slots = (size_t)V.D * (size_t)P.m_pad;
+        size_t words = (slots + 31) / 32;
+        SMAT_TRY(V.dia_data.alloc((size_t)elt * slots));
+        SMAT_TRY(V.dia_present.alloc(sizeof(uint32_t) * words));
+        SMAT_HIP(hipMemsetAsync(V.dia_data.p, 0, V.dia_data.bytes, s));
+        SMAT_HIP(hipMemsetAsync(V.dia_present.p, 0, V.dia_present.bytes, s));
+        SMAT_TRY(launch_csr_to_dia(m, n, P.m_pad, nnz, P.rp.as<int32_t>(), P.col.as<int32_t>(),
+                                   P.val.p, elt, W.diag_hist.as<unsigned>(), V.dia_data.p,
+                                   V.dia_present.as<uint32_t>(), s));
+        // windows of diagonals whose offsets span at most dia_span
+        std::vector<DiaWindow> win;
+        int max_span = 0;
+        for (int d = 0; d < V.D;) {
+            int e = d;
+            while (e + 1 < V.D &&
+                   (int64_t)P.dia_offsets[e + 1] - P.dia_offsets[d] <= prm.dia_span)
+                ++e;
+            win.push_back({d, e});
+            max_span = std::max(max_span, P.dia_offsets[e] - P.dia_offsets[d]);
+            d = e + 1;
+        }
+        V.nwin = (int)win.size();
+        V.max_span = max_span;
+        SMAT_TRY(V.dia_win.alloc(sizeof(DiaWindow) * std::max<size_t>(1, win.size())));
+        if (!win.empty())
+            SMAT_HIP(hipMemcpyAsync(V.dia_win.p, win.data(), sizeof(DiaWindow) * win.size(),
+                                    hipMemcpyHostToDevice, s));
+        SMAT_HIP(hipStreamSynchronize(s));
+        return SPMV_OK;
+    }
+    case SPMV_K_CSR_ADAPTIVE: {
+        BinSpec spec;
+        const int rpl = prm.adaptive_rows_per_lane;
+        for (int b = 0; b < 6; ++b) {  // widths 1..32
+            spec.upper[b] = rpl << b;
+            V.bin_lanes[b] = 1 << b;
+        }
+        spec.upper[6] = std::max(prm.adaptive_wg_min, spec.upper[5]);  // width 64
+        V.bin_lanes[6] = 64;
+        spec.upper[7] = (int)kSplitMin;   // one workgroup per row
+        spec.upper[8] = INT_MAX;          // split rows
+        V.bin_lanes[7] = 0;
+        V.bin_lanes[8] = -1;
+        unsigned nblk = (unsigned)std::max<int64_t>(1, (m + 255) / 256);
+        SMAT_TRY(V.bin_rows.alloc(sizeof(int32_t) * std::max<int64_t>(1, m)));
+        SMAT_TRY(V.bin_scratch.alloc(sizeof(unsigned) * ((size_t)nblk * kAdaptiveBins + kAdaptiveBins + 1)));
+        unsigned *blk = V.bin_scratch.as<unsigned>();
+        unsigned *offs = blk + (size_t)nblk * kAdaptiveBins;
+        SMAT_TRY(launch_bin_rows(m, P.rp.as<int32_t>(), spec, blk, V.bin_rows.as<int32_t>(), offs, s));
+        SMAT_HIP(hipMemcpyAsync(V.bin_off, offs, sizeof(V.bin_off), hipMemcpyDeviceToHost, s));
+        SMAT_HIP(hipStreamSynchronize(s));
+        // split rows: segment table on the host from their row_ptr entries
+        int64_t ns = V.bin_off[9] - V.bin_off[8];
+        if (ns > 0) {
+            Dev tmp;
+            SMAT_TRY(tmp.alloc(sizeof(int64_t) * 2 * ns));
+            k_gather_rowptr<<<(unsigned)((ns + 255) / 256), 256, 0, s>>>(
+                ns, V.bin_rows.as<int32_t>() + V.bin_off[8], P.rp.as<int32_t>(), tmp.as<int64_t>());
+            SMAT_LAUNCHED("gather_rowptr");
+            std::vector<int64_t> be(2 * ns);
+            std::vector<int32_t> rows(ns);
+            SMAT_HIP(hipMemcpyAsync(be.data(), tmp.p, sizeof(int64_t) * 2 * ns,
+                                    hipMemcpyDeviceToHost, s));
+            SMAT_HIP(hipMemcpyAsync(rows.data(), V.bin_rows.as<int32_t>() + V.bin_off[8],
+                                    sizeof(int32_t) * ns, hipMemcpyDeviceToHost, s));
+            SMAT_HIP(hipStreamSynchronize(s));
+            std::vector<int64_t> segs, begin(1, 0);
+            for (int64_t r = 0; r < ns; ++r) {
+                for (int64_t b = be[2 * r]; b < be[2 * r + 1]; b += kSplitSegment) {
+                    segs.push_back(r);
+                    segs.push_back(b);
+                    segs.push_back(std::min(b + kSplitSegment, be[2 * r + 1]));
+                }
+                begin.push_back((int64_t)segs.size() / 3);
+            }
+            V.nsplit_rows = ns;
+            V.nsplit_segs = (int64_t)segs.size() / 3;
+            SMAT_TRY(V.split_segs.alloc(sizeof(int64_t) * segs.size()));
+            SMAT_TRY(V.split_partials.alloc(sizeof(double) * V.nsplit_segs));
+            SMAT_TRY(V.split_begin.alloc(sizeof(int64_t) * begin.size()));
+            SMAT_TRY(V.split_rows.alloc(sizeof(int32_t) * ns));
+            SMAT_HIP(hipMemcpyAsync(V.split_segs.p, segs.data(), sizeof(int64_t) * segs.size(),
+                                    hipMemcpyHostToDevice, s));
+            SMAT_HIP(hipMemcpyAsync(V.split_begin.p, begin.data(), sizeof(int64_t) * begin.size(),
+                                    hipMemcpyHostToDevice, s));
+            SMAT_HIP(hipMemcpyAsync(V.split_rows.p, rows.data(), sizeof(int32_t) * ns,
+                                    hipMemcpyHostToDevice, s));
+            SMAT_HIP(hipStreamSynchronize(s));
+        }
+        V.bin_scratch.release();
+        return SPMV_OK;
+    }
+    default:
+        set_error("unknown kernel %d", kernel);
+        return SPMV_EINVAL;
+    }
+}
+
+spmv_status run_variant(const spmv_plan_s &P, const Variant &V, const void *x, void *y,
+                        hipStream_t s) {
+    const int elt = P.elt;
+    const int64_t m = P.m;
+    if (m == 0) return SPMV_OK;
+    switch (V.kernel) {
+    case SPMV_K_CSR_SCALAR:
+        return run_csr_scalar(elt, m, P.rp.as<int32_t>(), P.col.as<int32_t>(), P.val.p, x, y,
+                              V.prm.block, s);
+    case SPMV_K_CSR_VECTOR:
+        return run_csr_vector(elt, V.prm.vector_lanes, m, nullptr, P.rp.as<int32_t>(),
+                              P.col.as<int32_t>(), P.val.p, x, y, V.prm.block, s);
+    case SPMV_K_CSR_ADAPTIVE: {
+        const int32_t *rows = V.bin_rows.as<int32_t>();
+        for (int b = 0; b < 7; ++b) {
+            int64_t cnt = (int64_t)V.bin_off[b + 1] - V.bin_off[b];
+            if (cnt)
+                SMAT_TRY(run_csr_vector(elt, V.bin_lanes[b], cnt, rows + V.bin_off[b],
+                                        P.rp.as<int32_t>(), P.col.as<int32_t>(), P.val.p, x, y,
+                                        V.prm.block, s));
+        }
+        int64_t cnt = (int64_t)V.bin_off[8] - V.bin_off[7];
+        if (cnt)
+            SMAT_TRY(run_csr_rowblock(elt, cnt, rows + V.bin_off[7], P.rp.as<int32_t>(),
+                                      P.col.as<int32_t>(), P.val.p, x, y, s));
+        if (V.nsplit_rows)
+            SMAT_TRY(run_csr_split(elt, V.nsplit_segs, V.split_segs.as<int64_t>(),
+                                   V.split_partials.as<double>(), V.nsplit_rows,
+                                   V.split_begin.as<int64_t>(), V.split_rows.as<int32_t>(),
+                                   P.col.as<int32_t>(), P.val.p, x, y, s));
+        return SPMV_OK;
+    }
+    case SPMV_K_ELL:
+        return run_ell(elt, m, P.m_pad, V.K, V.ecol.as<int32_t>(), V.eval.p, x, y, V.prm.block,
+                       V.prm.ell_unroll, s);
+    case SPMV_K_DIA:
+    case SPMV_K_DIA_DIRECT:
+        return run_dia(elt, V.kernel == SPMV_K_DIA, m, P.n, P.m_pad, V.D, V.dia_off.as<int32_t>(),
+                       nullptr, V.nwin, V.dia_win.as<DiaWindow>(), V.max_span, V.dia_data.p, x, y,
+                       std::min(V.prm.block, 256), V.prm.dia_rows_per_thread, s);
+    case SPMV_K_COO:
+        return run_coo(elt, m, P.nnz, V.row_idx.as<int32_t>(), P.col.as<int32_t>(), P.val.p, x, y,
+                       V.prm.coo_chunk, V.coo_head.as<double>(), V.coo_tail.as<double>(),
+                       V.coo_flags.as<uint32_t>(), s);
+    default:
+        set_error("plan holds no kernel");
+        return SPMV_EINVAL;
+    }
+}
+
+// Median time in ms of `reps` runs (after one warm-up run).
+spmv_status time_variant(const spmv_plan_s &P, const Variant &V, const void *x, void *y,
+                         int reps, hipStream_t s, double *ms) {
+    hipEvent_t a, b;
+    SMAT_HIP(hipEventCreate(&a));
+    SMAT_HIP(hipEventCreate(&b));
+    spmv_status st = run_variant(P, V, x, y, s);
+    std::vector<double> t;
+    for (int r = 0; r < reps && st == SPMV_OK; ++r) {
+        (void)hipEventRecord(a, s);
+        st = run_variant(P, V, x, y, s);
+        (void)hipEventRecord(b, s);
+        if (hipEventSynchronize(b) != hipSuccess) {
+            st = hip_fail(hipGetLastError(), "timing");
+            break;
+        }
+        float f = 0;
+        (void)hipEventElapsedTime(&f, a, b);
+        t.push_back(f);
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (st != SPMV_OK) return st;
+    std::sort(t.begin(), t.end());
+    *ms = t.empty() ? 0.0 : t[t.size() / 2];
+    return SPMV_OK;
+}
+
+bool needs_csr(int kernel) {
+    return kernel == SPMV_K_CSR_SCALAR || kernel == SPMV_K_CSR_VECTOR ||
+           kernel == SPMV_K_CSR_ADAPTIVE || kernel == SPMV_K_COO;
+}
+
+}  // namespace
+}  // namespace smat
+
+// ====================================================================== C-ABI
+
+extern "C" const char *spmv_status_string(spmv_status s) {
+    switch (s) {
+    case SPMV_OK: return "SPMV_OK";
+    case SPMV_EINVAL: return "SPMV_EINVAL";
+    case SPMV_ENOMEM: return "SPMV_ENOMEM";
+    case SPMV_EDEVICE: return "SPMV_EDEVICE";
+    case SPMV_EUNSUPPORTED: return "SPMV_EUNSUPPORTED";
+    }
+    return "unknown status";
+}
+
+extern "C" const char *spmv_last_error(void) { return g_err; }
+
+extern "C" const char *spmv_kernel_name(int32_t k) {
+    static const char *names[] = {"csr_scalar", "csr_vector", "csr_adaptive", "ell",
+                                  "dia",        "dia_direct", "coo"};
+    return (k >= 0 && k < SPMV_K_COUNT) ? names[k] : "invalid";
+}
+
+extern "C" spmv_status spmv_plan_opts_default(spmv_plan_opts *o) {
+    if (!o) return SPMV_EINVAL;
+    std::memset(o, 0, sizeof(*o));
+    o->selector = -1;  // resolved at plan time: MLP if a model is given
+    o->force_kernel = -1;
+    o->confidence_tau = 0.1f;
+    o->measure_topk = 3;
+    o->timing_reps = 5;
+    return SPMV_OK;
+}
+
+static spmv_status check_csr(const spmv_csr *A) {
+    if (!A) {
+        set_error("csr is NULL");
+        return SPMV_EINVAL;
+    }
+    if (A->m < 0 || A->n < 0 || A->nnz < 0) {
+        set_error("negative m, n or nnz");
+        return SPMV_EINVAL;
+    }
+    if (A->dtype != SPMV_F32 && A->dtype != SPMV_F64) {
+        set_error("dtype must be SPMV_F32 or SPMV_F64");
+        return SPMV_EINVAL;
+    }
+    if (A->m >= INT_MAX || A->n >= INT_MAX || A->nnz >= INT_MAX) {
+        set_error("m, n and nnz must stay below 2^31 (int32 index paths)");
+        return SPMV_EUNSUPPORTED;
+    }
+    if (A->nnz > 0 && (A->m == 0 || A->n == 0)) {
+        set_error("nnz > 0 with an empty dimension");
+        return SPMV_EINVAL;
+    }
+    if (!A->row_ptr_dev || (A->nnz > 0 && (!A->col_dev || !A->val_dev))) {
+        set_error("NULL device array");
+        return SPMV_EINVAL;
+    }
+    return SPMV_OK;
+}
+
+extern "C" spmv_status spmv_features_compute(const spmv_csr *A, spmv_features *out, void *stream) {
+    SMAT_TRY(check_csr(A));
+    if (!out) {
+        set_error("out is NULL");
+        return SPMV_EINVAL;
+    }
+    FeatureWork W;
+    return validate_and_extract(*A, (hipStream_t)stream, *out, W, false, nullptr, nullptr);
+}
+
+static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opts_in,
+                                    hipStream_t s, spmv_plan_t *out) {
+    auto t_start = std::chrono::steady_clock::now();
+    SMAT_TRY(check_csr(A));
+    spmv_plan_opts opts;
+    if (opts_in)
+        opts = *opts_in;
+    else
+        spmv_plan_opts_default(&opts);
+    if (opts.timing_reps <= 0) opts.timing_reps = 5;
+    if (opts.measure_topk <= 0) opts.measure_topk = 3;
+    int mode = opts.selector;
+    if (mode < 0) mode = opts.model ? SPMV_SELECT_MLP : SPMV_SELECT_RULES;
+    if (mode > SPMV_SELECT_FORCED) {
+        set_error("unknown selector mode %d", mode);
+        return SPMV_EINVAL;
+    }
+    if (mode == SPMV_SELECT_MLP && !opts.model) {
+        set_error("SPMV_SELECT_MLP needs opts.model");
+        return SPMV_EINVAL;
+    }
+    if (mode == SPMV_SELECT_FORCED && (opts.force_kernel < 0 || opts.force_kernel >= SPMV_K_COUNT)) {
+        set_error("force_kernel %d out of range", opts.force_kernel);
+        return SPMV_EINVAL;
+    }
+    auto P = std::make_unique<spmv_plan_s>();
+    P->m = A->m;
+    P->n = A->n;
+    P->nnz = A->nnz;
+    P->dtype = A->dtype;
+    P->elt = elt_of(A->dtype);
+    P->m_pad = round_up(A->m, kRowPad);
+    spmv_plan_info &I = P->info;
+    I.m = A->m;
+    I.n = A->n;
+    I.nnz = A->nnz;
+    I.dtype = A->dtype;
+    I.confidence = -1.0f;
+    I.m_pad = P->m_pad;
+
+    FeatureWork W;
+    spmv_features F;
+    SMAT_TRY(validate_and_extract(*A, s, F, W, true, &I.t_validate_ms, &I.t_features_ms));
+    I.features = F;
+    auto t_sel0 = std::chrono::steady_clock::now();
+
+    // plan-owned CSR copy (every conversion starts from it)
+    SMAT_TRY(P->rp.alloc(sizeof(int32_t) * (size_t)(A->m + 1)));
+    SMAT_TRY(P->col.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(1, A->nnz)));
+    SMAT_TRY(P->val.alloc((size_t)P->elt * (size_t)std::max<int64_t>(1, A->nnz)));
+    SMAT_HIP(hipMemcpyAsync(P->rp.p, A->row_ptr_dev, sizeof(int32_t) * (A->m + 1),
+                            hipMemcpyDeviceToDevice, s));
+    if (A->nnz) {
+        SMAT_HIP(hipMemcpyAsync(P->col.p, A->col_dev, sizeof(int32_t) * A->nnz,
+                                hipMemcpyDeviceToDevice, s));
+        SMAT_HIP(hipMemcpyAsync(P->val.p, A->val_dev, (size_t)P->elt * A->nnz,
+                                hipMemcpyDeviceToDevice, s));
+    }
+    P->has_csr = true;
+
+    uint64_t cap = opts.mem_cap_bytes;
+    if (cap == 0) {
+        size_t fr = 0, tot = 0;
+        SMAT_HIP(hipMemGetInfo(&fr, &tot));
+        cap = fr / 4;
+    }
+    spmv_params prm_base = default_params(0, F);
+    if (opts.use_params) {
+        merge_params(prm_base, opts.params);
+        SMAT_TRY(check_params(prm_base));
+    }
+    uint32_t feas = feasible_mask(F, A->dtype, P->m_pad, cap, prm_base) & ~opts.disable_mask;
+    I.feasible_mask = feas;
+
+    // ---- selection
+    std::vector<int> cands;
+    int chosen = -1;
+    I.selector_used = mode;
+    if (mode == SPMV_SELECT_FORCED) {
+        uint32_t all = feasible_mask(F, A->dtype, P->m_pad, ~0ull, prm_base, false);
+        bool structural_ok = (all >> opts.force_kernel) & 1u;
+        // DIA and ELL need their zero-fill feasibility; the others always run
+        if (!structural_ok && (opts.force_kernel == SPMV_K_DIA || opts.force_kernel == SPMV_K_DIA_DIRECT ||
+                               opts.force_kernel == SPMV_K_ELL)) {
+            set_error("forced kernel %s is infeasible for this matrix (zero fill)",
+                      spmv_kernel_name(opts.force_kernel));
+            return SPMV_EINVAL;
+        }
+        if ((opts.force_kernel == SPMV_K_DIA || opts.force_kernel == SPMV_K_DIA_DIRECT) && !W.diag_hist.p) {
+            set_error("forced DIA without a diagonal census");
+            return SPMV_EINVAL;
+        }
+        chosen = opts.force_kernel;
+    } else if (mode == SPMV_SELECT_RULES) {
+        chosen = rules_choose(F, feas);
+    } else if (mode == SPMV_SELECT_EXHAUSTIVE) {
+        for (int k = 0; k < SPMV_K_COUNT; ++k)
+            if ((feas >> k) & 1u) cands.push_back(k);
+    } else {  // MLP
+        spmv_selector_s *sel = opts.model;
+        float raw[12];
+        raw_features(F, A->dtype, raw);
+        Dev draw, dsc;
+        SMAT_TRY(draw.alloc(sizeof(raw)));
+        SMAT_TRY(dsc.alloc(sizeof(float) * SPMV_K_COUNT));
+        SMAT_HIP(hipMemcpyAsync(draw.p, raw, sizeof(raw), hipMemcpyHostToDevice, s));
+        SMAT_TRY(run_mlp_infer(sel->params.as<float>(), sel->n_out, sel->mean.as<float>(),
+                               sel->stdv.as<float>(), draw.as<float>(), 1, dsc.as<float>(), s));
+        float sc[SPMV_K_COUNT];
+        SMAT_HIP(hipMemcpyAsync(sc, dsc.p, sizeof(sc), hipMemcpyDeviceToHost, s));
+        SMAT_HIP(hipStreamSynchronize(s));
+        std::vector<std::pair<float, int>> order;
+        for (int k = 0; k < SPMV_K_COUNT; ++k) {
+            I.mlp_scores[k] = sc[k];
+            if ((feas >> k) & 1u) order.push_back({sc[k], k});
+        }
+        std::sort(order.begin(), order.end());
+        if (order.empty()) {
+            chosen = SPMV_K_CSR_ADAPTIVE;
+        } else {
+            float margin = order.size() > 1 ? order[1].first - order[0].first : 1e30f;
+            I.confidence = margin;
+            if (margin >= opts.confidence_tau || order.size() == 1) {
+                chosen = order[0].second;
+            } else {
+                for (size_t q = 0; q < order.size() && (int)q < opts.measure_topk; ++q)
+                    cands.push_back(order[q].second);
+            }
+        }
+    }
+    if (chosen < 0 && cands.empty()) chosen = SPMV_K_CSR_ADAPTIVE;
+
+    // ---- execute and measure the candidates, keep the fastest
+    if (chosen < 0) {
+        Dev xs, ys;
+        SMAT_TRY(xs.alloc((size_t)P->elt * std::max<int64_t>(1, P->n)));
+        SMAT_TRY(ys.alloc((size_t)P->elt * std::max<int64_t>(1, P->m)));
+        if (P->n)
+            k_fill_one<<<(unsigned)((P->n + 255) / 256), 256, 0, s>>>(P->n, P->elt, xs.p);
+        SMAT_LAUNCHED("fill_one");
+        double best = 1e300;
+        for (int k : cands) {
+            auto V = std::make_unique<Variant>();
+            spmv_status st = build_variant(*P, F, W, k, prm_base, s, *V);
+            if (st == SPMV_ENOMEM) continue;  // candidate too large right now
+            if (st != SPMV_OK) return st;
+            double ms = 0;
+            SMAT_TRY(time_variant(*P, *V, xs.p, ys.p, opts.timing_reps, s, &ms));
+            I.measured_kernel[I.n_measured] = k;
+            I.measured_ms[I.n_measured] = ms;
+            ++I.n_measured;
+            if (ms < best) {
+                best = ms;
+                chosen = k;
+                P->var = std::move(V);
+            }
+        }
+        if (chosen < 0) {
+            set_error("no candidate kernel could be built");
+            return SPMV_ENOMEM;
+        }
+    }
+    auto t_conv0 = std::chrono::steady_clock::now();
+    if (!P->var) {
+        P->var = std::make_unique<Variant>();
+        spmv_status st = build_variant(*P, F, W, chosen, prm_base, s, *P->var);
+        if (st == SPMV_ENOMEM && mode != SPMV_SELECT_FORCED) {
+            // fall back to CSR once (needs no extra storage)
+            P->var = std::make_unique<Variant>();
+            chosen = SPMV_K_CSR_VECTOR;
+            SMAT_TRY(build_variant(*P, F, W, chosen, prm_base, s, *P->var));
+        } else if (st != SPMV_OK) {
+            return st;
+        }
+    }
+    SMAT_HIP(hipStreamSynchronize(s));
+    W.diag_hist.release();
+    if (!needs_csr(chosen)) {
+        P->rp.release();
+        P->col.release();
+        P->val.release();
+        P->has_csr = false;
+    }
+    auto t_end = std::chrono::steady_clock::now();
+    I.kernel = chosen;
+    I.format = (chosen <= SPMV_K_CSR_ADAPTIVE) ? SPMV_FMT_CSR
+               : chosen == SPMV_K_ELL          ? SPMV_FMT_ELL
+               : chosen == SPMV_K_COO          ? SPMV_FMT_COO
+                                               : SPMV_FMT_DIA;
+    I.params = P->var->prm;
+    I.ell_width = P->var->K;
+    I.dia_ndiags = P->var->D;
+    I.dia_windows = P->var->nwin;
+    I.device_bytes = P->rp.bytes + P->col.bytes + P->val.bytes + P->var->bytes();
+    I.t_select_ms = std::chrono::duration<double, std::milli>(t_conv0 - t_sel0).count();
+    I.t_convert_ms = std::chrono::duration<double, std::milli>(t_end - t_conv0).count();
+    I.t_plan_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();
+    *out = P.release();
+    return SPMV_OK;
+}
+
+extern "C" spmv_status spmv_plan_create(const spmv_csr *A, const spmv_plan_opts *opts,
+                                        void *stream, spmv_plan_t *out) {
+    if (!out) {
+        set_error("out is NULL");
+        return SPMV_EINVAL;
+    }
+    *out = nullptr;
+    try {
+        return plan_create_impl(A, opts, (hipStream_t)stream, out);
+    } catch (const std::bad_alloc &) {
+        set_error("host allocation failed");
+        return SPMV_ENOMEM;
+    }
+}
+
+static bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    uintptr_t x = (uintptr_t)a, y = (uintptr_t)b;
+    return na && nb && x < y + nb && y < x + na;
+}
+
+extern "C" spmv_status spmv_run(spmv_plan_t P, const void *x, void *y, void *stream) {
+    if (!P) {
+        set_error("plan is NULL");
+        return SPMV_EINVAL;
+    }
+    if (P->m == 0) return SPMV_OK;
+    if (!y || (P->n > 0 && !x)) {
+        set_error("x or y is NULL");
+        return SPMV_EINVAL;
+    }
+    if (overlap(x, (size_t)P->elt * P->n, y, (size_t)P->elt * P->m)) {
+        set_error("x and y overlap");
+        return SPMV_EINVAL;
+    }
+    return run_variant(*P, *P->var, x, y, (hipStream_t)stream);
+}
+
+extern "C" spmv_status spmv_plan_info_get(spmv_plan_t P, spmv_plan_info *out) {
+    if (!P || !out) {
+        set_error("plan or out is NULL");
+        return SPMV_EINVAL;
+    }
+    *out = P->info;
+    return SPMV_OK;
+}
+
+extern "C" spmv_status spmv_plan_destroy(spmv_plan_t P) {
+    delete P;
+    return SPMV_OK;
+}
+
+extern "C" spmv_status spmv_convert_roundtrip(spmv_plan_t P, int32_t *rp, int32_t *col, void *val,
+                                              void *stream) {
+    if (!P || !rp || (P->nnz > 0 && (!col || !val))) {
+        set_error("NULL argument");
+        return SPMV_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const Variant &V = *P->var;
+    const int64_t m = P->m, nnz = P->nnz;
+    const int elt = P->elt;
+    Dev counts, scan;
+    SMAT_TRY(counts.alloc(sizeof(int32_t) * std::max<int64_t>(1, m)));
+    SMAT_TRY(scan.alloc(sizeof(unsigned) * (size_t)(m / 4096 + 2)));
+    switch (V.kernel) {
+    case SPMV_K_CSR_SCALAR:
+    case SPMV_K_CSR_VECTOR:
+    case SPMV_K_CSR_ADAPTIVE:
+        SMAT_HIP(hipMemcpyAsync(rp, P->rp.p, sizeof(int32_t) * (m + 1), hipMemcpyDeviceToDevice, s));
+        if (nnz) {
+            SMAT_HIP(hipMemcpyAsync(col, P->col.p, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, s));
+            SMAT_HIP(hipMemcpyAsync(val, P->val.p, (size_t)elt * nnz, hipMemcpyDeviceToDevice, s));
+        }
+        break;
+    case SPMV_K_COO:
+        SMAT_TRY(launch_coo_to_csr(m, nnz, V.row_idx.as<int32_t>(), rp, s));
+        if (nnz) {
+            SMAT_HIP(hipMemcpyAsync(col, P->col.p, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, s));
+            SMAT_HIP(hipMemcpyAsync(val, P->val.p, (size_t)elt * nnz, hipMemcpyDeviceToDevice, s));
+        }
+        break;
+    case SPMV_K_ELL:
+        SMAT_TRY(launch_ell_to_csr(m, P->m_pad, V.K, V.ecol.as<int32_t>(), V.eval.p, elt, rp, col,
+                                   val, counts.as<int32_t>(), scan.as<unsigned>(), s));
+        break;
+    case SPMV_K_DIA:
+    case SPMV_K_DIA_DIRECT:
+        SMAT_TRY(launch_dia_to_csr(m, P->n, P->m_pad, V.D, V.dia_off.as<int32_t>(), V.dia_data.p,
+                                   V.dia_present.as<uint32_t>(), elt, rp, col, val,
+                                   counts.as<int32_t>(), scan.as<unsigned>(), s));
+        break;
+    default:
+        set_error("plan holds no kernel");
+        return SPMV_EINVAL;
+    }
+    SMAT_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
+}
+
+extern "C" spmv_status spmv_plan_export(spmv_plan_t P, int32_t which, void *dst, size_t bytes,
+                                        size_t *bytes_out, void *stream) {
+    if (!P) {
+        set_error("plan is NULL");
+        return SPMV_EINVAL;
+    }
+    const Variant &V = *P->var;
+    const void *src = nullptr;
+    size_t n = 0;
+    switch (which) {
+    case 0:
+        if (V.kernel == SPMV_K_COO) { src = V.row_idx.p; n = sizeof(int32_t) * P->nnz; }
+        break;
+    case 1:
+        if (V.kernel == SPMV_K_ELL) { src = V.ecol.p; n = sizeof(int32_t) * (size_t)V.K * P->m_pad; }
+        break;
+    case 2:
+        if (V.kernel == SPMV_K_ELL) { src = V.eval.p; n = (size_t)P->elt * V.K * P->m_pad; }
+        break;
+    case 3:
+        if (V.kernel == SPMV_K_DIA || V.kernel == SPMV_K_DIA_DIRECT) { src = V.dia_off.p; n = sizeof(int32_t) * V.D; }
+        break;
+    case 4:
+        if (V.kernel == SPMV_K_DIA || V.kernel == SPMV_K_DIA_DIRECT) { src = V.dia_data.p; n = (size_t)P->elt * V.D * P->m_pad; }
+        break;
+    case 5:
+        if (V.kernel == SPMV_K_DIA || V.kernel == SPMV_K_DIA_DIRECT) { src = V.dia_present.p; n = sizeof(uint32_t) * (((size_t)V.D * P->m_pad + 31) / 32); }
+        break;
+    case 6:
+        if (V.kernel == SPMV_K_CSR_ADAPTIVE) { src = V.bin_rows.p; n = sizeof(int32_t) * P->m; }
+        break;
+    default:
+        break;
+    }
+    if (!src && n == 0 && which >= 0 && which <= 6 && bytes_out) {
+        // an empty array of a present format
+    }
+    if (!src) {
+        set_error("plan has no array %d", which);
+        return SPMV_EINVAL;
+    }
+    if (bytes_out) *bytes_out = n;
+    if (!dst) return SPMV_OK;  // size query
+    if (bytes < n) {
+        set_error("destination too small (%zu < %zu)", bytes, n);
+        return SPMV_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (n) SMAT_HIP(hipMemcpyAsync(dst, src, n, hipMemcpyDeviceToDevice, s));
+    SMAT_HIP(hipStreamSynchronize(s));
+    return SPMV_OK;
+}
+
+extern "C" spmv_status spmv_selector_create(const float *params, int64_t n_params,
+                                            const float *mean, const float *stdv,
+                                            spmv_selector_t *out) {
+    if (!out || !params || !mean || !stdv) {
+        set_error("NULL argument");
+        return SPMV_EINVAL;
+    }
+    *out = nullptr;
+    if (n_params != spmv_mlp_param_count(SPMV_K_COUNT)) {
+        set_error("selector expects %lld parameters, got %lld",
+                  (long long)spmv_mlp_param_count(SPMV_K_COUNT), (long long)n_params);
+        return SPMV_EINVAL;
+    }
+    for (int i = 0; i < 12; ++i)
+        if (!(stdv[i] > 0.0f)) {
+            set_error("std[%d] must be > 0", i);
+            return SPMV_EINVAL;
+        }
+    auto S = std::make_unique<spmv_selector_s>();
+    S->n_out = SPMV_K_COUNT;
+    SMAT_TRY(S->params.alloc(sizeof(float) * n_params));
+    SMAT_TRY(S->mean.alloc(sizeof(float) * 12));
+    SMAT_TRY(S->stdv.alloc(sizeof(float) * 12));
+    SMAT_HIP(hipMemcpy(S->params.p, params, sizeof(float) * n_params, hipMemcpyHostToDevice));
+    SMAT_HIP(hipMemcpy(S->mean.p, mean, sizeof(float) * 12, hipMemcpyHostToDevice));
+    SMAT_HIP(hipMemcpy(S->stdv.p, stdv, sizeof(float) * 12, hipMemcpyHostToDevice));
+    *out = S.release();
+    return SPMV_OK;
+}
+
+extern "C" spmv_status spmv_selector_destroy(spmv_selector_t S) {
+    delete S;
+    return SPMV_OK;
+}
+
+extern "C" spmv_status spmv_selector_score(spmv_selector_t S, const float *raw, int64_t rows,
+                                           float *scores, void *stream) {
+    if (!S || (rows > 0 && (!raw || !scores)) || rows < 0) {
+        set_error("bad argument");
+        return SPMV_EINVAL;
+    }
+    return run_mlp_infer(S->params.as<float>(), S->n_out, S->mean.as<float>(), S->stdv.as<float>(),
+                         raw, rows, scores, (hipStream_t)stream);
+}
+
+extern "C" spmv_status spmv_stream_copy(void *dst, const void *src, size_t bytes, void *stream) {
+    if (!dst || !src || bytes % 16 || ((uintptr_t)dst | (uintptr_t)src) % 16) {
+        set_error("stream_copy needs 16-byte aligned buffers and a multiple of 16 bytes");
+        return SPMV_EINVAL;
+    }
+    return run_stream_copy(dst, src, bytes, (hipStream_t)stream);
+}
+

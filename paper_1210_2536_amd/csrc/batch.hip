@@ -1,0 +1,318 @@
+// K11 multilevel batch: y_l = A_l x_l for every level of an AMG-style
+// hierarchy (the paper's motivation, Section 1: AMG spends most of its time
+// in SpMV over a series of diverse level matrices).  Coarse levels are far
+// too small to fill the GPU on their own, so
+//   mode 0: one persistent launch; workgroups take (level, tile) items from a
+//           global ticket, largest levels first;
+//   mode 1: the per-level launches captured once into a HIP graph and
+//           replayed.
+// K12 stream copy (achievable HBM bandwidth probe) lives here as well.
+#include "plan.hpp"
+#include "spmv_device.hpp"
+
+#include <algorithm>
+#include <memory>
+
+namespace smat {
+namespace {
+
+constexpr int kMaxLevels = 16;
+constexpr int kPBlock = 256;   // persistent workgroup size
+constexpr int kPDiaRpt = 4;    // rows per thread of a DIA tile
+
+enum LevelKind { LK_SCALAR = 0, LK_VECTOR = 1, LK_ELL = 3, LK_DIA = 4, LK_DIA_DIRECT = 5 };
+
+struct LevelDesc {
+    int kind, lanes, K, D, nwin, pad;
+    int64_t m, n, m_pad, tile_rows, tile_begin;
+    const int32_t *rp, *col, *ecol, *offs;
+    const void *val, *eval, *data;
+    const DiaWindow *win;
+};
+
+struct Ptrs {
+    const void *x[kMaxLevels];
+    void *y[kMaxLevels];
+};
+
+template <typename T, int L>
+__device__ __forceinline__ void vector_tile(const LevelDesc &d, int64_t tile, const T *x, T *y) {
+    int64_t row = tile * (kPBlock / L) + threadIdx.x / L;
+    int lane = threadIdx.x & (L - 1);
+    if (row < d.m) {
+        double acc = csr_row_lanes<T, L>(row, lane, d.rp, d.col, (const T *)d.val, x);
+        if (lane == 0) y[row] = (T)acc;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kPBlock) void k_batch_persistent(const LevelDesc *__restrict__ L,
+                                                              int nlev, int64_t total, Ptrs P,
+                                                              unsigned long long *ticket) {
+    extern __shared__ unsigned char smem_raw[];
+    T *xs = reinterpret_cast<T *>(smem_raw);
+    __shared__ long long item;
+    for (;;) {
+        if (threadIdx.x == 0) item = (long long)atomicAdd(&ticket[0], 1ull);
+        __syncthreads();
+        const int64_t t = item;
+        __syncthreads();
+        if (t >= total) break;
+        int l = 0;
+        while (l + 1 < nlev && t >= L[l + 1].tile_begin) ++l;
+        const LevelDesc &d = L[l];
+        const int64_t tile = t - d.tile_begin;
+        const T *x = (const T *)P.x[l];
+        T *y = (T *)P.y[l];
+        switch (d.kind) {
+        case LK_SCALAR: {
+            int64_t i = tile * kPBlock + threadIdx.x;
+            if (i < d.m) y[i] = (T)csr_row_seq<T>(i, d.rp, d.col, (const T *)d.val, x);
+            break;
+        }
+        case LK_VECTOR:
+            switch (d.lanes) {
+            case 1: vector_tile<T, 1>(d, tile, x, y); break;
+            case 2: vector_tile<T, 2>(d, tile, x, y); break;
+            case 4: vector_tile<T, 4>(d, tile, x, y); break;
+            case 8: vector_tile<T, 8>(d, tile, x, y); break;
+            case 16: vector_tile<T, 16>(d, tile, x, y); break;
+            case 32: vector_tile<T, 32>(d, tile, x, y); break;
+            default: vector_tile<T, 64>(d, tile, x, y); break;
+            }
+            break;
+        case LK_ELL: {
+            int64_t i = tile * kPBlock + threadIdx.x;
+            if (i < d.m) y[i] = (T)ell_row<T, 4>(i, d.m_pad, d.K, d.ecol, (const T *)d.eval, x);
+            break;
+        }
+        case LK_DIA:
+            dia_tile_lds<T, kPDiaRpt>(tile * d.tile_rows, d.m, d.n, d.m_pad, d.offs, d.nwin, d.win,
+                                      (const T *)d.data, x, y, xs);
+            break;
+        default:
+            dia_tile_direct<T, kPDiaRpt>(tile * d.tile_rows, d.m, d.n, d.m_pad, d.D, d.offs,
+                                         (const T *)d.data, x, y);
+            break;
+        }
+        __syncthreads();  // LDS reuse by the next item
+    }
+    // the last workgroup out re-arms the ticket for the next launch
+    if (threadIdx.x == 0) {
+        unsigned long long prev = atomicAdd(&ticket[1], 1ull);
+        if (prev == gridDim.x - 1) {
+            atomicExch(&ticket[0], 0ull);
+            atomicExch(&ticket[1], 0ull);
+        }
+    }
+}
+
+template <typename T>
+__global__ void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+}  // namespace
+
+spmv_status run_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
+    int64_t n = (int64_t)(bytes / 16);
+    if (n == 0) return SPMV_OK;
+    int64_t g = std::min<int64_t>((n + 255) / 256, 256 * 64);
+    k_stream_copy<int><<<(unsigned)g, 256, 0, s>>>((const uint4 *)src, (uint4 *)dst, n);
+    SMAT_LAUNCHED("stream_copy");
+    return SPMV_OK;
+}
+
+}  // namespace smat
+
+using namespace smat;
+
+struct spmv_batch_s {
+    int mode = 0;
+    int nlev = 0;
+    int elt = 8;
+    std::vector<spmv_plan_t> plans;
+    std::vector<int> persistent_levels;  // indices handled inside the persistent kernel
+    std::vector<int> extra_levels;       // launched separately
+    smat::Dev desc, ticket;
+    int64_t total_tiles = 0;
+    size_t lds_bytes = 0;
+    int grid = 0;
+    // graph mode
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+    hipStream_t cap = nullptr;
+    std::vector<const void *> gx;
+    std::vector<void *> gy;
+    ~spmv_batch_s() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (cap) (void)hipStreamDestroy(cap);
+    }
+};
+
+extern "C" spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplans, int32_t mode,
+                                         spmv_batch_t *out) {
+    if (!out || !plans || nplans <= 0 || nplans > kMaxLevels || (mode != 0 && mode != 1)) {
+        set_error("spmv_batch_create: need 1..%d plans and mode 0 or 1", kMaxLevels);
+        return SPMV_EINVAL;
+    }
+    *out = nullptr;
+    auto B = std::make_unique<spmv_batch_s>();
+    B->mode = mode;
+    B->nlev = nplans;
+    B->elt = plans[0] ? plans[0]->elt : 8;
+    for (int l = 0; l < nplans; ++l) {
+        if (!plans[l]) {
+            set_error("plan %d is NULL", l);
+            return SPMV_EINVAL;
+        }
+        if (plans[l]->elt != B->elt) {
+            set_error("all plans of a batch must share one dtype");
+            return SPMV_EINVAL;
+        }
+        B->plans.push_back(plans[l]);
+    }
+    if (mode == 1) {
+        SMAT_HIP(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+        *out = B.release();
+        return SPMV_OK;
+    }
+    std::vector<LevelDesc> descs;
+    int64_t tiles = 0;
+    for (int l = 0; l < nplans; ++l) {
+        const spmv_plan_s &P = *plans[l];
+        const Variant &V = *P.var;
+        LevelDesc d{};
+        d.m = P.m;
+        d.n = P.n;
+        d.m_pad = P.m_pad;
+        d.rp = P.rp.as<int32_t>();
+        d.col = P.col.as<int32_t>();
+        d.val = P.val.p;
+        switch (V.kernel) {
+        case SPMV_K_CSR_SCALAR: d.kind = LK_SCALAR; d.tile_rows = kPBlock; break;
+        case SPMV_K_CSR_VECTOR:
+            d.kind = LK_VECTOR;
+            d.lanes = V.prm.vector_lanes;
+            d.tile_rows = kPBlock / d.lanes;
+            break;
+        case SPMV_K_ELL:
+            d.kind = LK_ELL;
+            d.tile_rows = kPBlock;
+            d.K = V.K;
+            d.ecol = V.ecol.as<int32_t>();
+            d.eval = V.eval.p;
+            break;
+        case SPMV_K_DIA:
+        case SPMV_K_DIA_DIRECT:
+            d.kind = V.kernel == SPMV_K_DIA ? LK_DIA : LK_DIA_DIRECT;
+            d.tile_rows = (int64_t)kPBlock * kPDiaRpt;
+            d.D = V.D;
+            d.nwin = V.nwin;
+            d.offs = V.dia_off.as<int32_t>();
+            d.win = V.dia_win.as<DiaWindow>();
+            d.data = V.dia_data.p;
+            if (d.kind == LK_DIA)
+                B->lds_bytes = std::max(B->lds_bytes,
+                                        (size_t)(d.tile_rows + V.max_span) * (size_t)P.elt);
+            if (V.D == 0) d.kind = -1;
+            break;
+        default:
+            d.kind = -1;
+        }
+        if (d.kind < 0 || P.m == 0) {
+            B->extra_levels.push_back(l);
+            continue;
+        }
+        d.tile_begin = tiles;
+        tiles += (P.m + d.tile_rows - 1) / d.tile_rows;
+        B->persistent_levels.push_back(l);
+        descs.push_back(d);
+    }
+    B->total_tiles = tiles;
+    if (B->lds_bytes > 64 * 1024) {
+        set_error("DIA window too wide for the persistent kernel's LDS");
+        return SPMV_EUNSUPPORTED;
+    }
+    spmv_status st = B->desc.alloc(sizeof(LevelDesc) * std::max<size_t>(1, descs.size()));
+    if (st != SPMV_OK) return st;
+    st = B->ticket.alloc(2 * sizeof(unsigned long long));
+    if (st != SPMV_OK) return st;
+    if (!descs.empty())
+        SMAT_HIP(hipMemcpy(B->desc.p, descs.data(), sizeof(LevelDesc) * descs.size(),
+                           hipMemcpyHostToDevice));
+    SMAT_HIP(hipMemset(B->ticket.p, 0, B->ticket.bytes));
+    int dev = 0, cus = 0;
+    SMAT_HIP(hipGetDevice(&dev));
+    SMAT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    B->grid = (int)std::min<int64_t>(std::max<int64_t>(1, tiles), (int64_t)cus * 8);
+    *out = B.release();
+    return SPMV_OK;
+}
+
+extern "C" spmv_status spmv_batch_run(spmv_batch_t B, const void *const *xs, void *const *ys,
+                                      void *stream) {
+    if (!B || !xs || !ys) {
+        set_error("spmv_batch_run: NULL argument");
+        return SPMV_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (B->mode == 1) {
+        bool same = B->exec && B->gx.size() == (size_t)B->nlev;
+        for (int l = 0; same && l < B->nlev; ++l) same = B->gx[l] == xs[l] && B->gy[l] == ys[l];
+        if (!same) {
+            if (B->exec) (void)hipGraphExecDestroy(B->exec);
+            if (B->graph) (void)hipGraphDestroy(B->graph);
+            B->exec = nullptr;
+            B->graph = nullptr;
+            SMAT_HIP(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+            spmv_status st = SPMV_OK;
+            for (int l = 0; l < B->nlev && st == SPMV_OK; ++l)
+                st = spmv_run(B->plans[l], xs[l], ys[l], B->cap);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(B->cap, &g);
+            if (st != SPMV_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return st;
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            B->graph = g;
+            SMAT_HIP(hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0));
+            B->gx.assign(xs, xs + B->nlev);
+            B->gy.assign(ys, ys + B->nlev);
+        }
+        SMAT_HIP(hipGraphLaunch(B->exec, s));
+        return SPMV_OK;
+    }
+    Ptrs P{};
+    int k = 0;
+    for (int l : B->persistent_levels) {
+        P.x[k] = xs[l];
+        P.y[k] = ys[l];
+        ++k;
+    }
+    if (B->total_tiles > 0) {
+        if (B->elt == 8)
+            k_batch_persistent<double><<<B->grid, kPBlock, B->lds_bytes, s>>>(
+                B->desc.as<LevelDesc>(), (int)B->persistent_levels.size(), B->total_tiles, P,
+                B->ticket.as<unsigned long long>());
+        else
+            k_batch_persistent<float><<<B->grid, kPBlock, B->lds_bytes, s>>>(
+                B->desc.as<LevelDesc>(), (int)B->persistent_levels.size(), B->total_tiles, P,
+                B->ticket.as<unsigned long long>());
+        SMAT_LAUNCHED("batch_persistent");
+    }
+    for (int l : B->extra_levels) {
+        spmv_status st = spmv_run(B->plans[l], xs[l], ys[l], s);
+        if (st != SPMV_OK) return st;
+    }
+    return SPMV_OK;
+}
+
+extern "C" spmv_status spmv_batch_destroy(spmv_batch_t B) {
+    delete B;
+    return SPMV_OK;
+}

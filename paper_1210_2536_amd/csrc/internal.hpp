@@ -1,0 +1,139 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/spmv.h"
+
+namespace smat {
+
+constexpr int kWave = 64;           // gfx9 wavefront width
+constexpr int kRowPad = 64;         // ELL / DIA slot stride is m rounded up to this
+constexpr int kFp64MaxDepth = 4096; // longest sequential float64 summation chain
+constexpr int kAdaptiveBins = 9;    // widths 1..64 (7 bins) + workgroup + split
+
+void set_error(const char *fmt, ...);
+spmv_status hip_fail(hipError_t e, const char *what);
+
+#define SMAT_HIP(expr)                                                   \
+    do {                                                                 \
+        hipError_t _e = (expr);                                          \
+        if (_e != hipSuccess) return ::smat::hip_fail(_e, #expr);        \
+    } while (0)
+
+#define SMAT_LAUNCHED(what)                                              \
+    do {                                                                 \
+        hipError_t _e = hipGetLastError();                               \
+        if (_e != hipSuccess) return ::smat::hip_fail(_e, what);         \
+    } while (0)
+
+// ----------------------------------------------------------------- K0 / K1
+// Validation flags.
+enum : uint32_t {
+    kBadRowPtr0 = 1u, kBadRowPtrEnd = 2u, kBadRowPtrOrder = 4u,
+    kBadColRange = 8u, kBadColOrder = 16u,
+};
+
+struct RowStats {       // device-side reduction target for the row pass
+    unsigned long long sum_rd, sum_rd2;
+    int max_rd, min_rd;
+};
+
+struct EntryStats {     // device-side reduction target for the entry pass
+    unsigned long long blocks4;
+    int bandwidth;
+    int pad;
+};
+
+struct DiagStats {
+    unsigned long long ndiags, ntrue;
+};
+
+spmv_status launch_validate_rows(int64_t m, int64_t nnz, const int32_t *rp, uint32_t *flags,
+                                 hipStream_t s);
+spmv_status launch_validate_entries(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
+                                    const int32_t *col, uint32_t *flags, hipStream_t s);
+spmv_status launch_row_stats(int64_t m, const int32_t *rp, RowStats *out, hipStream_t s);
+spmv_status launch_row_hist(int64_t m, const int32_t *rp, int max_rd, unsigned int *hist,
+                            hipStream_t s);
+spmv_status launch_powerlaw_fit(const unsigned int *hist, int max_rd, int64_t m, double *sums,
+                                hipStream_t s);
+spmv_status launch_entry_stats(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
+                               const int32_t *col, EntryStats *out, unsigned int *diag_hist,
+                               hipStream_t s);
+spmv_status launch_diag_stats(int64_t m, int64_t n, const unsigned int *diag_hist, DiagStats *out,
+                              hipStream_t s);
+spmv_status launch_diag_compact(int64_t m, int64_t n, unsigned int *diag_hist, int32_t *offsets,
+                                unsigned int *block_scratch, hipStream_t s);
+
+// ----------------------------------------------------------------- K2 / K5
+spmv_status launch_csr_to_coo(int64_t m, int64_t nnz, const int32_t *rp, int32_t *row_idx,
+                              hipStream_t s);
+spmv_status launch_csr_to_ell(int64_t m, int64_t m_pad, int K, const int32_t *rp,
+                              const int32_t *col, const void *val, int elt, int32_t *ecol,
+                              void *eval, hipStream_t s);
+spmv_status launch_csr_to_dia(int64_t m, int64_t n, int64_t m_pad, int64_t nnz, const int32_t *rp,
+                              const int32_t *col, const void *val, int elt,
+                              const unsigned int *slot_map, void *data, uint32_t *present,
+                              hipStream_t s);
+spmv_status launch_coo_to_csr(int64_t m, int64_t nnz, const int32_t *row_idx, int32_t *rp,
+                              hipStream_t s);
+spmv_status launch_ell_to_csr(int64_t m, int64_t m_pad, int K, const int32_t *ecol,
+                              const void *eval, int elt, int32_t *rp, int32_t *col, void *val,
+                              int32_t *counts, unsigned int *scratch, hipStream_t s);
+spmv_status launch_dia_to_csr(int64_t m, int64_t n, int64_t m_pad, int D, const int32_t *offs,
+                              const void *data, const uint32_t *present, int elt, int32_t *rp,
+                              int32_t *col, void *val, int32_t *counts, unsigned int *scratch,
+                              hipStream_t s);
+// scratch: at least ceil(m / 4096) unsigned ints
+spmv_status launch_exclusive_scan_rows(int64_t m, const int32_t *counts, int32_t *rp,
+                                       unsigned int *scratch, hipStream_t s);
+
+// Row binning for CSR_ADAPTIVE: bin_of(len) in [0, kAdaptiveBins).
+struct BinSpec {
+    int upper[kAdaptiveBins];   // inclusive upper row length per bin
+};
+spmv_status launch_bin_rows(int64_t m, const int32_t *rp, const BinSpec &spec,
+                            unsigned int *block_counts, int32_t *rows_out,
+                            unsigned int *bin_offsets_dev, hipStream_t s);
+
+// ----------------------------------------------------------------- SpMV
+struct DiaWindow { int d0, d1; };   // diagonals [d0, d1] share one LDS window
+
+spmv_status run_csr_scalar(int elt, int64_t m, const int32_t *rp, const int32_t *col,
+                           const void *val, const void *x, void *y, int block, hipStream_t s);
+spmv_status run_csr_vector(int elt, int lanes, int64_t nrows, const int32_t *rows,
+                           const int32_t *rp, const int32_t *col, const void *val, const void *x,
+                           void *y, int block, hipStream_t s);
+spmv_status run_csr_rowblock(int elt, int64_t nrows, const int32_t *rows, const int32_t *rp,
+                             const int32_t *col, const void *val, const void *x, void *y,
+                             hipStream_t s);
+// split rows: segments (row, begin, end) reduce into partials, then fix-up
+spmv_status run_csr_split(int elt, int64_t nseg, const int64_t *segs, double *partials,
+                          int64_t nrows, const int64_t *row_seg_begin, const int32_t *rows,
+                          const int32_t *col, const void *val, const void *x, void *y,
+                          hipStream_t s);
+spmv_status run_ell(int elt, int64_t m, int64_t m_pad, int K, const int32_t *ecol,
+                    const void *eval, const void *x, void *y, int block, int unroll,
+                    hipStream_t s);
+spmv_status run_dia(int elt, bool lds, int64_t m, int64_t n, int64_t m_pad, int D,
+                    const int32_t *offs_dev, const int32_t *offs_host, int nwin,
+                    const DiaWindow *win_dev, int max_span, const void *data, const void *x,
+                    void *y, int block, int rows_per_thread, hipStream_t s);
+spmv_status run_coo(int elt, int64_t m, int64_t nnz, const int32_t *row_idx, const int32_t *col,
+                    const void *val, const void *x, void *y, int chunk, double *head,
+                    double *tail, uint32_t *flags, hipStream_t s);
+spmv_status run_fill_zero(int elt, int64_t m, void *y, hipStream_t s);
+
+// ----------------------------------------------------------------- MLP
+spmv_status run_mlp_infer(const float *params, int n_out, const float *mean, const float *stdv,
+                          const float *raw, int64_t rows, float *scores, hipStream_t s);
+
+// ----------------------------------------------------------------- misc
+spmv_status run_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+
+}  // namespace smat

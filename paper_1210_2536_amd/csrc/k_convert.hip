@@ -1,0 +1,357 @@
+// K2 format conversions (paper Section 2.1: the four basic formats; Table 4
+// and Section 4: ELL and DIA pay for zero fill) and K5 row binning for the
+// length-adaptive CSR kernel.
+//
+// Layouts (Figure 1 did not survive; standard definitions):
+//   COO  row index per stored entry, CSR order; columns and values are the
+//        CSR arrays themselves.
+//   ELL  K = max_RD slots per row, slot k of row i at k*m_pad + i (slot-major,
+//        coalesced across rows); empty slots hold col -1 and value +0.0.
+//   DIA  occupied diagonals d = j - i ascending; entry (i, i+off) at
+//        slot*m_pad + i; absent slots hold +0.0; a presence bitmap (bit s of
+//        uint32 word s >> 5) keeps explicit zeros distinguishable.
+// Values are copied as raw bit patterns (uint32 / uint64), never through
+// floating-point registers, so conversions are bit exact.
+#include "internal.hpp"
+
+namespace smat {
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kEntryRun = 8;
+
+__device__ __forceinline__ int64_t row_of_entry(const int32_t *__restrict__ rp, int64_t m,
+                                                int64_t p) {
+    int64_t lo = 0, hi = m - 1;
+    while (lo < hi) {
+        int64_t mid = (lo + hi + 1) >> 1;
+        if (rp[mid] <= p)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
+
+inline unsigned grid_for(int64_t work, int block) {
+    int64_t g = (work + block - 1) / block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+__global__ void k_csr_to_coo(int64_t m, int64_t nnz, const int32_t *__restrict__ rp,
+                             int32_t *__restrict__ row_idx) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t p0 = t * kEntryRun;
+    if (p0 >= nnz) return;
+    int64_t p1 = p0 + kEntryRun < nnz ? p0 + kEntryRun : nnz;
+    int64_t row = row_of_entry(rp, m, p0);
+    int64_t rend = rp[row + 1];
+    for (int64_t p = p0; p < p1; ++p) {
+        while (p >= rend) rend = rp[++row + 1];
+        row_idx[p] = (int32_t)row;
+    }
+}
+
+template <typename U>
+__global__ void k_csr_to_ell(int64_t m, int64_t m_pad, int K, const int32_t *__restrict__ rp,
+                             const int32_t *__restrict__ col, const U *__restrict__ val,
+                             int32_t *__restrict__ ecol, U *__restrict__ eval) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m_pad) return;
+    int64_t b = 0, len = 0;
+    if (i < m) {
+        b = rp[i];
+        len = rp[i + 1] - b;
+    }
+    for (int k = 0; k < K; ++k) {
+        int64_t s = (int64_t)k * m_pad + i;
+        if (k < len) {
+            ecol[s] = col[b + k];
+            eval[s] = val[b + k];
+        } else {
+            ecol[s] = -1;
+            eval[s] = 0;
+        }
+    }
+}
+
+template <typename U>
+__global__ void k_csr_to_dia(int64_t m, int64_t m_pad, int64_t nnz, const int32_t *__restrict__ rp,
+                             const int32_t *__restrict__ col, const U *__restrict__ val,
+                             const unsigned int *__restrict__ slot_map, U *__restrict__ data,
+                             uint32_t *present) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t p0 = t * kEntryRun;
+    if (p0 >= nnz) return;
+    int64_t p1 = p0 + kEntryRun < nnz ? p0 + kEntryRun : nnz;
+    int64_t row = row_of_entry(rp, m, p0);
+    int64_t rend = rp[row + 1];
+    for (int64_t p = p0; p < p1; ++p) {
+        while (p >= rend) rend = rp[++row + 1];
+        int64_t d = (int64_t)col[p] - row;
+        int64_t slot = slot_map[d + m - 1];
+        int64_t s = slot * m_pad + row;
+        data[s] = val[p];
+        atomicOr(&present[s >> 5], 1u << (s & 31));
+    }
+}
+
+__global__ void k_coo_to_csr(int64_t m, int64_t nnz, const int32_t *__restrict__ row_idx,
+                             int32_t *__restrict__ rp) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i > m) return;
+    int64_t a = 0, b = nnz;  // first entry with row_idx >= i
+    while (a < b) {
+        int64_t mid = (a + b) >> 1;
+        if (row_idx[mid] < i)
+            a = mid + 1;
+        else
+            b = mid;
+    }
+    rp[i] = (int32_t)a;
+}
+
+__global__ void k_ell_count(int64_t m, int64_t m_pad, int K, const int32_t *__restrict__ ecol,
+                            int32_t *__restrict__ counts) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int c = 0;
+    for (int k = 0; k < K; ++k) c += ecol[(int64_t)k * m_pad + i] >= 0;
+    counts[i] = c;
+}
+
+template <typename U>
+__global__ void k_ell_gather(int64_t m, int64_t m_pad, int K, const int32_t *__restrict__ ecol,
+                             const U *__restrict__ eval, const int32_t *__restrict__ rp,
+                             int32_t *__restrict__ col, U *__restrict__ val) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int64_t o = rp[i];
+    for (int k = 0; k < K; ++k) {
+        int64_t s = (int64_t)k * m_pad + i;
+        int32_t c = ecol[s];
+        if (c >= 0) {
+            col[o] = c;
+            val[o] = eval[s];
+            ++o;
+        }
+    }
+}
+
+__device__ __forceinline__ bool bit_at(const uint32_t *__restrict__ w, int64_t s) {
+    return (w[s >> 5] >> (s & 31)) & 1u;
+}
+
+__global__ void k_dia_count(int64_t m, int64_t m_pad, int D, const uint32_t *__restrict__ present,
+                            int32_t *__restrict__ counts) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int c = 0;
+    for (int d = 0; d < D; ++d) c += bit_at(present, (int64_t)d * m_pad + i);
+    counts[i] = c;
+}
+
+template <typename U>
+__global__ void k_dia_gather(int64_t m, int64_t m_pad, int D, const int32_t *__restrict__ offs,
+                             const U *__restrict__ data, const uint32_t *__restrict__ present,
+                             const int32_t *__restrict__ rp, int32_t *__restrict__ col,
+                             U *__restrict__ val) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    int64_t o = rp[i];
+    for (int d = 0; d < D; ++d) {
+        int64_t s = (int64_t)d * m_pad + i;
+        if (bit_at(present, s)) {
+            col[o] = (int32_t)(i + offs[d]);
+            val[o] = data[s];
+            ++o;
+        }
+    }
+}
+
+// ---- row binning: bin b holds rows with upper[b-1] < len <= upper[b]
+__device__ __forceinline__ int bin_of(int len, const BinSpec &spec) {
+    int b = 0;
+    while (b < kAdaptiveBins - 1 && len > spec.upper[b]) ++b;
+    return b;
+}
+
+__global__ void k_bin_count(int64_t m, const int32_t *__restrict__ rp, BinSpec spec,
+                            unsigned int *__restrict__ block_counts) {
+    __shared__ unsigned int cnt[kAdaptiveBins];
+    if (threadIdx.x < kAdaptiveBins) cnt[threadIdx.x] = 0;
+    __syncthreads();
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < m) atomicAdd(&cnt[bin_of(rp[i + 1] - rp[i], spec)], 1u);
+    __syncthreads();
+    // bin-major layout so each bin's blocks are contiguous for the scan
+    if (threadIdx.x < kAdaptiveBins)
+        block_counts[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = cnt[threadIdx.x];
+}
+
+// Exclusive scan over the bin-major block counts, one workgroup; also the
+// per-bin start offsets (bin_offsets[b], b <= kAdaptiveBins).
+__global__ void k_bin_scan(unsigned int *v, int64_t nblk, unsigned int *bin_offsets) {
+    __shared__ unsigned int part[1024];
+    __shared__ unsigned int carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    int64_t count = nblk * kAdaptiveBins;
+    for (int64_t base = 0; base < count; base += 1024) {
+        int64_t i = base + threadIdx.x;
+        unsigned int x = i < count ? v[i] : 0;
+        part[threadIdx.x] = x;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            unsigned int add = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+            __syncthreads();
+            part[threadIdx.x] += add;
+            __syncthreads();
+        }
+        unsigned int incl = part[threadIdx.x];
+        if (i < count) {
+            v[i] = carry + incl - x;
+            if (i % nblk == 0) bin_offsets[i / nblk] = carry + incl - x;
+        }
+        __syncthreads();
+        if (threadIdx.x == 1023) carry += incl;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bin_offsets[kAdaptiveBins] = carry;
+}
+
+// Stable scatter: rows keep ascending order inside each bin.
+__global__ void k_bin_scatter(int64_t m, const int32_t *__restrict__ rp, BinSpec spec,
+                              const unsigned int *__restrict__ block_base,
+                              int32_t *__restrict__ rows_out) {
+    constexpr int kWaves = kBlock / kWave;
+    __shared__ unsigned int wave_cnt[kWaves][kAdaptiveBins];
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int lane = threadIdx.x % kWave, w = threadIdx.x / kWave;
+    int b = i < m ? bin_of(rp[i + 1] - rp[i], spec) : -1;
+    unsigned long long below = lane ? (~0ull >> (kWave - lane)) : 0ull;
+    unsigned int rank = 0;
+    for (int q = 0; q < kAdaptiveBins; ++q) {
+        unsigned long long mask = __ballot(b == q);
+        if (b == q) rank = __popcll(mask & below);
+        if (lane == 0) wave_cnt[w][q] = __popcll(mask);
+    }
+    __syncthreads();
+    if (b >= 0) {
+        unsigned int pos = block_base[(int64_t)b * gridDim.x + blockIdx.x] + rank;
+        for (int w2 = 0; w2 < w; ++w2) pos += wave_cnt[w2][b];
+        rows_out[pos] = (int32_t)i;
+    }
+}
+
+}  // namespace
+
+spmv_status launch_csr_to_coo(int64_t m, int64_t nnz, const int32_t *rp, int32_t *row_idx,
+                              hipStream_t s) {
+    if (nnz == 0) return SPMV_OK;
+    k_csr_to_coo<<<grid_for((nnz + kEntryRun - 1) / kEntryRun, kBlock), kBlock, 0, s>>>(
+        m, nnz, rp, row_idx);
+    SMAT_LAUNCHED("csr_to_coo");
+    return SPMV_OK;
+}
+
+spmv_status launch_csr_to_ell(int64_t m, int64_t m_pad, int K, const int32_t *rp,
+                              const int32_t *col, const void *val, int elt, int32_t *ecol,
+                              void *eval, hipStream_t s) {
+    if (K == 0 || m_pad == 0) return SPMV_OK;
+    if (elt == 8)
+        k_csr_to_ell<uint64_t><<<grid_for(m_pad, kBlock), kBlock, 0, s>>>(
+            m, m_pad, K, rp, col, (const uint64_t *)val, ecol, (uint64_t *)eval);
+    else
+        k_csr_to_ell<uint32_t><<<grid_for(m_pad, kBlock), kBlock, 0, s>>>(
+            m, m_pad, K, rp, col, (const uint32_t *)val, ecol, (uint32_t *)eval);
+    SMAT_LAUNCHED("csr_to_ell");
+    return SPMV_OK;
+}
+
+spmv_status launch_csr_to_dia(int64_t m, int64_t n, int64_t m_pad, int64_t nnz, const int32_t *rp,
+                              const int32_t *col, const void *val, int elt,
+                              const unsigned int *slot_map, void *data, uint32_t *present,
+                              hipStream_t s) {
+    (void)n;
+    if (nnz == 0) return SPMV_OK;
+    unsigned g = grid_for((nnz + kEntryRun - 1) / kEntryRun, kBlock);
+    if (elt == 8)
+        k_csr_to_dia<uint64_t><<<g, kBlock, 0, s>>>(m, m_pad, nnz, rp, col,
+                                                    (const uint64_t *)val, slot_map,
+                                                    (uint64_t *)data, present);
+    else
+        k_csr_to_dia<uint32_t><<<g, kBlock, 0, s>>>(m, m_pad, nnz, rp, col,
+                                                    (const uint32_t *)val, slot_map,
+                                                    (uint32_t *)data, present);
+    SMAT_LAUNCHED("csr_to_dia");
+    return SPMV_OK;
+}
+
+spmv_status launch_coo_to_csr(int64_t m, int64_t nnz, const int32_t *row_idx, int32_t *rp,
+                              hipStream_t s) {
+    k_coo_to_csr<<<grid_for(m + 1, kBlock), kBlock, 0, s>>>(m, nnz, row_idx, rp);
+    SMAT_LAUNCHED("coo_to_csr");
+    return SPMV_OK;
+}
+
+spmv_status launch_ell_to_csr(int64_t m, int64_t m_pad, int K, const int32_t *ecol,
+                              const void *eval, int elt, int32_t *rp, int32_t *col, void *val,
+                              int32_t *counts, unsigned int *scratch, hipStream_t s) {
+    if (m > 0) {
+        k_ell_count<<<grid_for(m, kBlock), kBlock, 0, s>>>(m, m_pad, K, ecol, counts);
+        SMAT_LAUNCHED("ell_count");
+    }
+    spmv_status st = launch_exclusive_scan_rows(m, counts, rp, scratch, s);
+    if (st != SPMV_OK) return st;
+    if (m == 0) return SPMV_OK;
+    if (elt == 8)
+        k_ell_gather<uint64_t><<<grid_for(m, kBlock), kBlock, 0, s>>>(
+            m, m_pad, K, ecol, (const uint64_t *)eval, rp, col, (uint64_t *)val);
+    else
+        k_ell_gather<uint32_t><<<grid_for(m, kBlock), kBlock, 0, s>>>(
+            m, m_pad, K, ecol, (const uint32_t *)eval, rp, col, (uint32_t *)val);
+    SMAT_LAUNCHED("ell_gather");
+    return SPMV_OK;
+}
+
+spmv_status launch_dia_to_csr(int64_t m, int64_t n, int64_t m_pad, int D, const int32_t *offs,
+                              const void *data, const uint32_t *present, int elt, int32_t *rp,
+                              int32_t *col, void *val, int32_t *counts, unsigned int *scratch,
+                              hipStream_t s) {
+    (void)n;
+    if (m > 0) {
+        k_dia_count<<<grid_for(m, kBlock), kBlock, 0, s>>>(m, m_pad, D, present, counts);
+        SMAT_LAUNCHED("dia_count");
+    }
+    spmv_status st = launch_exclusive_scan_rows(m, counts, rp, scratch, s);
+    if (st != SPMV_OK) return st;
+    if (m == 0) return SPMV_OK;
+    if (elt == 8)
+        k_dia_gather<uint64_t><<<grid_for(m, kBlock), kBlock, 0, s>>>(
+            m, m_pad, D, offs, (const uint64_t *)data, present, rp, col, (uint64_t *)val);
+    else
+        k_dia_gather<uint32_t><<<grid_for(m, kBlock), kBlock, 0, s>>>(
+            m, m_pad, D, offs, (const uint32_t *)data, present, rp, col, (uint32_t *)val);
+    SMAT_LAUNCHED("dia_gather");
+    return SPMV_OK;
+}
+
+spmv_status launch_bin_rows(int64_t m, const int32_t *rp, const BinSpec &spec,
+                            unsigned int *block_counts, int32_t *rows_out,
+                            unsigned int *bin_offsets_dev, hipStream_t s) {
+    if (m == 0) {
+        SMAT_HIP(hipMemsetAsync(bin_offsets_dev, 0, sizeof(unsigned) * (kAdaptiveBins + 1), s));
+        return SPMV_OK;
+    }
+    unsigned nblk = grid_for(m, kBlock);
+    k_bin_count<<<nblk, kBlock, 0, s>>>(m, rp, spec, block_counts);
+    SMAT_LAUNCHED("bin_count");
+    k_bin_scan<<<1, 1024, 0, s>>>(block_counts, nblk, bin_offsets_dev);
+    SMAT_LAUNCHED("bin_scan");
+    k_bin_scatter<<<nblk, kBlock, 0, s>>>(m, rp, spec, block_counts, rows_out);
+    SMAT_LAUNCHED("bin_scatter");
+    return SPMV_OK;
+}
+
+}  // namespace smat

@@ -1,0 +1,487 @@
+// SpMV kernels for gfx950: one implementation family per storage format
+// (paper Section 2.1 and Table 4), all computing
+//     y_i = sum over stored entries of row i of a_ij x_j.
+//
+// Numerics: float64 data multiplies and accumulates in float64 with fused
+// multiply-add; float32 data is widened to float64 (the product of two
+// float32 numbers is exact there), accumulated in float64 and rounded once.
+// Every kernel bounds its sequential summation chain (at most a few thousand
+// additions per partial sum; long rows are split across lanes and
+// workgroups), which keeps the float64 result within 1e-12 (|A||x|)_i.
+//
+// Results are deterministic: no floating-point atomics anywhere; partial
+// sums that cross workgroups are combined by a second kernel in a fixed
+// order.
+#include "spmv_device.hpp"
+
+#include <climits>
+
+namespace smat {
+namespace {
+
+inline unsigned grid_for(int64_t work, int block) {
+    int64_t g = (work + block - 1) / block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+// ---------------------------------------------------------------- CSR scalar
+// One thread per row: the plain CSR kernel (the "naive" CSR SpMV that the
+// paper's Introduction contrasts against tuned kernels).
+template <typename T>
+__global__ __launch_bounds__(1024) void k_csr_scalar(int64_t m, const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ col,
+                                                     const T *__restrict__ val,
+                                                     const T *__restrict__ x, T *__restrict__ y) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    y[i] = (T)csr_row_seq<T>(i, rp, col, val, x);
+}
+
+// ---------------------------------------------------------------- CSR vector
+// L lanes per row (L = 1..64, a sub-wavefront group); lanes stride the row so
+// each trip of the group loads L consecutive entries; xor-shuffle reduction.
+// `rows` (optional) lists the rows to process, e.g. one length bin.
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_csr_vector(int64_t nrows, const int32_t *__restrict__ rows,
+                                                    const int32_t *__restrict__ rp,
+                                                    const int32_t *__restrict__ col,
+                                                    const T *__restrict__ val,
+                                                    const T *__restrict__ x, T *__restrict__ y) {
+    int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t r = gt / L;
+    int lane = threadIdx.x & (L - 1);
+    if (r >= nrows) return;  // whole lane groups leave together
+    int64_t row = rows ? (int64_t)rows[r] : r;
+    double acc = csr_row_lanes<T, L>(row, lane, rp, col, val, x);
+    if (lane == 0) y[row] = (T)acc;
+}
+
+// ---------------------------------------------------------------- long rows
+// One workgroup per row for rows too long for one wavefront.
+constexpr int kRowBlock = 512;
+
+template <typename T>
+__global__ __launch_bounds__(kRowBlock) void k_csr_rowblock(const int32_t *__restrict__ rows,
+                                                            const int32_t *__restrict__ rp,
+                                                            const int32_t *__restrict__ col,
+                                                            const T *__restrict__ val,
+                                                            const T *__restrict__ x,
+                                                            T *__restrict__ y) {
+    __shared__ double part[kRowBlock / kWave];
+    int64_t row = rows[blockIdx.x];
+    int32_t b = rp[row], e = rp[row + 1];
+    double acc = 0.0;
+#pragma unroll 4
+    for (int32_t p = b + threadIdx.x; p < e; p += kRowBlock)
+        acc = fma((double)val[p], (double)x[col[p]], acc);
+    for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kRowBlock / kWave; ++w) s += part[w];
+        y[row] = (T)s;
+    }
+}
+
+// Rows longer than one workgroup may sum alone: segments of a row reduce to
+// partials (one workgroup each), then one thread per row adds them in order.
+template <typename T>
+__global__ __launch_bounds__(kRowBlock) void k_csr_segment(const int64_t *__restrict__ segs,
+                                                           const int32_t *__restrict__ col,
+                                                           const T *__restrict__ val,
+                                                           const T *__restrict__ x,
+                                                           double *__restrict__ partials) {
+    __shared__ double part[kRowBlock / kWave];
+    int64_t b = segs[3 * blockIdx.x + 1], e = segs[3 * blockIdx.x + 2];
+    double acc = 0.0;
+#pragma unroll 4
+    for (int64_t p = b + threadIdx.x; p < e; p += kRowBlock)
+        acc = fma((double)val[p], (double)x[col[p]], acc);
+    for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < kRowBlock / kWave; ++w) s += part[w];
+        partials[blockIdx.x] = s;
+    }
+}
+
+template <typename T>
+__global__ void k_csr_segment_fixup(int64_t nrows, const int64_t *__restrict__ row_seg_begin,
+                                    const int32_t *__restrict__ rows,
+                                    const double *__restrict__ partials, T *__restrict__ y) {
+    int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    double s = 0.0;
+    for (int64_t q = row_seg_begin[r]; q < row_seg_begin[r + 1]; ++q) s += partials[q];
+    y[rows[r]] = (T)s;
+}
+
+// ---------------------------------------------------------------- ELL
+// Slot-major layout: thread i reads slot k of row i at k*m_pad + i, so a
+// wavefront reads 64 consecutive values and 64 consecutive columns per slot.
+// U slots are loaded before any is used, to keep more loads in flight.
+template <typename T, int U>
+__global__ __launch_bounds__(1024) void k_ell(int64_t m, int64_t m_pad, int K,
+                                              const int32_t *__restrict__ ecol,
+                                              const T *__restrict__ eval, const T *__restrict__ x,
+                                              T *__restrict__ y) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    y[i] = (T)ell_row<T, U>(i, m_pad, K, ecol, eval, x);
+}
+
+// ---------------------------------------------------------------- DIA
+// A workgroup owns R = blockDim * RPT consecutive rows.  Diagonals are grouped
+// into windows whose offsets span at most `max_span`; for each window the
+// slice x[r0 + lo, r0 + R + hi) is staged once in LDS and every diagonal of
+// the window reads its shifted view from there, while the diagonal values
+// stream from HBM with unit stride.  Summation runs over diagonals in
+// ascending offset order, i.e. ascending column order as in CSR.
+template <typename T, int RPT>
+__global__ __launch_bounds__(256) void k_dia_lds(int64_t m, int64_t n, int64_t m_pad,
+                                                 const int32_t *__restrict__ offs, int nwin,
+                                                 const DiaWindow *__restrict__ win,
+                                                 const T *__restrict__ data,
+                                                 const T *__restrict__ x, T *__restrict__ y) {
+    extern __shared__ unsigned char smem_raw[];
+    T *xs = reinterpret_cast<T *>(smem_raw);
+    const int64_t r0 = (int64_t)blockIdx.x * blockDim.x * RPT;
+    dia_tile_lds<T, RPT>(r0, m, n, m_pad, offs, nwin, win, data, x, y, xs);
+}
+
+// DIA without LDS: x comes through L1/L2 (neighbouring diagonals hit the same
+// cache lines).
+template <typename T, int RPT>
+__global__ __launch_bounds__(256) void k_dia_direct(int64_t m, int64_t n, int64_t m_pad, int D,
+                                                    const int32_t *__restrict__ offs,
+                                                    const T *__restrict__ data,
+                                                    const T *__restrict__ x, T *__restrict__ y) {
+    const int64_t r0 = (int64_t)blockIdx.x * blockDim.x * RPT;
+    dia_tile_direct<T, RPT>(r0, m, n, m_pad, D, offs, data, x, y);
+}
+
+// ---------------------------------------------------------------- COO
+// Each wavefront owns a chunk of E*64 consecutive entries (rows ascending).
+// Per trip the 64 lanes form their products and run a segmented inclusive
+// scan keyed by row index (6 shuffle steps); the lane ending a row segment
+// writes the row.  The running sum of a row that continues past a trip is
+// carried to the next trip; a row cut by a chunk boundary leaves a partial
+// (head: row began in an earlier chunk; tail: row continues in a later one)
+// that k_coo_fixup adds up in chunk order.  Rows with no entries are
+// written as 0 by the lane that sees the gap.
+template <typename T>
+__device__ __forceinline__ void coo_emit(int row, double v, int first_row, bool first_partial,
+                                         int last_row, bool last_continues, int64_t w,
+                                         double *head, double *tail, T *y) {
+    if (row == first_row && first_partial)
+        head[w] = v;
+    else if (row == last_row && last_continues)
+        tail[w] = v;
+    else
+        y[row] = (T)v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_coo(int64_t m, int64_t nnz, int E,
+                                             const int32_t *__restrict__ ri,
+                                             const int32_t *__restrict__ col,
+                                             const T *__restrict__ val, const T *__restrict__ x,
+                                             T *__restrict__ y, double *__restrict__ head,
+                                             double *__restrict__ tail,
+                                             uint32_t *__restrict__ flags) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t w = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) / kWave;
+    const int64_t chunk = (int64_t)E * kWave;
+    const int64_t c0 = w * chunk;
+    if (c0 >= nnz) return;  // whole wavefront
+    const int64_t c1 = c0 + chunk < nnz ? c0 + chunk : nnz;
+    const int first_row = ri[c0];
+    const int last_row = ri[c1 - 1];
+    const int prev_row = c0 > 0 ? ri[c0 - 1] : -1;
+    const int next_row = c1 < nnz ? ri[c1] : INT_MAX;
+    const bool first_partial = prev_row == first_row;
+    const bool last_continues = next_row == last_row;
+    // empty rows between the previous chunk's last row and this chunk's first
+    for (int64_t r = (int64_t)prev_row + 1 + lane; r < first_row; r += kWave) y[r] = T(0);
+    // empty rows after the matrix's last stored entry
+    if (c1 == nnz)
+        for (int64_t r = (int64_t)last_row + 1 + lane; r < m; r += kWave) y[r] = T(0);
+
+    int carry_row = -1;
+    double carry = 0.0;
+    int before = first_row;  // row of the entry preceding lane 0 of this trip
+    for (int64_t it = c0; it < c1; it += kWave) {
+        const int64_t p = it + lane;
+        const bool valid = p < c1;
+        const int r = valid ? ri[p] : INT_MAX;
+        double v = valid ? fma((double)val[p], (double)x[col[p]], 0.0) : 0.0;
+        // rows skipped between consecutive entries have no entries: zero them
+        int rb = __shfl_up(r, 1, kWave);
+        if (lane == 0) rb = before;
+        if (valid && r > rb + 1)
+            for (int rr = rb + 1; rr < r; ++rr) y[rr] = T(0);
+        const int r_lane0 = __shfl(r, 0, kWave);
+        if (carry_row >= 0) {
+            if (carry_row == r_lane0) {
+                if (lane == 0) v = carry + v;
+            } else if (lane == 0) {
+                coo_emit<T>(carry_row, carry, first_row, first_partial, last_row,
+                            last_continues, w, head, tail, y);
+            }
+        }
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            double vu = __shfl_up(v, off, kWave);
+            int ru = __shfl_up(r, off, kWave);
+            if (lane >= off && ru == r) v += vu;
+        }
+        const int rn = __shfl_down(r, 1, kWave);
+        if (valid && lane != kWave - 1 && rn != r)
+            coo_emit<T>(r, v, first_row, first_partial, last_row, last_continues, w, head, tail,
+                        y);
+        const int r_last = __shfl(r, kWave - 1, kWave);
+        const double v_last = __shfl(v, kWave - 1, kWave);
+        if (r_last != INT_MAX) {
+            carry_row = r_last;
+            carry = v_last;
+            before = r_last;
+        } else {
+            carry_row = -1;
+        }
+    }
+    if (carry_row >= 0 && lane == 0)
+        coo_emit<T>(carry_row, carry, first_row, first_partial, last_row, last_continues, w, head,
+                    tail, y);
+    if (lane == 0)
+        flags[w] = (first_partial ? 1u : 0u) | (last_continues ? 2u : 0u) |
+                   (first_row == last_row ? 4u : 0u);
+}
+
+// The chunk in which a row that crosses chunk boundaries starts ("owner")
+// adds its tail partial and the head partials of the following chunks, in
+// chunk order, and writes the row.
+template <typename T>
+__global__ void k_coo_fixup(int64_t nchunks, int64_t chunk, int64_t nnz,
+                            const int32_t *__restrict__ ri, const double *__restrict__ head,
+                            const double *__restrict__ tail, const uint32_t *__restrict__ flags,
+                            T *__restrict__ y) {
+    int64_t w = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (w >= nchunks) return;
+    uint32_t f = flags[w];
+    if (!(f & 2u)) return;                  // last row ends inside this chunk
+    if ((f & 1u) && (f & 4u)) return;       // a middle piece of an earlier row
+    int64_t c1 = (w + 1) * chunk < nnz ? (w + 1) * chunk : nnz;
+    int row = ri[c1 - 1];
+    double s = tail[w];
+    for (int64_t w2 = w + 1; w2 < nchunks; ++w2) {
+        s += head[w2];
+        uint32_t f2 = flags[w2];
+        if (!((f2 & 2u) && (f2 & 4u))) break;
+    }
+    y[row] = (T)s;
+}
+
+template <typename T>
+__global__ void k_fill_zero(int64_t m, T *y) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < m) y[i] = T(0);
+}
+
+template <typename T>
+spmv_status csr_vector_dispatch(int lanes, int64_t nrows, const int32_t *rows, const int32_t *rp,
+                                const int32_t *col, const T *val, const T *x, T *y, int block,
+                                hipStream_t s) {
+    if (nrows == 0) return SPMV_OK;
+    if (block <= 0) block = 256;
+    block = block < lanes ? lanes : block;
+    unsigned g = grid_for(nrows * lanes, block);
+    switch (lanes) {
+    case 1: k_csr_vector<T, 1><<<g, block, 0, s>>>(nrows, rows, rp, col, val, x, y); break;
+    case 2: k_csr_vector<T, 2><<<g, block, 0, s>>>(nrows, rows, rp, col, val, x, y); break;
+    case 4: k_csr_vector<T, 4><<<g, block, 0, s>>>(nrows, rows, rp, col, val, x, y); break;
+    case 8: k_csr_vector<T, 8><<<g, block, 0, s>>>(nrows, rows, rp, col, val, x, y); break;
+    case 16: k_csr_vector<T, 16><<<g, block, 0, s>>>(nrows, rows, rp, col, val, x, y); break;
+    case 32: k_csr_vector<T, 32><<<g, block, 0, s>>>(nrows, rows, rp, col, val, x, y); break;
+    case 64: k_csr_vector<T, 64><<<g, block, 0, s>>>(nrows, rows, rp, col, val, x, y); break;
+    default:
+        set_error("csr_vector: lanes must be a power of two in [1, 64], got %d", lanes);
+        return SPMV_EINVAL;
+    }
+    SMAT_LAUNCHED("csr_vector");
+    return SPMV_OK;
+}
+
+template <typename T>
+spmv_status ell_dispatch(int64_t m, int64_t m_pad, int K, const int32_t *ecol, const T *eval,
+                         const T *x, T *y, int block, int unroll, hipStream_t s) {
+    if (m == 0) return SPMV_OK;
+    if (block <= 0) block = 256;
+    unsigned g = grid_for(m, block);
+    switch (unroll) {
+    case 1: k_ell<T, 1><<<g, block, 0, s>>>(m, m_pad, K, ecol, eval, x, y); break;
+    case 2: k_ell<T, 2><<<g, block, 0, s>>>(m, m_pad, K, ecol, eval, x, y); break;
+    default: k_ell<T, 4><<<g, block, 0, s>>>(m, m_pad, K, ecol, eval, x, y); break;
+    }
+    SMAT_LAUNCHED("ell");
+    return SPMV_OK;
+}
+
+template <typename T>
+spmv_status dia_dispatch(bool lds, int64_t m, int64_t n, int64_t m_pad, int D,
+                         const int32_t *offs, int nwin, const DiaWindow *win, int max_span,
+                         const T *data, const T *x, T *y, int block, int rpt, hipStream_t s) {
+    if (m == 0) return SPMV_OK;
+    if (block <= 0) block = 256;
+    if (rpt != 1 && rpt != 2 && rpt != 4 && rpt != 8) rpt = 4;
+    int64_t tile = (int64_t)block * rpt;
+    unsigned g = grid_for(m, (int)tile);
+    if (lds) {
+        size_t sh = (size_t)(tile + max_span) * sizeof(T);
+        switch (rpt) {
+        case 1: k_dia_lds<T, 1><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
+        case 2: k_dia_lds<T, 2><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
+        case 4: k_dia_lds<T, 4><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
+        default: k_dia_lds<T, 8><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
+        }
+    } else {
+        switch (rpt) {
+        case 1: k_dia_direct<T, 1><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
+        case 2: k_dia_direct<T, 2><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
+        case 4: k_dia_direct<T, 4><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
+        default: k_dia_direct<T, 8><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
+        }
+    }
+    SMAT_LAUNCHED(lds ? "dia_lds" : "dia_direct");
+    return SPMV_OK;
+}
+
+}  // namespace
+
+#define SMAT_BY_ELT(elt, CALL_F, CALL_D) ((elt) == 8 ? (CALL_D) : (CALL_F))
+
+spmv_status run_csr_scalar(int elt, int64_t m, const int32_t *rp, const int32_t *col,
+                           const void *val, const void *x, void *y, int block, hipStream_t s) {
+    if (m == 0) return SPMV_OK;
+    if (block <= 0) block = 256;
+    unsigned g = grid_for(m, block);
+    if (elt == 8)
+        k_csr_scalar<double><<<g, block, 0, s>>>(m, rp, col, (const double *)val,
+                                                 (const double *)x, (double *)y);
+    else
+        k_csr_scalar<float><<<g, block, 0, s>>>(m, rp, col, (const float *)val,
+                                                (const float *)x, (float *)y);
+    SMAT_LAUNCHED("csr_scalar");
+    return SPMV_OK;
+}
+
+spmv_status run_csr_vector(int elt, int lanes, int64_t nrows, const int32_t *rows,
+                           const int32_t *rp, const int32_t *col, const void *val, const void *x,
+                           void *y, int block, hipStream_t s) {
+    return SMAT_BY_ELT(elt,
+                       csr_vector_dispatch<float>(lanes, nrows, rows, rp, col, (const float *)val,
+                                                  (const float *)x, (float *)y, block, s),
+                       csr_vector_dispatch<double>(lanes, nrows, rows, rp, col,
+                                                   (const double *)val, (const double *)x,
+                                                   (double *)y, block, s));
+}
+
+spmv_status run_csr_rowblock(int elt, int64_t nrows, const int32_t *rows, const int32_t *rp,
+                             const int32_t *col, const void *val, const void *x, void *y,
+                             hipStream_t s) {
+    if (nrows == 0) return SPMV_OK;
+    if (elt == 8)
+        k_csr_rowblock<double><<<(unsigned)nrows, kRowBlock, 0, s>>>(
+            rows, rp, col, (const double *)val, (const double *)x, (double *)y);
+    else
+        k_csr_rowblock<float><<<(unsigned)nrows, kRowBlock, 0, s>>>(
+            rows, rp, col, (const float *)val, (const float *)x, (float *)y);
+    SMAT_LAUNCHED("csr_rowblock");
+    return SPMV_OK;
+}
+
+spmv_status run_csr_split(int elt, int64_t nseg, const int64_t *segs, double *partials,
+                          int64_t nrows, const int64_t *row_seg_begin, const int32_t *rows,
+                          const int32_t *col, const void *val, const void *x, void *y,
+                          hipStream_t s) {
+    if (nrows == 0) return SPMV_OK;
+    if (elt == 8) {
+        k_csr_segment<double><<<(unsigned)nseg, kRowBlock, 0, s>>>(
+            segs, col, (const double *)val, (const double *)x, partials);
+        SMAT_LAUNCHED("csr_segment");
+        k_csr_segment_fixup<double><<<grid_for(nrows, 64), 64, 0, s>>>(
+            nrows, row_seg_begin, rows, partials, (double *)y);
+    } else {
+        k_csr_segment<float><<<(unsigned)nseg, kRowBlock, 0, s>>>(
+            segs, col, (const float *)val, (const float *)x, partials);
+        SMAT_LAUNCHED("csr_segment");
+        k_csr_segment_fixup<float><<<grid_for(nrows, 64), 64, 0, s>>>(
+            nrows, row_seg_begin, rows, partials, (float *)y);
+    }
+    SMAT_LAUNCHED("csr_segment_fixup");
+    return SPMV_OK;
+}
+
+spmv_status run_ell(int elt, int64_t m, int64_t m_pad, int K, const int32_t *ecol,
+                    const void *eval, const void *x, void *y, int block, int unroll,
+                    hipStream_t s) {
+    return SMAT_BY_ELT(elt,
+                       ell_dispatch<float>(m, m_pad, K, ecol, (const float *)eval,
+                                           (const float *)x, (float *)y, block, unroll, s),
+                       ell_dispatch<double>(m, m_pad, K, ecol, (const double *)eval,
+                                            (const double *)x, (double *)y, block, unroll, s));
+}
+
+spmv_status run_dia(int elt, bool lds, int64_t m, int64_t n, int64_t m_pad, int D,
+                    const int32_t *offs_dev, const int32_t *offs_host, int nwin,
+                    const DiaWindow *win_dev, int max_span, const void *data, const void *x,
+                    void *y, int block, int rows_per_thread, hipStream_t s) {
+    (void)offs_host;
+    if (D == 0) return run_fill_zero(elt, m, y, s);
+    return SMAT_BY_ELT(elt,
+                       dia_dispatch<float>(lds, m, n, m_pad, D, offs_dev, nwin, win_dev, max_span,
+                                           (const float *)data, (const float *)x, (float *)y,
+                                           block, rows_per_thread, s),
+                       dia_dispatch<double>(lds, m, n, m_pad, D, offs_dev, nwin, win_dev,
+                                            max_span, (const double *)data, (const double *)x,
+                                            (double *)y, block, rows_per_thread, s));
+}
+
+spmv_status run_coo(int elt, int64_t m, int64_t nnz, const int32_t *row_idx, const int32_t *col,
+                    const void *val, const void *x, void *y, int chunk, double *head,
+                    double *tail, uint32_t *flags, hipStream_t s) {
+    if (m == 0) return SPMV_OK;
+    if (nnz == 0) return run_fill_zero(elt, m, y, s);
+    int64_t per = (int64_t)chunk * kWave;
+    int64_t nchunks = (nnz + per - 1) / per;
+    unsigned g = grid_for(nchunks * kWave, 256);
+    if (elt == 8) {
+        k_coo<double><<<g, 256, 0, s>>>(m, nnz, chunk, row_idx, col, (const double *)val,
+                                        (const double *)x, (double *)y, head, tail, flags);
+        SMAT_LAUNCHED("coo");
+        k_coo_fixup<double><<<grid_for(nchunks, 256), 256, 0, s>>>(nchunks, per, nnz, row_idx,
+                                                                   head, tail, flags, (double *)y);
+    } else {
+        k_coo<float><<<g, 256, 0, s>>>(m, nnz, chunk, row_idx, col, (const float *)val,
+                                       (const float *)x, (float *)y, head, tail, flags);
+        SMAT_LAUNCHED("coo");
+        k_coo_fixup<float><<<grid_for(nchunks, 256), 256, 0, s>>>(nchunks, per, nnz, row_idx,
+                                                                  head, tail, flags, (float *)y);
+    }
+    SMAT_LAUNCHED("coo_fixup");
+    return SPMV_OK;
+}
+
+spmv_status run_fill_zero(int elt, int64_t m, void *y, hipStream_t s) {
+    if (m == 0) return SPMV_OK;
+    if (elt == 8)
+        k_fill_zero<double><<<grid_for(m, 256), 256, 0, s>>>(m, (double *)y);
+    else
+        k_fill_zero<float><<<grid_for(m, 256), 256, 0, s>>>(m, (float *)y);
+    SMAT_LAUNCHED("fill_zero");
+    return SPMV_OK;
+}
+
+}  // namespace smat

@@ -1,0 +1,84 @@
+// Plan and variant state shared by the C-ABI translation units.
+#pragma once
+
+#include <memory>
+#include <vector>
+
+#include "internal.hpp"
+
+namespace smat {
+
+// Device allocation owned by a plan or a candidate.
+struct Dev {
+    void *p = nullptr;
+    size_t bytes = 0;
+    Dev() = default;
+    Dev(const Dev &) = delete;
+    Dev &operator=(const Dev &) = delete;
+    ~Dev() { release(); }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    spmv_status alloc(size_t b) {
+        release();
+        if (b == 0) b = 16;
+        hipError_t e = hipMalloc(&p, b);
+        if (e != hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+            set_error("device allocation of %zu bytes failed: %s", b, hipGetErrorString(e));
+            return SPMV_ENOMEM;
+        }
+        bytes = b;
+        return SPMV_OK;
+    }
+    template <typename T> T *as() const { return static_cast<T *>(p); }
+};
+
+// Kernel-specific state: the matrix in one format plus launch parameters.
+struct Variant {
+    int kernel = -1;
+    spmv_params prm{};
+    // COO
+    Dev row_idx, coo_head, coo_tail, coo_flags;
+    // ELL
+    Dev ecol, eval;
+    int K = 0;
+    // DIA
+    Dev dia_off, dia_data, dia_present, dia_win;
+    int D = 0, nwin = 0, max_span = 0;
+    // CSR adaptive
+    Dev bin_rows, bin_scratch, split_segs, split_partials, split_begin, split_rows;
+    unsigned bin_off[kAdaptiveBins + 1] = {};
+    int bin_lanes[kAdaptiveBins] = {};
+    int64_t nsplit_rows = 0, nsplit_segs = 0;
+    uint64_t bytes() const {
+        return row_idx.bytes + coo_head.bytes + coo_tail.bytes + coo_flags.bytes + ecol.bytes +
+               eval.bytes + dia_off.bytes + dia_data.bytes + dia_present.bytes + dia_win.bytes +
+               bin_rows.bytes + bin_scratch.bytes + split_segs.bytes + split_partials.bytes +
+               split_begin.bytes + split_rows.bytes;
+    }
+};
+
+
+}  // namespace smat
+
+struct spmv_selector_s {
+    smat::Dev params, mean, stdv;
+    int n_out = 0;
+};
+
+struct spmv_plan_s {
+    int64_t m = 0, n = 0, nnz = 0;
+    int dtype = 0, elt = 4;
+    int64_t m_pad = 0;
+    smat::Dev rp, col, val;             // CSR copy (CSR kernels and COO)
+    bool has_csr = false;
+    std::unique_ptr<smat::Variant> var; // the chosen kernel's state
+    spmv_plan_info info{};
+    smat::Dev diag_map;                 // diagonal -> slot map (kept only while converting)
+    std::vector<int32_t> dia_offsets;
+};
+

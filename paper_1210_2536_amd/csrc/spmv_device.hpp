@@ -1,0 +1,132 @@
+// Per-row / per-tile SpMV device functions shared by the stand-alone kernels
+// and the persistent multilevel kernel, so both compute every output with the
+// same operations in the same order (bitwise-identical results).
+#pragma once
+
+#include "internal.hpp"
+
+namespace smat {
+
+// Plain CSR row: one thread, storage order.
+template <typename T>
+__device__ __forceinline__ double csr_row_seq(int64_t i, const int32_t *__restrict__ rp,
+                                              const int32_t *__restrict__ col,
+                                              const T *__restrict__ val,
+                                              const T *__restrict__ x) {
+    double acc = 0.0;
+    int32_t b = rp[i], e = rp[i + 1];
+    for (int32_t p = b; p < e; ++p) acc = fma((double)val[p], (double)x[col[p]], acc);
+    return acc;
+}
+
+// CSR row by a group of L lanes (lane = 0..L-1); lanes stride the row and
+// reduce by xor shuffles.  Every lane of the group returns the row sum.
+template <typename T, int L>
+__device__ __forceinline__ double csr_row_lanes(int64_t row, int lane,
+                                                const int32_t *__restrict__ rp,
+                                                const int32_t *__restrict__ col,
+                                                const T *__restrict__ val,
+                                                const T *__restrict__ x) {
+    int32_t b = rp[row], e = rp[row + 1];
+    double acc = 0.0;
+#pragma unroll 4
+    for (int32_t p = b + lane; p < e; p += L) acc = fma((double)val[p], (double)x[col[p]], acc);
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, L);
+    return acc;
+}
+
+// ELL row: slots in order, U slots loaded ahead of use.
+template <typename T, int U>
+__device__ __forceinline__ double ell_row(int64_t i, int64_t m_pad, int K,
+                                          const int32_t *__restrict__ ecol,
+                                          const T *__restrict__ eval, const T *__restrict__ x) {
+    double acc = 0.0;
+    int k = 0;
+    for (; k + U <= K; k += U) {
+        int32_t c[U];
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int64_t s = (int64_t)(k + u) * m_pad + i;
+            c[u] = ecol[s];
+            v[u] = eval[s];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (c[u] >= 0) acc = fma((double)v[u], (double)x[c[u]], acc);
+    }
+    for (; k < K; ++k) {
+        int64_t s = (int64_t)k * m_pad + i;
+        int32_t c = ecol[s];
+        if (c >= 0) acc = fma((double)eval[s], (double)x[c], acc);
+    }
+    return acc;
+}
+
+// DIA tile with x windows staged in LDS; every thread of the workgroup must
+// call it (it synchronises).  Rows r0 + threadIdx.x + q*blockDim.x, q < RPT.
+template <typename T, int RPT>
+__device__ __forceinline__ void dia_tile_lds(int64_t r0, int64_t m, int64_t n, int64_t m_pad,
+                                             const int32_t *__restrict__ offs, int nwin,
+                                             const DiaWindow *__restrict__ win,
+                                             const T *__restrict__ data,
+                                             const T *__restrict__ x, T *__restrict__ y, T *xs) {
+    const int R = blockDim.x * RPT;
+    double acc[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
+    for (int w = 0; w < nwin; ++w) {
+        const int d0 = win[w].d0, d1 = win[w].d1;
+        const int lo = offs[d0], hi = offs[d1];
+        const int len = R + (hi - lo);
+        __syncthreads();  // previous window fully consumed
+        for (int t = threadIdx.x; t < len; t += blockDim.x) {
+            int64_t j = r0 + lo + t;
+            xs[t] = (j >= 0 && j < n) ? x[j] : T(0);
+        }
+        __syncthreads();
+        for (int d = d0; d <= d1; ++d) {
+            const int sh = offs[d] - lo;
+            const T *dd = data + (int64_t)d * m_pad + r0;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                int il = threadIdx.x + q * blockDim.x;
+                if (r0 + il < m) acc[q] = fma((double)dd[il], (double)xs[il + sh], acc[q]);
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        int64_t i = r0 + threadIdx.x + q * blockDim.x;
+        if (i < m) y[i] = (T)acc[q];
+    }
+}
+
+// DIA tile reading x through the caches.
+template <typename T, int RPT>
+__device__ __forceinline__ void dia_tile_direct(int64_t r0, int64_t m, int64_t n, int64_t m_pad,
+                                                int D, const int32_t *__restrict__ offs,
+                                                const T *__restrict__ data,
+                                                const T *__restrict__ x, T *__restrict__ y) {
+    double acc[RPT];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
+    for (int d = 0; d < D; ++d) {
+        const int64_t off = offs[d];
+        const T *dd = data + (int64_t)d * m_pad;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            int64_t i = r0 + threadIdx.x + q * blockDim.x;
+            int64_t j = i + off;
+            if (i < m && j >= 0 && j < n) acc[q] = fma((double)dd[i], (double)x[j], acc[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        int64_t i = r0 + threadIdx.x + q * blockDim.x;
+        if (i < m) y[i] = (T)acc[q];
+    }
+}
+
+}  // namespace smat

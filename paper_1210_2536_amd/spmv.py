@@ -1,0 +1,299 @@
+"""Torch-facing wrapper over the C-ABI (device memory and streams only).
+
+All computation happens in the HIP library; this module only turns torch
+device tensors into pointers and sizes, and the current torch stream into the
+``hipStream_t`` handle.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+import os
+
+import numpy as np
+
+from . import capi as C
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return C.SPMV_F64
+    if t.dtype == torch.float32:
+        return C.SPMV_F32
+    raise TypeError(f"values must be float32 or float64, got {t.dtype}")
+
+
+def make_csr(row_ptr, col, val, n):
+    """spmv_csr view of torch device tensors (int32 row_ptr/col, f32/f64 val)."""
+    torch = _torch()
+    for name, t, dt in (("row_ptr", row_ptr, torch.int32), ("col", col, torch.int32)):
+        if t.dtype != dt or not t.is_cuda or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous int32 device tensor")
+    if not val.is_cuda or not val.is_contiguous():
+        raise TypeError("val must be a contiguous device tensor")
+    m = row_ptr.numel() - 1
+    return C.spmv_csr(m, int(n), int(col.numel()), _ptr(row_ptr), _ptr(col), _ptr(val),
+                      _dtype_code(val))
+
+
+def _struct_to_dict(s):
+    out = {}
+    for name, _ in s._fields_:
+        v = getattr(s, name)
+        if isinstance(v, ctypes.Structure):
+            v = _struct_to_dict(v)
+        elif isinstance(v, ctypes.Array):
+            v = list(v)
+        out[name] = v
+    return out
+
+
+def features(row_ptr, col, val, n, stream=None):
+    """GPU feature extraction (validation included) as a dict."""
+    A = make_csr(row_ptr, col, val, n)
+    F = C.spmv_features()
+    C.check(C.lib().spmv_features_compute(ctypes.byref(A), ctypes.byref(F), _stream_handle(stream)),
+            "spmv_features_compute")
+    return _struct_to_dict(F)
+
+
+class Selector:
+    """Learned selector weights uploaded to the device."""
+
+    def __init__(self, params, mean, std):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        mu = np.ascontiguousarray(mean, dtype=np.float32)
+        sd = np.ascontiguousarray(std, dtype=np.float32)
+        h = ctypes.c_void_p()
+        C.check(C.lib().spmv_selector_create(p.ctypes.data_as(ctypes.c_void_p), p.size,
+                                             mu.ctypes.data_as(ctypes.c_void_p),
+                                             sd.ctypes.data_as(ctypes.c_void_p), ctypes.byref(h)),
+                "spmv_selector_create")
+        self.handle = h
+        self.params, self.mean, self.std = p, mu, sd
+
+    @classmethod
+    def load(cls, path):
+        with open(path) as fh:
+            d = json.load(fh)
+        return cls(d["params"], d["mean"], d["std"])
+
+    def score(self, raw, stream=None):
+        """raw: float32 device tensor [rows, 12] -> scores [rows, K_COUNT]."""
+        torch = _torch()
+        raw = raw.to(torch.float32).contiguous()
+        out = torch.empty((raw.shape[0], C.K_COUNT), dtype=torch.float32, device=raw.device)
+        C.check(C.lib().spmv_selector_score(self.handle, _ptr(raw), raw.shape[0], _ptr(out),
+                                            _stream_handle(stream)), "spmv_selector_score")
+        return out
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h and C._lib is not None:
+            C.lib().spmv_selector_destroy(h)
+            self.handle = None
+
+
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights",
+                               "selector_gfx950.json")
+
+
+def default_selector():
+    return Selector.load(DEFAULT_WEIGHTS) if os.path.exists(DEFAULT_WEIGHTS) else None
+
+
+class Plan:
+    """spmv_plan_create / spmv_run over torch device tensors.
+
+    selector: "rules", "mlp", "exhaustive", or a kernel name / index to force.
+    """
+
+    def __init__(self, row_ptr, col, val, n=None, selector="rules", model=None,
+                 tau=None, topk=None, reps=None, disable=(), mem_cap=0, params=None,
+                 stream=None):
+        torch = _torch()
+        m = row_ptr.numel() - 1
+        n = m if n is None else int(n)
+        A = make_csr(row_ptr, col, val, n)
+        o = C.spmv_plan_opts()
+        C.lib().spmv_plan_opts_default(ctypes.byref(o))
+        if isinstance(selector, int) or selector in C.KERNELS:
+            o.selector = C.SELECT_FORCED
+            o.force_kernel = selector if isinstance(selector, int) else C.KERNELS.index(selector)
+        else:
+            o.selector = {"rules": C.SELECT_RULES, "mlp": C.SELECT_MLP,
+                          "exhaustive": C.SELECT_EXHAUSTIVE}[selector]
+        if selector == "mlp":
+            model = model or default_selector()
+            if model is None:
+                raise RuntimeError("selector='mlp' needs a model (no trained weights found)")
+        self._model = model
+        o.model = model.handle if model is not None else None
+        if tau is not None:
+            o.confidence_tau = tau
+        if topk is not None:
+            o.measure_topk = topk
+        if reps is not None:
+            o.timing_reps = reps
+        mask = 0
+        for k in disable:
+            mask |= 1 << (k if isinstance(k, int) else C.KERNELS.index(k))
+        o.disable_mask = mask
+        o.mem_cap_bytes = int(mem_cap)
+        if params:
+            o.use_params = 1
+            for k, v in params.items():
+                setattr(o.params, k, int(v))
+        h = ctypes.c_void_p()
+        st = C.lib().spmv_plan_create(ctypes.byref(A), ctypes.byref(o), _stream_handle(stream),
+                                      ctypes.byref(h))
+        C.check(st, "spmv_plan_create")
+        self.handle = h
+        self.m, self.n, self.nnz = m, n, int(col.numel())
+        self.dtype = val.dtype
+        self.device = val.device
+
+    def run(self, x, y=None, stream=None):
+        torch = _torch()
+        if x.dtype != self.dtype or not x.is_contiguous() or x.numel() != self.n:
+            raise TypeError("x must be a contiguous vector of length n and the matrix dtype")
+        if y is None:
+            y = torch.empty(self.m, dtype=self.dtype, device=self.device)
+        elif y.dtype != self.dtype or not y.is_contiguous() or y.numel() != self.m:
+            raise TypeError("y must be a contiguous vector of length m and the matrix dtype")
+        C.check(C.lib().spmv_run(self.handle, _ptr(x), _ptr(y), _stream_handle(stream)),
+                "spmv_run")
+        return y
+
+    __call__ = run
+
+    def info(self):
+        I = C.spmv_plan_info()
+        C.check(C.lib().spmv_plan_info_get(self.handle, ctypes.byref(I)), "spmv_plan_info_get")
+        d = _struct_to_dict(I)
+        d["kernel_name"] = C.KERNELS[d["kernel"]]
+        d["format_name"] = C.FORMATS[d["format"]]
+        return d
+
+    def roundtrip(self, stream=None):
+        torch = _torch()
+        rp = torch.empty(self.m + 1, dtype=torch.int32, device=self.device)
+        col = torch.empty(max(1, self.nnz), dtype=torch.int32, device=self.device)
+        val = torch.empty(max(1, self.nnz), dtype=self.dtype, device=self.device)
+        C.check(C.lib().spmv_convert_roundtrip(self.handle, _ptr(rp), ctypes.c_void_p(col.data_ptr()),
+                                               ctypes.c_void_p(val.data_ptr()),
+                                               _stream_handle(stream)), "spmv_convert_roundtrip")
+        return rp, col[:self.nnz], val[:self.nnz]
+
+    def export(self, which, stream=None):
+        """Internal array `which` (see spmv_plan_export) as a uint8 device tensor."""
+        torch = _torch()
+        n = ctypes.c_size_t(0)
+        C.check(C.lib().spmv_plan_export(self.handle, which, None, 0, ctypes.byref(n),
+                                         _stream_handle(stream)), "spmv_plan_export(size)")
+        buf = torch.empty(max(1, n.value), dtype=torch.uint8, device=self.device)
+        C.check(C.lib().spmv_plan_export(self.handle, which, ctypes.c_void_p(buf.data_ptr()),
+                                         buf.numel(), None, _stream_handle(stream)),
+                "spmv_plan_export")
+        return buf[:n.value]
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h and C._lib is not None:
+            C.lib().spmv_plan_destroy(h)
+        self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+class Batch:
+    """spmv_batch_*: all levels in one persistent launch (mode 0) or a graph (1)."""
+
+    def __init__(self, plans, mode=0):
+        self.plans = list(plans)
+        arr = (ctypes.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        h = ctypes.c_void_p()
+        C.check(C.lib().spmv_batch_create(arr, len(self.plans), int(mode), ctypes.byref(h)),
+                "spmv_batch_create")
+        self.handle = h
+        self.mode = mode
+
+    def run(self, xs, ys, stream=None):
+        n = len(self.plans)
+        xa = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        ya = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ys])
+        C.check(C.lib().spmv_batch_run(self.handle, xa, ya, _stream_handle(stream)),
+                "spmv_batch_run")
+        return ys
+
+    def close(self):
+        h = getattr(self, "handle", None)
+        if h and C._lib is not None:
+            C.lib().spmv_batch_destroy(h)
+        self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+def stream_copy(dst, src, stream=None):
+    nbytes = src.numel() * src.element_size()
+    C.check(C.lib().spmv_stream_copy(_ptr(dst), _ptr(src), nbytes, _stream_handle(stream)),
+            "spmv_stream_copy")
+    return dst
+
+
+# ---- selector training kernels -------------------------------------------------
+
+def mlp_param_count(n_out=C.K_COUNT):
+    return int(C.lib().spmv_mlp_param_count(n_out))
+
+
+def mlp_forward(params, x, n_out=C.K_COUNT, stream=None):
+    torch = _torch()
+    B = x.shape[0]
+    ws = torch.empty(int(C.lib().spmv_mlp_workspace_floats(B)), dtype=torch.float32, device=x.device)
+    out = torch.empty((B, n_out), dtype=torch.float32, device=x.device)
+    C.check(C.lib().spmv_mlp_forward(_ptr(params), n_out, _ptr(x), B, _ptr(out), _ptr(ws),
+                                     _stream_handle(stream)), "spmv_mlp_forward")
+    return out
+
+
+def mlp_backward(params, x, target, mask, n_out=C.K_COUNT, grad=None, ws=None, loss=None,
+                 stream=None):
+    torch = _torch()
+    B = x.shape[0]
+    if ws is None:
+        ws = torch.empty(int(C.lib().spmv_mlp_workspace_floats(B)), dtype=torch.float32,
+                         device=x.device)
+    if grad is None:
+        grad = torch.empty_like(params)
+    if loss is None:
+        loss = torch.empty(1, dtype=torch.float32, device=x.device)
+    C.check(C.lib().spmv_mlp_backward(_ptr(params), n_out, _ptr(x), _ptr(target), _ptr(mask), B,
+                                      _ptr(grad), _ptr(loss), _ptr(ws), _stream_handle(stream)),
+            "spmv_mlp_backward")
+    return grad, loss
+
+
+def mlp_adam(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    C.check(C.lib().spmv_mlp_adam(_ptr(params), _ptr(grad), _ptr(m), _ptr(v), params.numel(),
+                                  int(step), lr, beta1, beta2, eps, _stream_handle(stream)),
+            "spmv_mlp_adam")

@@ -1,0 +1,98 @@
+"""Multilevel batch (persistent kernel, HIP graph) and selector-network kernels."""
+import numpy as np
+import pytest
+
+from oracle import mlp as OM
+from paper_1210_2536_amd import synth as S
+
+from gpu_util import assert_parity, dev, note, vec
+
+pytestmark = pytest.mark.gpu
+
+
+def _levels():
+    return S.multilevel(32, 5)  # 32^3 .. 2^3
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+@pytest.mark.parametrize("kernel", ["dia", "dia_direct", "ell", "csr_vector", "csr_scalar", "mixed"])
+def test_batch_equals_per_level_runs(kernel, dtype):
+    import torch
+    from paper_1210_2536_amd.spmv import Batch, Plan
+    levels = _levels()
+    kinds = (["dia", "ell", "csr_vector", "coo", "csr_adaptive"] if kernel == "mixed"
+             else [kernel] * len(levels))
+    plans, xs, ys_ref = [], [], []
+    for l, (A, k) in enumerate(zip(levels, kinds)):
+        rp, col, val = dev(A, dtype)
+        p = Plan(rp, col, val, n=A.n, selector=k)
+        plans.append(p)
+        x = S.uniform_vector(A.n, [4, l])
+        xs.append(vec(x, dtype))
+        y = p.run(xs[-1])
+        assert_parity(y.cpu().numpy(), A, x, dtype)
+        ys_ref.append(y.cpu().numpy())
+    for mode in (0, 1):
+        note(f"[batch] kernel={kernel} mode={mode} {np.dtype(dtype).name}")
+        B = Batch(plans, mode=mode)
+        ys = [torch.full((A.m,), float("nan"), dtype=xs[0].dtype, device="cuda") for A in levels]
+        for rep in range(3):   # replays must keep giving the same answer
+            for y in ys:
+                y.fill_(float("nan"))
+            B.run(xs, ys)
+            torch.cuda.synchronize()
+            for y, r in zip(ys, ys_ref):
+                assert np.array_equal(y.cpu().numpy().view(np.uint8), r.view(np.uint8)), (mode, rep)
+
+
+def test_mlp_forward_backward_adam_match_oracle():
+    import torch
+    from paper_1210_2536_amd import spmv as G
+    C = 7
+    rng = np.random.default_rng(60)
+    n_par = OM.n_params(C)
+    assert G.mlp_param_count(C) == n_par
+    flat = rng.normal(0, 0.3, n_par).astype(np.float32)
+    B = 37
+    z = rng.normal(size=(B, 12)).astype(np.float32)
+    t = rng.normal(size=(B, C)).astype(np.float32)
+    mask = (rng.random((B, C)) < 0.8).astype(np.float32)
+    params64 = OM.unflatten(flat.astype(np.float64), C)
+    s_ref, cache = OM.forward(params64, z.astype(np.float64))
+    g_ref = OM.flatten(OM.backward(params64, cache, s_ref, t.astype(np.float64), mask.astype(np.float64)))
+    loss_ref = OM.loss(s_ref, t.astype(np.float64), mask.astype(np.float64))
+    P = torch.from_numpy(flat).cuda()
+    Z = torch.from_numpy(z).cuda()
+    s = G.mlp_forward(P, Z, C).cpu().numpy()
+    np.testing.assert_allclose(s, s_ref, rtol=1e-4, atol=1e-6)
+    g, loss = G.mlp_backward(P, Z, torch.from_numpy(t).cuda(), torch.from_numpy(mask).cuda(), C)
+    np.testing.assert_allclose(g.cpu().numpy(), g_ref, rtol=1e-4, atol=1e-6)
+    assert float(loss.item()) == pytest.approx(loss_ref, rel=1e-5)
+    # one Adam step from zero moments
+    m = torch.zeros_like(P)
+    v = torch.zeros_like(P)
+    G.mlp_adam(P, g, m, v, step=1, lr=1e-3)
+    p_ref, _, _ = OM.adam_step(flat.astype(np.float64), g.cpu().numpy().astype(np.float64),
+                               np.zeros(n_par), np.zeros(n_par), 1, lr=1e-3)
+    np.testing.assert_allclose(P.cpu().numpy(), p_ref, rtol=1e-5, atol=1e-7)
+
+
+def test_selector_inference_matches_training_forward_and_oracle():
+    import torch
+    from paper_1210_2536_amd import spmv as G
+    from oracle import features as OF
+    C = 7
+    rng = np.random.default_rng(61)
+    flat = rng.normal(0, 0.3, OM.n_params(C)).astype(np.float32)
+    mats = [S.stencil_5pt(32), S.zipf_g2(np.random.default_rng([62, 0]), 4000),
+            S.uniform_g1(np.random.default_rng([62, 1]), 3000)]
+    raw = np.stack([OF.mlp_raw_features(OF.extract(A.m, A.n, A.row_ptr, A.col), i % 2 == 0)
+                    for i, A in enumerate(mats)])
+    mean = raw.mean(axis=0).astype(np.float32)
+    std = (raw.std(axis=0) + 1.0).astype(np.float32)
+    sel = G.Selector(flat, mean, std)
+    sc = sel.score(torch.from_numpy(raw.astype(np.float32)).cuda()).cpu().numpy()
+    z = OM.preprocess(raw.astype(np.float32).astype(np.float64), mean.astype(np.float64),
+                      std.astype(np.float64))
+    s_ref, _ = OM.forward(OM.unflatten(flat.astype(np.float64), C), z)
+    np.testing.assert_allclose(sc, s_ref, rtol=1e-4, atol=1e-5)

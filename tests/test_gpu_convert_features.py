@@ -1,0 +1,166 @@
+"""GPU conversions, layouts, features, validation and rule selection vs the oracle."""
+import numpy as np
+import pytest
+
+from oracle import convert as OC
+from oracle import features as OF
+from oracle import rules as OR
+from paper_1210_2536_amd import synth as S
+
+from gpu_util import dev, note
+
+pytestmark = pytest.mark.gpu
+
+
+def _mats():
+    out = [S.stencil_5pt(64), S.stencil_27pt(10), S.stencil_7pt(16)]
+    for g, gen in enumerate((S.band_g0, S.uniform_g1, S.zipf_g2, S.blocks_g3)):
+        for s in range(2):
+            out.append(gen(np.random.default_rng([50, g, s]), 3000 + 4111 * s))
+    rng = np.random.default_rng(51)
+    out.append(S.random_csr(rng, 97, 61, 0.1, explicit_zeros=True))
+    return out
+
+
+def _poisoned(val, dtype):
+    v = val.astype(dtype).copy()
+    if dtype == np.float64 and v.size > 8:
+        b = v.view(np.uint64)
+        v[0] = -0.0
+        v[5] = 0.0
+        b[2] = np.uint64(0x7FF0000000000001)
+        b[3] = np.uint64(0xFFF8DEADBEEF0001)
+    elif v.size > 8:
+        b = v.view(np.uint32)
+        v[0] = -0.0
+        b[2] = np.uint32(0x7FC0BEEF)
+    return v
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_roundtrip_bit_exact_and_layouts(dtype):
+    import torch
+    from paper_1210_2536_amd.spmv import Plan
+    for A in _mats():
+        val = _poisoned(A.val, dtype)
+        B = S.CSR(A.m, A.n, A.row_ptr, A.col, val, A.name)
+        f = OF.extract(A.m, A.n, A.row_ptr, A.col)
+        for k in ("csr_vector", "csr_adaptive", "coo", "ell", "dia", "dia_direct"):
+            if k == "ell" and not f["ell_feasible"]:
+                continue
+            if k.startswith("dia") and not f["dia_feasible"]:
+                continue
+            note(f"[convert] {A.name} {np.dtype(dtype).name} {k}")
+            rp, col, v = dev(B, dtype)
+            p = Plan(rp, col, v, n=A.n, selector=k)
+            rp2, col2, v2 = p.roundtrip()
+            assert np.array_equal(rp2.cpu().numpy(), A.row_ptr.astype(np.int32))
+            assert np.array_equal(col2.cpu().numpy(), A.col)
+            assert np.array_equal(v2.cpu().numpy().view(np.uint8), val.view(np.uint8))
+            info = p.info()
+            m_pad = info["m_pad"]
+            if k == "coo":
+                r, _, _ = OC.csr_to_coo(A.row_ptr, A.col, val)
+                assert np.array_equal(p.export(0).cpu().numpy().view(np.int32), r)
+            if k == "ell":
+                K, ec, ev = OC.csr_to_ell(A.row_ptr, A.col, val, m_pad)
+                assert info["ell_width"] == K
+                assert np.array_equal(p.export(1).cpu().numpy().view(np.int32), ec)
+                assert np.array_equal(p.export(2).cpu().numpy(), ev.view(np.uint8))
+            if k.startswith("dia"):
+                offs, data, words = OC.csr_to_dia(A.m, A.n, A.row_ptr, A.col, val, m_pad)
+                assert np.array_equal(p.export(3).cpu().numpy().view(np.int32), offs)
+                assert np.array_equal(p.export(4).cpu().numpy(), data.view(np.uint8))
+                assert np.array_equal(p.export(5).cpu().numpy().view(np.uint32), words)
+            if k == "csr_adaptive":
+                order = p.export(6).cpu().numpy().view(np.int32)
+                assert np.array_equal(np.sort(order), np.arange(A.m))
+
+
+def test_features_match_oracle():
+    from paper_1210_2536_amd.spmv import features
+    for A in _mats() + [S.zipf_large(n=300_000, kmax=30_000, seed=(52, 0))]:
+        note(f"[features] {A.name}")
+        rp, col, val = dev(A, np.float64)
+        g = features(rp, col, val, A.n)
+        f = OF.extract(A.m, A.n, A.row_ptr, A.col)
+        for gk, fk in (("m", "M"), ("n", "N"), ("nnz", "NNZ"), ("sum_rd", "sum_rd"),
+                       ("sum_rd2", "sum_rd2"), ("max_rd", "max_RD"), ("min_rd", "min_RD"),
+                       ("ndiags", "Ndiags"), ("ntdiags", "NTdiags"), ("bandwidth", "bandwidth"),
+                       ("blocks4", "blocks4"), ("dia_feasible", "dia_feasible"),
+                       ("ell_feasible", "ell_feasible")):
+            assert g[gk] == f[fk], (A.name, gk, g[gk], f[fk])
+        for gk, fk in (("aver_rd", "aver_RD"), ("var_rd", "var_RD"), ("std_rd", "std_RD"),
+                       ("er_dia", "ER_DIA"), ("er_ell", "ER_ELL"),
+                       ("ntdiags_ratio", "NTdiags_ratio"), ("R", "R"),
+                       ("block_fill", "block_fill")):
+            assert g[gk] == pytest.approx(f[fk], rel=1e-12, abs=1e-300), (A.name, gk)
+
+
+def test_rule_selection_matches_oracle():
+    from paper_1210_2536_amd.spmv import Plan
+    mats = _mats() + [S.zipf_large(n=200_000, kmax=20_000, seed=(33, 2))]
+    for A in mats:
+        f = OF.extract(A.m, A.n, A.row_ptr, A.col)
+        want = OR.choose_format(f)
+        rp, col, val = dev(A, np.float64)
+        info = Plan(rp, col, val, n=A.n, selector="rules").info()
+        got = info["format_name"].upper()
+        assert got == want, (A.name, got, want)
+
+
+def _bad_csr_cases():
+    good = S.stencil_5pt(6)
+    cases = []
+    c = good.col.copy(); c[3], c[4] = c[4], c[3]
+    cases.append(("unsorted", good.row_ptr, c))
+    c = good.col.copy(); c[4] = c[3]
+    cases.append(("duplicate", good.row_ptr, c))
+    c = good.col.copy(); c[10] = good.n
+    cases.append(("col_too_big", good.row_ptr, c))
+    c = good.col.copy(); c[0] = -1
+    cases.append(("col_negative", good.row_ptr, c))
+    r = good.row_ptr.copy(); r[5], r[6] = r[6], r[5]
+    cases.append(("row_ptr_decreasing", r, good.col))
+    r = good.row_ptr.copy(); r[0] = 1
+    cases.append(("row_ptr0", r, good.col))
+    return good, cases
+
+
+def test_invalid_csr_is_rejected():
+    import torch
+    from paper_1210_2536_amd import capi as C
+    from paper_1210_2536_amd.spmv import Plan
+    good, cases = _bad_csr_cases()
+    for name, rp, col in cases:
+        B = S.CSR(good.m, good.n, rp, col, good.val, name)
+        r, c, v = dev(B, np.float64)
+        with pytest.raises(C.SpmvError) as ei:
+            Plan(r, c, v, n=good.n)
+        assert ei.value.status == C.SPMV_EINVAL, name
+    # row_ptr[m] != nnz: give one value less
+    r, c, v = dev(good, np.float64)
+    with pytest.raises(C.SpmvError):
+        Plan(r, c[:-1].contiguous(), v[:-1].contiguous(), n=good.n)
+
+
+def test_memory_cap_filters_padded_formats():
+    from paper_1210_2536_amd.spmv import Plan
+    A = S.stencil_27pt(16)
+    rp, col, val = dev(A, np.float64)
+    info = Plan(rp, col, val, n=A.n, selector="rules", mem_cap=1024).info()
+    assert info["format_name"] not in ("dia", "ell")
+    assert not (info["feasible_mask"] >> 4) & 1
+    info = Plan(rp, col, val, n=A.n, selector="rules").info()
+    assert info["format_name"] == "dia"
+
+
+def test_exhaustive_picks_the_fastest_measured():
+    from paper_1210_2536_amd.spmv import Plan
+    A = S.stencil_27pt(40)
+    rp, col, val = dev(A, np.float64)
+    info = Plan(rp, col, val, n=A.n, selector="exhaustive").info()
+    n = info["n_measured"]
+    assert n >= 5
+    times = dict(zip(info["measured_kernel"][:n], info["measured_ms"][:n]))
+    assert info["kernel"] == min(times, key=times.get)

@@ -1,0 +1,194 @@
+"""GPU parity: every kernel of the HIP library against the CPU oracle.
+
+Float64 results must lie within 1e-12 (|A||x|)_i of the oracle, float32 within
+2e-6 (|A||x|)_i; integer stencils on polynomial vectors are exact in any
+summation order, so there the GPU must match the oracle bit for bit.
+"""
+import numpy as np
+import pytest
+
+from oracle import features as OF
+from oracle import spmv as O
+from paper_1210_2536_amd import synth as S
+
+from gpu_util import assert_parity, dev, note, vec
+
+pytestmark = pytest.mark.gpu
+
+KERNELS = ("csr_scalar", "csr_vector", "csr_adaptive", "ell", "dia", "dia_direct", "coo")
+DTYPES = (np.float64, np.float32)
+
+
+def _plan(A, dtype, kernel, **kw):
+    from paper_1210_2536_amd.spmv import Plan
+    rp, col, val = dev(A, dtype)
+    return Plan(rp, col, val, n=A.n, selector=kernel, **kw)
+
+
+def _feasible(A, kernel):
+    f = OF.extract(A.m, A.n, A.row_ptr, A.col)
+    if kernel == "ell":
+        return f["ell_feasible"]
+    if kernel in ("dia", "dia_direct"):
+        return f["dia_feasible"]
+    return True
+
+
+def _run_all(A, dtype, x, kernels=KERNELS, **kw):
+    out = {}
+    for k in kernels:
+        if not _feasible(A, k):
+            continue
+        note(f"[parity] {A.name} {np.dtype(dtype).name} {k} m={A.m} nnz={A.nnz}")
+        p = _plan(A, dtype, k, **kw)
+        assert p.info()["kernel_name"] == k
+        y = p.run(vec(x, dtype)).cpu().numpy()
+        out[k] = y
+    return out
+
+
+def test_c1_laplacian_all_formats():
+    """5-point Laplacian 64x64 (n = 4096, nnz = 20224), float64, x from seed 1."""
+    A = S.stencil_5pt(64)
+    x = S.uniform_vector(A.n, 1)
+    ys = _run_all(A, np.float64, x)
+    assert set(ys) == set(KERNELS)
+    for k, y in ys.items():
+        assert_parity(y, A, x, np.float64)
+    # integer polynomial: exact in any order -> bitwise equal to the oracle
+    g = 64
+    i, j = np.divmod(np.arange(A.n), g)
+    xp = (i * i + j * j).astype(np.float64)
+    ref, _ = O.spmv_accurate(A.row_ptr, A.col, A.val, xp)
+    for dtype in DTYPES:
+        for k, y in _run_all(A, dtype, xp).items():
+            assert np.array_equal(y.astype(np.float64), ref), (k, dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("gen", range(4), ids=S.GEN_NAMES)
+def test_generators_all_kernels(gen, dtype):
+    for s, n in enumerate((1000, 5003, 30011)):
+        rng = np.random.default_rng([40, gen, s])
+        A = (S.band_g0, S.uniform_g1, S.zipf_g2, S.blocks_g3)[gen](rng, n)
+        A.name = f"g{gen}_{A.name}"
+        x = S.uniform_vector(A.n, [41, gen, s])
+        for k, y in _run_all(A, dtype, x).items():
+            assert_parity(y, A, x, dtype)
+
+
+def _edge_matrices():
+    rng = np.random.default_rng(77)
+    mats = []
+    # empty rows at the start, middle and end, explicit zeros, rectangular
+    m, n = 300, 170
+    dense = (rng.random((m, n)) < 0.05) * rng.uniform(-1, 1, (m, n))
+    dense[:7] = 0
+    dense[100:160] = 0
+    dense[-11:] = 0
+    dense[50, :] = rng.uniform(-1, 1, n)         # one dense row
+    r, c = np.nonzero(dense != 0)
+    vals = dense[r, c]
+    vals[::17] = 0.0                             # explicit stored zeros
+    rp = np.zeros(m + 1, np.int64)
+    np.cumsum(np.bincount(r, minlength=m), out=rp[1:])
+    mats.append(S.CSR(m, n, rp, c.astype(np.int32), vals, "edge_rect_empty_rows"))
+    # 1 x 1, one row, one column
+    mats.append(S.CSR(1, 1, np.array([0, 1]), np.array([0], np.int32), np.array([2.5]), "one"))
+    k = 100_000
+    mats.append(S.CSR(1, k, np.array([0, k]), np.arange(k, dtype=np.int32),
+                      rng.uniform(-1, 1, k), "dense_row_1e5"))
+    mats.append(S.CSR(64, 1, np.arange(65), np.zeros(64, np.int32), rng.uniform(-1, 1, 64),
+                      "one_column"))
+    # wide-offset band: DIA windows far apart (offsets +-g^2)
+    mats.append(S.stencil_7pt(20))
+    # a few very long rows among short ones (exercises every adaptive bin)
+    m = 20_000
+    lens = np.ones(m, np.int64)
+    lens[[5, 6000, 19999]] = [15_000, 9_000, 20_000]
+    lens[100:200] = 70
+    lens[300:400] = 3000
+    cols = S._sorted_distinct_cols(np.random.default_rng(5), lens, m)
+    rp = np.zeros(m + 1, np.int64)
+    np.cumsum(lens, out=rp[1:])
+    mats.append(S.CSR(m, m, rp, cols, rng.uniform(-1, 1, cols.size), "mixed_long_rows"))
+    return mats
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_edge_cases(dtype):
+    for A in _edge_matrices():
+        x = S.uniform_vector(A.n, [42, A.m])
+        for k, y in _run_all(A, dtype, x).items():
+            assert_parity(y, A, x, dtype)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_tiny_tiles_force_every_boundary(dtype):
+    """COO chunks of 64 entries, DIA windows of one diagonal, small workgroups."""
+    A = _edge_matrices()[-1]
+    x = S.uniform_vector(A.n, 43)
+    for prm in ({"coo_chunk": 1}, {"coo_chunk": 3}, {"adaptive_wg_min": 64, "adaptive_rows_per_lane": 1},
+                {"vector_lanes": 64}, {"vector_lanes": 1, "block": 64}):
+        for k, y in _run_all(A, dtype, x, kernels=("coo", "csr_adaptive", "csr_vector"),
+                             params=prm).items():
+            assert_parity(y, A, x, dtype)
+    B = S.stencil_27pt(12)
+    xb = S.uniform_vector(B.n, 44)
+    for prm in ({"dia_span": 0}, {"dia_span": 1, "dia_rows_per_thread": 1},
+                {"dia_rows_per_thread": 8}, {"ell_unroll": 1}, {"ell_unroll": 2}):
+        for k, y in _run_all(B, dtype, xb, kernels=("dia", "dia_direct", "ell"), params=prm).items():
+            assert_parity(y, B, xb, dtype)
+
+
+def test_empty_matrices():
+    import torch
+    from paper_1210_2536_amd.spmv import Plan
+    for k in KERNELS:
+        # m = 0
+        rp = torch.zeros(1, dtype=torch.int32, device="cuda")
+        col = torch.zeros(0, dtype=torch.int32, device="cuda")
+        val = torch.zeros(0, dtype=torch.float64, device="cuda")
+        if k in ("ell", "dia", "dia_direct"):
+            continue
+        p = Plan(rp, col, val, n=5, selector=k)
+        p.run(torch.ones(5, dtype=torch.float64, device="cuda"))
+    # nnz = 0, m > 0: y is all zero for every kernel that accepts it
+    for k in KERNELS:
+        rp = torch.zeros(33, dtype=torch.int32, device="cuda")
+        col = torch.zeros(0, dtype=torch.int32, device="cuda")
+        val = torch.zeros(0, dtype=torch.float32, device="cuda")
+        try:
+            p = Plan(rp, col, val, n=7, selector=k)
+        except RuntimeError:
+            assert k in ("ell", "dia", "dia_direct")
+            continue
+        y = p.run(torch.ones(7, dtype=torch.float32, device="cuda"),
+                  torch.full((32,), 9.0, dtype=torch.float32, device="cuda"))
+        assert torch.all(y == 0)
+
+
+def test_determinism_bitwise():
+    A = S.zipf_g2(np.random.default_rng([45, 0]), 50_000)
+    x = S.uniform_vector(A.n, 45)
+    for k in KERNELS:
+        if not _feasible(A, k):
+            continue
+        p = _plan(A, np.float64, k, params={"coo_chunk": 2})
+        xv = vec(x, np.float64)
+        y1 = p.run(xv).cpu().numpy()
+        y2 = p.run(xv).cpu().numpy()
+        assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64)), k
+
+
+def test_run_argument_errors():
+    import torch
+    from paper_1210_2536_amd import capi as C
+    A = S.stencil_5pt(8)
+    p = _plan(A, np.float64, "csr_vector")
+    buf = torch.zeros(2 * A.n, dtype=torch.float64, device="cuda")
+    st = C.lib().spmv_run(p.handle, C.ctypes.c_void_p(buf.data_ptr()),
+                          C.ctypes.c_void_p(buf.data_ptr() + 8 * 10), None)
+    assert st == C.SPMV_EINVAL and b"overlap" in C.lib().spmv_last_error()
+    assert C.lib().spmv_run(None, None, None, None) == C.SPMV_EINVAL
+    assert C.lib().spmv_plan_destroy(None) == C.SPMV_OK
