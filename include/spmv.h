@@ -154,6 +154,8 @@ typedef struct {
     int64_t m_pad;
     uint64_t device_bytes;              /* plan-owned device memory           */
     double t_validate_ms, t_features_ms, t_select_ms, t_convert_ms, t_plan_ms;
+    float mlp_input[12];                /* raw selector inputs of this matrix  */
+    int32_t rules_kernel;               /* what SPMV_SELECT_RULES would pick   */
 } spmv_plan_info;
 
 typedef struct spmv_plan_s *spmv_plan_t;

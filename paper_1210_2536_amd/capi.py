@@ -10,7 +10,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsmat_spmv.so")
+LIB_PATH = os.environ.get("SMAT_SPMV_LIB") or os.path.join(HERE, "libsmat_spmv.so")
 
 SPMV_F32, SPMV_F64 = 0, 1
 SPMV_OK, SPMV_EINVAL, SPMV_ENOMEM, SPMV_EDEVICE, SPMV_EUNSUPPORTED = 0, -1, -2, -3, -4
@@ -59,7 +59,8 @@ class spmv_plan_info(ctypes.Structure):
                 ("feasible_mask", u32), ("features", spmv_features), ("params", spmv_params),
                 ("ell_width", i32), ("dia_ndiags", i32), ("dia_windows", i32), ("m_pad", i64),
                 ("device_bytes", u64), ("t_validate_ms", f64), ("t_features_ms", f64),
-                ("t_select_ms", f64), ("t_convert_ms", f64), ("t_plan_ms", f64)]
+                ("t_select_ms", f64), ("t_convert_ms", f64), ("t_plan_ms", f64),
+                ("mlp_input", f32 * 12), ("rules_kernel", i32)]
 
 
 _SIGS = {

@@ -263,8 +263,8 @@ spmv_status check_params(const spmv_params &p) {
 
 // Longest COO chain: a row spans at most this many chunks in float64.
 constexpr int64_t kCooMaxChunksPerRow = 3000;
-constexpr int64_t kSplitSegment = 512 * 2048;          // entries per split segment
-constexpr int64_t kSplitMin = 512 * 3584;              // rows longer than this are split
+constexpr int64_t kSplitSegment = 512 * 1024;   // entries per split segment (512 threads)
+constexpr int64_t kSplitMin = 256 * 4000;       // longer rows than this are split
 
 // Kernels that can hold this matrix (zero-fill rule, storage cap) and, when
 // `accuracy` is set, also keep every float64 summation chain short enough for
@@ -308,7 +308,7 @@ int rules_choose(const spmv_features &F, uint32_t feas) {
     const int64_t nd = F.ndiags;
     if ((feas & (1u << SPMV_K_DIA)) && nd >= 0 && nd <= 500) {
         if (nd < 25 || 5 * NNZ > (__int128)3 * nd * M || 5 * (__int128)F.ntdiags > 2 * (__int128)nd)
-            return SPMV_K_DIA;
+            return SPMV_K_DIA_DIRECT;  // the faster DIA implementation on gfx950
     }
     if (feas & (1u << SPMV_K_ELL)) {
         const __int128 mx = F.max_rd;
@@ -438,6 +438,19 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
         SMAT_TRY(launch_bin_rows(m, P.rp.as<int32_t>(), spec, blk, V.bin_rows.as<int32_t>(), offs, s));
         SMAT_HIP(hipMemcpyAsync(V.bin_off, offs, sizeof(V.bin_off), hipMemcpyDeviceToHost, s));
         SMAT_HIP(hipStreamSynchronize(s));
+        // one launch over bins 7..0 (longest rows first)
+        {
+            unsigned blocks = 0;
+            for (int q = 0; q < 8; ++q) {
+                int b = 7 - q;
+                V.alaunch.first[q] = blocks;
+                unsigned cnt = V.bin_off[b + 1] - V.bin_off[b];
+                unsigned per = b == 7 ? 1u : (unsigned)(256 >> b);
+                blocks += (cnt + per - 1) / per;
+            }
+            V.alaunch.first[8] = blocks;
+            for (int b = 0; b < 9; ++b) V.alaunch.row_begin[b] = V.bin_off[b];
+        }
         // split rows: segment table on the host from their row_ptr entries
         int64_t ns = V.bin_off[9] - V.bin_off[8];
         if (ns > 0) {
@@ -498,18 +511,8 @@ spmv_status run_variant(const spmv_plan_s &P, const Variant &V, const void *x, v
         return run_csr_vector(elt, V.prm.vector_lanes, m, nullptr, P.rp.as<int32_t>(),
                               P.col.as<int32_t>(), P.val.p, x, y, V.prm.block, s);
     case SPMV_K_CSR_ADAPTIVE: {
-        const int32_t *rows = V.bin_rows.as<int32_t>();
-        for (int b = 0; b < 7; ++b) {
-            int64_t cnt = (int64_t)V.bin_off[b + 1] - V.bin_off[b];
-            if (cnt)
-                SMAT_TRY(run_csr_vector(elt, V.bin_lanes[b], cnt, rows + V.bin_off[b],
-                                        P.rp.as<int32_t>(), P.col.as<int32_t>(), P.val.p, x, y,
-                                        V.prm.block, s));
-        }
-        int64_t cnt = (int64_t)V.bin_off[8] - V.bin_off[7];
-        if (cnt)
-            SMAT_TRY(run_csr_rowblock(elt, cnt, rows + V.bin_off[7], P.rp.as<int32_t>(),
-                                      P.col.as<int32_t>(), P.val.p, x, y, s));
+        SMAT_TRY(run_csr_adaptive(elt, V.alaunch, V.bin_rows.as<int32_t>(), P.rp.as<int32_t>(),
+                                  P.col.as<int32_t>(), P.val.p, x, y, s));
         if (V.nsplit_rows)
             SMAT_TRY(run_csr_split(elt, V.nsplit_segs, V.split_segs.as<int64_t>(),
                                    V.split_partials.as<double>(), V.nsplit_rows,
@@ -714,6 +717,8 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
     }
     uint32_t feas = feasible_mask(F, A->dtype, P->m_pad, cap, prm_base) & ~opts.disable_mask;
     I.feasible_mask = feas;
+    raw_features(F, A->dtype, I.mlp_input);
+    I.rules_kernel = rules_choose(F, feas);
 
     // ---- selection
     std::vector<int> cands;

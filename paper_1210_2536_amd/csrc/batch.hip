@@ -107,11 +107,25 @@ __global__ __launch_bounds__(kPBlock) void k_batch_persistent(const LevelDesc *_
     }
 }
 
-template <typename T>
-__global__ void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__ dst, int64_t n) {
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x)
-        dst[i] = src[i];
+// Grid-stride copy of 16-byte words, four independent words per thread and
+// trip (all loads issued before the stores), streaming cache policy.
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void k_stream_copy(const v4u *__restrict__ src,
+                                                     v4u *__restrict__ dst, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        v4u a = __builtin_nontemporal_load(src + i);
+        v4u b = __builtin_nontemporal_load(src + i + stride);
+        v4u c = __builtin_nontemporal_load(src + i + 2 * stride);
+        v4u d = __builtin_nontemporal_load(src + i + 3 * stride);
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + stride);
+        __builtin_nontemporal_store(c, dst + i + 2 * stride);
+        __builtin_nontemporal_store(d, dst + i + 3 * stride);
+    }
+    for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 }  // namespace
@@ -119,8 +133,11 @@ __global__ void k_stream_copy(const uint4 *__restrict__ src, uint4 *__restrict__
 spmv_status run_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
     int64_t n = (int64_t)(bytes / 16);
     if (n == 0) return SPMV_OK;
-    int64_t g = std::min<int64_t>((n + 255) / 256, 256 * 64);
-    k_stream_copy<int><<<(unsigned)g, 256, 0, s>>>((const uint4 *)src, (uint4 *)dst, n);
+    int dev = 0, cus = 256;
+    SMAT_HIP(hipGetDevice(&dev));
+    SMAT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    int64_t g = std::min<int64_t>((n + 1023) / 1024, (int64_t)cus * 8);
+    k_stream_copy<<<(unsigned)g, 256, 0, s>>>((const v4u *)src, (v4u *)dst, n);
     SMAT_LAUNCHED("stream_copy");
     return SPMV_OK;
 }

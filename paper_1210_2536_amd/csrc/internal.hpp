@@ -109,9 +109,17 @@ spmv_status run_csr_scalar(int elt, int64_t m, const int32_t *rp, const int32_t 
 spmv_status run_csr_vector(int elt, int lanes, int64_t nrows, const int32_t *rows,
                            const int32_t *rp, const int32_t *col, const void *val, const void *x,
                            void *y, int block, hipStream_t s);
-spmv_status run_csr_rowblock(int elt, int64_t nrows, const int32_t *rows, const int32_t *rp,
-                             const int32_t *col, const void *val, const void *x, void *y,
-                             hipStream_t s);
+// One launch over all length bins.  Launch position q (q = 0..7) serves bin
+// 7 - q; first[q] is its first workgroup, first[8] the grid size.  Bin b holds
+// rows[row_begin[b] .. row_begin[b+1]); bin 7 gives a 256-thread workgroup to
+// each row, bins 6..0 give 64..1 lanes (256 / L rows per workgroup).
+struct AdaptiveLaunch {
+    unsigned first[9];
+    unsigned row_begin[9];
+};
+spmv_status run_csr_adaptive(int elt, const AdaptiveLaunch &a, const int32_t *rows,
+                             const int32_t *rp, const int32_t *col, const void *val,
+                             const void *x, void *y, hipStream_t s);
 // split rows: segments (row, begin, end) reduce into partials, then fix-up
 spmv_status run_csr_split(int elt, int64_t nseg, const int64_t *segs, double *partials,
                           int64_t nrows, const int64_t *row_seg_begin, const int32_t *rows,

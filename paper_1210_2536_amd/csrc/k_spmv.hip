@@ -56,31 +56,58 @@ __global__ __launch_bounds__(256) void k_csr_vector(int64_t nrows, const int32_t
     if (lane == 0) y[row] = (T)acc;
 }
 
-// ---------------------------------------------------------------- long rows
-// One workgroup per row for rows too long for one wavefront.
-constexpr int kRowBlock = 512;
+// ---------------------------------------------------------------- CSR adaptive
+// Rows binned by length, all bins in one launch.  Workgroups are handed out
+// longest bin first: launch position q serves bin 7 - q, where bin 7 gives a
+// whole 256-thread workgroup to each row and bins 6..0 give 64..1 lanes.
+constexpr int kRowBlock = 512;     // split-row segments
+constexpr int kAdaptBlock = 256;
+
+template <typename T, int L>
+__device__ __forceinline__ void adaptive_lanes(unsigned local, unsigned rbeg, unsigned rend,
+                                               const int32_t *__restrict__ rows,
+                                               const int32_t *__restrict__ rp,
+                                               const int32_t *__restrict__ col,
+                                               const T *__restrict__ val, const T *__restrict__ x,
+                                               T *__restrict__ y) {
+    int64_t r = (int64_t)rbeg + (int64_t)local * (kAdaptBlock / L) + threadIdx.x / L;
+    int lane = threadIdx.x & (L - 1);
+    if (r < rend) {
+        int64_t row = rows[r];
+        double acc = csr_row_lanes<T, L>(row, lane, rp, col, val, x);
+        if (lane == 0) y[row] = (T)acc;
+    }
+}
 
 template <typename T>
-__global__ __launch_bounds__(kRowBlock) void k_csr_rowblock(const int32_t *__restrict__ rows,
-                                                            const int32_t *__restrict__ rp,
-                                                            const int32_t *__restrict__ col,
-                                                            const T *__restrict__ val,
-                                                            const T *__restrict__ x,
-                                                            T *__restrict__ y) {
-    __shared__ double part[kRowBlock / kWave];
-    int64_t row = rows[blockIdx.x];
-    int32_t b = rp[row], e = rp[row + 1];
-    double acc = 0.0;
-#pragma unroll 4
-    for (int32_t p = b + threadIdx.x; p < e; p += kRowBlock)
-        acc = fma((double)val[p], (double)x[col[p]], acc);
-    for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
-    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int w = 0; w < kRowBlock / kWave; ++w) s += part[w];
-        y[row] = (T)s;
+__global__ __launch_bounds__(kAdaptBlock) void k_csr_adaptive(AdaptiveLaunch a,
+                                                              const int32_t *__restrict__ rows,
+                                                              const int32_t *__restrict__ rp,
+                                                              const int32_t *__restrict__ col,
+                                                              const T *__restrict__ val,
+                                                              const T *__restrict__ x,
+                                                              T *__restrict__ y) {
+    __shared__ double part[kAdaptBlock / kWave];
+    const unsigned bid = blockIdx.x;
+    int q = 0;
+    while (q < 7 && bid >= a.first[q + 1]) ++q;
+    const int b = 7 - q;
+    const unsigned local = bid - a.first[q];
+    const unsigned rb = a.row_begin[b], re = a.row_begin[b + 1];
+    switch (b) {
+    case 7: {
+        int64_t row = rows[rb + local];
+        double s = csr_row_block<T, kAdaptBlock>(row, rp, col, val, x, part);
+        if (threadIdx.x == 0) y[row] = (T)s;
+        break;
+    }
+    case 6: adaptive_lanes<T, 64>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 5: adaptive_lanes<T, 32>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 4: adaptive_lanes<T, 16>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 3: adaptive_lanes<T, 8>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 2: adaptive_lanes<T, 4>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 1: adaptive_lanes<T, 2>(local, rb, re, rows, rp, col, val, x, y); break;
+    default: adaptive_lanes<T, 1>(local, rb, re, rows, rp, col, val, x, y); break;
     }
 }
 
@@ -97,7 +124,7 @@ __global__ __launch_bounds__(kRowBlock) void k_csr_segment(const int64_t *__rest
     double acc = 0.0;
 #pragma unroll 4
     for (int64_t p = b + threadIdx.x; p < e; p += kRowBlock)
-        acc = fma((double)val[p], (double)x[col[p]], acc);
+        acc = fma((double)ld_stream(val + p), (double)x[ld_stream(col + p)], acc);
     for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
     __syncthreads();
@@ -216,8 +243,8 @@ __global__ __launch_bounds__(256) void k_coo(int64_t m, int64_t nnz, int E,
     for (int64_t it = c0; it < c1; it += kWave) {
         const int64_t p = it + lane;
         const bool valid = p < c1;
-        const int r = valid ? ri[p] : INT_MAX;
-        double v = valid ? fma((double)val[p], (double)x[col[p]], 0.0) : 0.0;
+        const int r = valid ? ld_stream(ri + p) : INT_MAX;
+        double v = valid ? fma((double)ld_stream(val + p), (double)x[ld_stream(col + p)], 0.0) : 0.0;
         // rows skipped between consecutive entries have no entries: zero them
         int rb = __shfl_up(r, 1, kWave);
         if (lane == 0) rb = before;
@@ -388,17 +415,18 @@ spmv_status run_csr_vector(int elt, int lanes, int64_t nrows, const int32_t *row
                                                    (double *)y, block, s));
 }
 
-spmv_status run_csr_rowblock(int elt, int64_t nrows, const int32_t *rows, const int32_t *rp,
-                             const int32_t *col, const void *val, const void *x, void *y,
-                             hipStream_t s) {
-    if (nrows == 0) return SPMV_OK;
+spmv_status run_csr_adaptive(int elt, const AdaptiveLaunch &a, const int32_t *rows,
+                             const int32_t *rp, const int32_t *col, const void *val,
+                             const void *x, void *y, hipStream_t s) {
+    const unsigned nblk = a.first[8];
+    if (nblk == 0) return SPMV_OK;
     if (elt == 8)
-        k_csr_rowblock<double><<<(unsigned)nrows, kRowBlock, 0, s>>>(
-            rows, rp, col, (const double *)val, (const double *)x, (double *)y);
+        k_csr_adaptive<double><<<nblk, kAdaptBlock, 0, s>>>(
+            a, rows, rp, col, (const double *)val, (const double *)x, (double *)y);
     else
-        k_csr_rowblock<float><<<(unsigned)nrows, kRowBlock, 0, s>>>(
-            rows, rp, col, (const float *)val, (const float *)x, (float *)y);
-    SMAT_LAUNCHED("csr_rowblock");
+        k_csr_adaptive<float><<<nblk, kAdaptBlock, 0, s>>>(
+            a, rows, rp, col, (const float *)val, (const float *)x, (float *)y);
+    SMAT_LAUNCHED("csr_adaptive");
     return SPMV_OK;
 }
 

@@ -53,6 +53,7 @@ struct Variant {
     Dev bin_rows, bin_scratch, split_segs, split_partials, split_begin, split_rows;
     unsigned bin_off[kAdaptiveBins + 1] = {};
     int bin_lanes[kAdaptiveBins] = {};
+    AdaptiveLaunch alaunch{};
     int64_t nsplit_rows = 0, nsplit_segs = 0;
     uint64_t bytes() const {
         return row_idx.bytes + coo_head.bytes + coo_tail.bytes + coo_flags.bytes + ecol.bytes +

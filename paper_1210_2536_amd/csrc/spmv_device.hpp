@@ -5,7 +5,22 @@
 
 #include "internal.hpp"
 
+// Matrix arrays are read once per SpMV: load them non-temporally so that they
+// do not push the reused x vector out of L2.
+#ifndef SMAT_STREAM_NT
+#define SMAT_STREAM_NT 1
+#endif
+
 namespace smat {
+
+template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p) {
+#if SMAT_STREAM_NT
+    return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
+}
 
 // Plain CSR row: one thread, storage order.
 template <typename T>
@@ -29,11 +44,41 @@ __device__ __forceinline__ double csr_row_lanes(int64_t row, int lane,
                                                 const T *__restrict__ x) {
     int32_t b = rp[row], e = rp[row + 1];
     double acc = 0.0;
+    if (L == kWave) {
+        // a full wavefront consumes whole cache lines per trip: stream them
 #pragma unroll 4
-    for (int32_t p = b + lane; p < e; p += L) acc = fma((double)val[p], (double)x[col[p]], acc);
+        for (int32_t p = b + lane; p < e; p += L)
+            acc = fma((double)ld_stream(val + p), (double)x[ld_stream(col + p)], acc);
+    } else {
+        // narrower groups come back to the same lines on later trips
+#pragma unroll 4
+        for (int32_t p = b + lane; p < e; p += L) acc = fma((double)val[p], (double)x[col[p]], acc);
+    }
 #pragma unroll
     for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, L);
     return acc;
+}
+
+// CSR row by a whole workgroup of B threads (B a multiple of 64); thread 0
+// returns the row sum.  `part` is LDS scratch of B / 64 doubles.
+template <typename T, int B>
+__device__ __forceinline__ double csr_row_block(int64_t row, const int32_t *__restrict__ rp,
+                                                const int32_t *__restrict__ col,
+                                                const T *__restrict__ val,
+                                                const T *__restrict__ x, double *part) {
+    int32_t b = rp[row], e = rp[row + 1];
+    double acc = 0.0;
+#pragma unroll 4
+    for (int32_t p = b + threadIdx.x; p < e; p += B)
+        acc = fma((double)ld_stream(val + p), (double)x[ld_stream(col + p)], acc);
+    for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < B / kWave; ++w) s += part[w];
+    __syncthreads();
+    return s;
 }
 
 // ELL row: slots in order, U slots loaded ahead of use.
@@ -49,8 +94,8 @@ __device__ __forceinline__ double ell_row(int64_t i, int64_t m_pad, int K,
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             int64_t s = (int64_t)(k + u) * m_pad + i;
-            c[u] = ecol[s];
-            v[u] = eval[s];
+            c[u] = ld_stream(ecol + s);
+            v[u] = ld_stream(eval + s);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -58,8 +103,8 @@ __device__ __forceinline__ double ell_row(int64_t i, int64_t m_pad, int K,
     }
     for (; k < K; ++k) {
         int64_t s = (int64_t)k * m_pad + i;
-        int32_t c = ecol[s];
-        if (c >= 0) acc = fma((double)eval[s], (double)x[c], acc);
+        int32_t c = ld_stream(ecol + s);
+        if (c >= 0) acc = fma((double)ld_stream(eval + s), (double)x[c], acc);
     }
     return acc;
 }
@@ -92,7 +137,8 @@ __device__ __forceinline__ void dia_tile_lds(int64_t r0, int64_t m, int64_t n, i
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
                 int il = threadIdx.x + q * blockDim.x;
-                if (r0 + il < m) acc[q] = fma((double)dd[il], (double)xs[il + sh], acc[q]);
+                if (r0 + il < m)
+                    acc[q] = fma((double)ld_stream(dd + il), (double)xs[il + sh], acc[q]);
             }
         }
     }
@@ -112,14 +158,40 @@ __device__ __forceinline__ void dia_tile_direct(int64_t r0, int64_t m, int64_t n
     double acc[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
-    for (int d = 0; d < D; ++d) {
+    int d = 0;
+    // two diagonals per trip: all their loads are issued before the FMAs
+    for (; d + 2 <= D; d += 2) {
+        const int64_t off0 = offs[d], off1 = offs[d + 1];
+        const T *d0 = data + (int64_t)d * m_pad;
+        const T *d1 = d0 + m_pad;
+        T v0[RPT], v1[RPT], x0[RPT], x1[RPT];
+        bool k0[RPT], k1[RPT];
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            int64_t i = r0 + threadIdx.x + q * blockDim.x;
+            int64_t j0 = i + off0, j1 = i + off1;
+            k0[q] = i < m && j0 >= 0 && j0 < n;
+            k1[q] = i < m && j1 >= 0 && j1 < n;
+            v0[q] = k0[q] ? ld_stream(d0 + i) : T(0);
+            x0[q] = k0[q] ? x[j0] : T(0);
+            v1[q] = k1[q] ? ld_stream(d1 + i) : T(0);
+            x1[q] = k1[q] ? x[j1] : T(0);
+        }
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            if (k0[q]) acc[q] = fma((double)v0[q], (double)x0[q], acc[q]);
+            if (k1[q]) acc[q] = fma((double)v1[q], (double)x1[q], acc[q]);
+        }
+    }
+    for (; d < D; ++d) {
         const int64_t off = offs[d];
         const T *dd = data + (int64_t)d * m_pad;
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             int64_t i = r0 + threadIdx.x + q * blockDim.x;
             int64_t j = i + off;
-            if (i < m && j >= 0 && j < n) acc[q] = fma((double)dd[i], (double)x[j], acc[q]);
+            if (i < m && j >= 0 && j < n)
+                acc[q] = fma((double)ld_stream(dd + i), (double)x[j], acc[q]);
         }
     }
 #pragma unroll

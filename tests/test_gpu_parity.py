@@ -112,6 +112,12 @@ def _edge_matrices():
     rp = np.zeros(m + 1, np.int64)
     np.cumsum(lens, out=rp[1:])
     mats.append(S.CSR(m, m, rp, cols, rng.uniform(-1, 1, cols.size), "mixed_long_rows"))
+    # a row longer than one workgroup may sum alone: split into segments
+    k, n = 1_100_000, 1_200_000
+    lens = np.array([k, 10, 0, 3])
+    cols = S._sorted_distinct_cols(np.random.default_rng(6), lens, n)
+    rp = np.concatenate([[0], np.cumsum(lens)])
+    mats.append(S.CSR(4, n, rp, cols, rng.uniform(-1, 1, cols.size), "split_row"))
     return mats
 
 
@@ -126,7 +132,7 @@ def test_edge_cases(dtype):
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
 def test_tiny_tiles_force_every_boundary(dtype):
     """COO chunks of 64 entries, DIA windows of one diagonal, small workgroups."""
-    A = _edge_matrices()[-1]
+    A = _edge_matrices()[-2]
     x = S.uniform_vector(A.n, 43)
     for prm in ({"coo_chunk": 1}, {"coo_chunk": 3}, {"adaptive_wg_min": 64, "adaptive_rows_per_lane": 1},
                 {"vector_lanes": 64}, {"vector_lanes": 1, "block": 64}):
