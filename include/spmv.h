@@ -102,6 +102,9 @@ typedef struct {
     int32_t dia_span;           /* DIA: max offset span staged per LDS window */
     int32_t coo_chunk;          /* COO: entries per lane per wavefront chunk  */
     int32_t ell_unroll;         /* ELL: slots fetched per loop trip (1, 2, 4) */
+    int32_t stream_nt;          /* matrix arrays loaded non-temporally: 1 on,
+                                   2 off (0 = default: on when the matrix is
+                                   DIA-feasible, i.e. banded)                */
 } spmv_params;
 
 typedef struct spmv_selector_s *spmv_selector_t;
@@ -252,6 +255,12 @@ spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplans, int32_t 
                               spmv_batch_t *out);
 spmv_status spmv_batch_run(spmv_batch_t batch, const void *const *xs_dev, void *const *ys_dev,
                            void *stream);
+/* Autotune the persistent launch: time grids of 1, 2, 4, 8 and 16 workgroups
+ * per compute unit on the given vectors (outputs are overwritten) and keep
+ * the fastest; *grid_out (if not NULL) receives the chosen grid.  No-op for
+ * graph mode.  Synchronises `stream`. */
+spmv_status spmv_batch_tune(spmv_batch_t batch, const void *const *xs_dev, void *const *ys_dev,
+                            int32_t reps, void *stream, int32_t *grid_out);
 spmv_status spmv_batch_destroy(spmv_batch_t batch);
 
 /* Achievable-bandwidth probe: dst_dev[i] = src_dev[i] for `bytes` bytes

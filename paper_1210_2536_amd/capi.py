@@ -33,7 +33,7 @@ class spmv_csr(ctypes.Structure):
 class spmv_params(ctypes.Structure):
     _fields_ = [("block", i32), ("vector_lanes", i32), ("adaptive_rows_per_lane", i32),
                 ("adaptive_wg_min", i32), ("dia_rows_per_thread", i32), ("dia_span", i32),
-                ("coo_chunk", i32), ("ell_unroll", i32)]
+                ("coo_chunk", i32), ("ell_unroll", i32), ("stream_nt", i32)]
 
 
 class spmv_plan_opts(ctypes.Structure):
@@ -83,6 +83,7 @@ _SIGS = {
     "spmv_batch_create": (i32, [vp, i32, i32, vp]),
     "spmv_batch_run": (i32, [vp, vp, vp, vp]),
     "spmv_batch_destroy": (i32, [vp]),
+    "spmv_batch_tune": (i32, [vp, vp, vp, i32, vp, vp]),
     "spmv_stream_copy": (i32, [vp, vp, ctypes.c_size_t, vp]),
     "spmv_status_string": (ctypes.c_char_p, [i32]),
     "spmv_last_error": (ctypes.c_char_p, []),

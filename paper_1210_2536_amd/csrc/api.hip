@@ -214,6 +214,10 @@ spmv_params default_params(int kernel, const spmv_features &F) {
     p.dia_span = 64;
     p.coo_chunk = 8;
     p.ell_unroll = 4;
+    // streaming loads pay off when x is reused through the cache (banded
+    // matrices); random gathers from a large x do better with the default
+    // policy (measured on gfx950)
+    p.stream_nt = F.dia_feasible ? 1 : 2;
     (void)kernel;
     return p;
 }
@@ -227,6 +231,7 @@ void merge_params(spmv_params &p, const spmv_params &u) {
     if (u.dia_span > 0) p.dia_span = u.dia_span;
     if (u.coo_chunk > 0) p.coo_chunk = u.coo_chunk;
     if (u.ell_unroll > 0) p.ell_unroll = u.ell_unroll;
+    if (u.stream_nt > 0) p.stream_nt = u.stream_nt;
 }
 
 spmv_status check_params(const spmv_params &p) {
@@ -256,6 +261,10 @@ spmv_status check_params(const spmv_params &p) {
     }
     if (!(p.ell_unroll == 1 || p.ell_unroll == 2 || p.ell_unroll == 4)) {
         set_error("params.ell_unroll must be 1, 2 or 4");
+        return SPMV_EINVAL;
+    }
+    if (p.stream_nt != 1 && p.stream_nt != 2) {
+        set_error("params.stream_nt must be 1 (on) or 2 (off)");
         return SPMV_EINVAL;
     }
     return SPMV_OK;
@@ -502,17 +511,18 @@ spmv_status run_variant(const spmv_plan_s &P, const Variant &V, const void *x, v
                         hipStream_t s) {
     const int elt = P.elt;
     const int64_t m = P.m;
+    const bool nt = V.prm.stream_nt == 1;
     if (m == 0) return SPMV_OK;
     switch (V.kernel) {
     case SPMV_K_CSR_SCALAR:
         return run_csr_scalar(elt, m, P.rp.as<int32_t>(), P.col.as<int32_t>(), P.val.p, x, y,
                               V.prm.block, s);
     case SPMV_K_CSR_VECTOR:
-        return run_csr_vector(elt, V.prm.vector_lanes, m, nullptr, P.rp.as<int32_t>(),
+        return run_csr_vector(elt, nt, V.prm.vector_lanes, m, P.rp.as<int32_t>(),
                               P.col.as<int32_t>(), P.val.p, x, y, V.prm.block, s);
     case SPMV_K_CSR_ADAPTIVE: {
-        SMAT_TRY(run_csr_adaptive(elt, V.alaunch, V.bin_rows.as<int32_t>(), P.rp.as<int32_t>(),
-                                  P.col.as<int32_t>(), P.val.p, x, y, s));
+        SMAT_TRY(run_csr_adaptive(elt, nt, V.alaunch, V.bin_rows.as<int32_t>(),
+                                  P.rp.as<int32_t>(), P.col.as<int32_t>(), P.val.p, x, y, s));
         if (V.nsplit_rows)
             SMAT_TRY(run_csr_split(elt, V.nsplit_segs, V.split_segs.as<int64_t>(),
                                    V.split_partials.as<double>(), V.nsplit_rows,
@@ -521,16 +531,17 @@ spmv_status run_variant(const spmv_plan_s &P, const Variant &V, const void *x, v
         return SPMV_OK;
     }
     case SPMV_K_ELL:
-        return run_ell(elt, m, P.m_pad, V.K, V.ecol.as<int32_t>(), V.eval.p, x, y, V.prm.block,
-                       V.prm.ell_unroll, s);
+        return run_ell(elt, nt, m, P.m_pad, V.K, V.ecol.as<int32_t>(), V.eval.p, x, y,
+                       V.prm.block, V.prm.ell_unroll, s);
     case SPMV_K_DIA:
     case SPMV_K_DIA_DIRECT:
-        return run_dia(elt, V.kernel == SPMV_K_DIA, m, P.n, P.m_pad, V.D, V.dia_off.as<int32_t>(),
-                       nullptr, V.nwin, V.dia_win.as<DiaWindow>(), V.max_span, V.dia_data.p, x, y,
-                       std::min(V.prm.block, 256), V.prm.dia_rows_per_thread, s);
+        return run_dia(elt, nt, V.kernel == SPMV_K_DIA, m, P.n, P.m_pad, V.D,
+                       V.dia_off.as<int32_t>(), V.nwin, V.dia_win.as<DiaWindow>(), V.max_span,
+                       V.dia_data.p, x, y, std::min(V.prm.block, 256), V.prm.dia_rows_per_thread,
+                       s);
     case SPMV_K_COO:
-        return run_coo(elt, m, P.nnz, V.row_idx.as<int32_t>(), P.col.as<int32_t>(), P.val.p, x, y,
-                       V.prm.coo_chunk, V.coo_head.as<double>(), V.coo_tail.as<double>(),
+        return run_coo(elt, nt, m, P.nnz, V.row_idx.as<int32_t>(), P.col.as<int32_t>(), P.val.p,
+                       x, y, V.prm.coo_chunk, V.coo_head.as<double>(), V.coo_tail.as<double>(),
                        V.coo_flags.as<uint32_t>(), s);
     default:
         set_error("plan holds no kernel");
@@ -563,6 +574,125 @@ spmv_status time_variant(const spmv_plan_s &P, const Variant &V, const void *x, 
     if (st != SPMV_OK) return st;
     std::sort(t.begin(), t.end());
     *ms = t.empty() ? 0.0 : t[t.size() / 2];
+    return SPMV_OK;
+}
+
+// Parameter points tried by the autotuner for one kernel (the paper's offline
+// "kernel search", Section 3, done per matrix): at most a dozen, around the
+// defaults.
+std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_features &F,
+                                   int dtype) {
+    std::vector<spmv_params> g;
+    auto add = [&](spmv_params p) {
+        if (check_params(p) == SPMV_OK) g.push_back(p);
+    };
+    const int nts[2] = {1, 2};
+    switch (kernel) {
+    case SPMV_K_CSR_SCALAR:
+        for (int bs : {64, 128, 256, 512}) {
+            spmv_params p = b;
+            p.block = bs;
+            add(p);
+        }
+        break;
+    case SPMV_K_CSR_VECTOR:
+        for (int f : {-2, -1, 0, 1, 2})
+            for (int nt : nts) {
+                spmv_params p = b;
+                int L = f >= 0 ? b.vector_lanes << f : b.vector_lanes >> -f;
+                if (L < 1 || L > 64) continue;
+                if (dtype == SPMV_F64 && (F.max_rd + L - 1) / L + ilog2(L) > kFp64MaxDepth)
+                    continue;
+                p.vector_lanes = L;
+                p.stream_nt = nt;
+                add(p);
+            }
+        break;
+    case SPMV_K_CSR_ADAPTIVE:
+        for (int rpl : {1, 2, 4})
+            for (int nt : nts) {
+                spmv_params p = b;
+                p.adaptive_rows_per_lane = rpl;
+                p.stream_nt = nt;
+                add(p);
+            }
+        break;
+    case SPMV_K_ELL:
+        for (int u : {2, 4})
+            for (int bs : {256, 512})
+                for (int nt : nts) {
+                    spmv_params p = b;
+                    p.ell_unroll = u;
+                    p.block = bs;
+                    p.stream_nt = nt;
+                    add(p);
+                }
+        break;
+    case SPMV_K_DIA_DIRECT:
+        for (int r : {1, 2, 4, 8})
+            for (int nt : nts) {
+                spmv_params p = b;
+                p.dia_rows_per_thread = r;
+                p.stream_nt = nt;
+                add(p);
+            }
+        break;
+    case SPMV_K_DIA:
+        for (int r : {2, 4, 8})
+            for (int sp : {32, 256})
+                for (int nt : nts) {
+                    spmv_params p = b;
+                    p.dia_rows_per_thread = r;
+                    p.dia_span = sp;
+                    p.stream_nt = nt;
+                    add(p);
+                }
+        break;
+    case SPMV_K_COO:
+        for (int c : {2, 4, 8, 16})
+            for (int nt : nts) {
+                spmv_params p = b;
+                p.coo_chunk = c;
+                p.stream_nt = nt;
+                if (dtype == SPMV_F64 && F.max_rd > kCooMaxChunksPerRow * (int64_t)c * kWave)
+                    continue;
+                add(p);
+            }
+        break;
+    default:
+        break;
+    }
+    return g;
+}
+
+bool same_params(const spmv_params &a, const spmv_params &b) {
+    return std::memcmp(&a, &b, sizeof(a)) == 0;
+}
+
+// Time the grid for the chosen kernel and keep the fastest variant.
+spmv_status autotune_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W, int reps,
+                             hipStream_t s, std::unique_ptr<Variant> &best) {
+    Dev xs, ys;
+    SMAT_TRY(xs.alloc((size_t)P.elt * std::max<int64_t>(1, P.n)));
+    SMAT_TRY(ys.alloc((size_t)P.elt * std::max<int64_t>(1, P.m)));
+    if (P.n) k_fill_one<<<(unsigned)((P.n + 255) / 256), 256, 0, s>>>(P.n, P.elt, xs.p);
+    SMAT_LAUNCHED("fill_one");
+    double best_ms = 0;
+    SMAT_TRY(time_variant(P, *best, xs.p, ys.p, reps, s, &best_ms));
+    const int kernel = best->kernel;
+    for (const spmv_params &p : tune_grid(kernel, best->prm, F, P.dtype)) {
+        if (same_params(p, best->prm)) continue;
+        auto V = std::make_unique<Variant>();
+        spmv_status st = build_variant(P, F, W, kernel, p, s, *V);
+        if (st == SPMV_ENOMEM) continue;
+        if (st != SPMV_OK) return st;
+        double ms = 0;
+        SMAT_TRY(time_variant(P, *V, xs.p, ys.p, reps, s, &ms));
+        if (ms < best_ms) {
+            best_ms = ms;
+            best = std::move(V);
+        }
+    }
     return SPMV_OK;
 }
 
@@ -821,6 +951,8 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
             return st;
         }
     }
+    if (opts.autotune && !opts.use_params)
+        SMAT_TRY(autotune_variant(*P, F, W, opts.timing_reps, s, P->var));
     SMAT_HIP(hipStreamSynchronize(s));
     W.diag_hist.release();
     if (!needs_csr(chosen)) {

@@ -23,7 +23,7 @@ constexpr int kPDiaRpt = 4;    // rows per thread of a DIA tile
 enum LevelKind { LK_SCALAR = 0, LK_VECTOR = 1, LK_ELL = 3, LK_DIA = 4, LK_DIA_DIRECT = 5 };
 
 struct LevelDesc {
-    int kind, lanes, K, D, nwin, pad;
+    int kind, lanes, K, D, nwin, nt;
     int64_t m, n, m_pad, tile_rows, tile_begin;
     const int32_t *rp, *col, *ecol, *offs;
     const void *val, *eval, *data;
@@ -35,13 +35,51 @@ struct Ptrs {
     void *y[kMaxLevels];
 };
 
-template <typename T, int L>
+template <typename T, int L, bool NT>
 __device__ __forceinline__ void vector_tile(const LevelDesc &d, int64_t tile, const T *x, T *y) {
     int64_t row = tile * (kPBlock / L) + threadIdx.x / L;
     int lane = threadIdx.x & (L - 1);
     if (row < d.m) {
-        double acc = csr_row_lanes<T, L>(row, lane, d.rp, d.col, (const T *)d.val, x);
+        double acc = csr_row_lanes<T, L, NT>(row, lane, d.rp, d.col, (const T *)d.val, x);
         if (lane == 0) y[row] = (T)acc;
+    }
+}
+
+// One (level, tile) work item; the same device functions as the stand-alone
+// kernels, so each row is computed exactly as by the level's own run.
+template <typename T, bool NT>
+__device__ __forceinline__ void batch_item(const LevelDesc &d, int64_t tile, const T *x, T *y,
+                                           T *xs) {
+    switch (d.kind) {
+    case LK_SCALAR: {
+        int64_t i = tile * kPBlock + threadIdx.x;
+        if (i < d.m) y[i] = (T)csr_row_seq<T>(i, d.rp, d.col, (const T *)d.val, x);
+        break;
+    }
+    case LK_VECTOR:
+        switch (d.lanes) {
+        case 1: vector_tile<T, 1, NT>(d, tile, x, y); break;
+        case 2: vector_tile<T, 2, NT>(d, tile, x, y); break;
+        case 4: vector_tile<T, 4, NT>(d, tile, x, y); break;
+        case 8: vector_tile<T, 8, NT>(d, tile, x, y); break;
+        case 16: vector_tile<T, 16, NT>(d, tile, x, y); break;
+        case 32: vector_tile<T, 32, NT>(d, tile, x, y); break;
+        default: vector_tile<T, 64, NT>(d, tile, x, y); break;
+        }
+        break;
+    case LK_ELL: {
+        int64_t i = tile * kPBlock + threadIdx.x;
+        if (i < d.m) y[i] = (T)ell_row<T, 4, NT>(i, d.m_pad, d.K, d.ecol, (const T *)d.eval, x);
+        break;
+    }
+    case LK_DIA:
+        dia_tile_lds<T, kPDiaRpt, NT>(tile * d.tile_rows, d.m, d.n, d.m_pad, d.offs, d.nwin,
+                                      d.win, (const T *)d.data, x, y, xs);
+        break;
+    default:
+        dia_tile_direct<T, kPDiaRpt, NT>(tile * d.tile_rows, d.m, d.n, d.m_pad, d.D, d.offs,
+                                         (const T *)d.data, x, y);
+        break;
     }
 }
 
@@ -64,37 +102,10 @@ __global__ __launch_bounds__(kPBlock) void k_batch_persistent(const LevelDesc *_
         const int64_t tile = t - d.tile_begin;
         const T *x = (const T *)P.x[l];
         T *y = (T *)P.y[l];
-        switch (d.kind) {
-        case LK_SCALAR: {
-            int64_t i = tile * kPBlock + threadIdx.x;
-            if (i < d.m) y[i] = (T)csr_row_seq<T>(i, d.rp, d.col, (const T *)d.val, x);
-            break;
-        }
-        case LK_VECTOR:
-            switch (d.lanes) {
-            case 1: vector_tile<T, 1>(d, tile, x, y); break;
-            case 2: vector_tile<T, 2>(d, tile, x, y); break;
-            case 4: vector_tile<T, 4>(d, tile, x, y); break;
-            case 8: vector_tile<T, 8>(d, tile, x, y); break;
-            case 16: vector_tile<T, 16>(d, tile, x, y); break;
-            case 32: vector_tile<T, 32>(d, tile, x, y); break;
-            default: vector_tile<T, 64>(d, tile, x, y); break;
-            }
-            break;
-        case LK_ELL: {
-            int64_t i = tile * kPBlock + threadIdx.x;
-            if (i < d.m) y[i] = (T)ell_row<T, 4>(i, d.m_pad, d.K, d.ecol, (const T *)d.eval, x);
-            break;
-        }
-        case LK_DIA:
-            dia_tile_lds<T, kPDiaRpt>(tile * d.tile_rows, d.m, d.n, d.m_pad, d.offs, d.nwin, d.win,
-                                      (const T *)d.data, x, y, xs);
-            break;
-        default:
-            dia_tile_direct<T, kPDiaRpt>(tile * d.tile_rows, d.m, d.n, d.m_pad, d.D, d.offs,
-                                         (const T *)d.data, x, y);
-            break;
-        }
+        if (d.nt)
+            batch_item<T, true>(d, tile, x, y, xs);
+        else
+            batch_item<T, false>(d, tile, x, y, xs);
         __syncthreads();  // LDS reuse by the next item
     }
     // the last workgroup out re-arms the ticket for the next launch
@@ -209,6 +220,7 @@ extern "C" spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplan
         d.rp = P.rp.as<int32_t>();
         d.col = P.col.as<int32_t>();
         d.val = P.val.p;
+        d.nt = V.prm.stream_nt == 1;
         switch (V.kernel) {
         case SPMV_K_CSR_SCALAR: d.kind = LK_SCALAR; d.tile_rows = kPBlock; break;
         case SPMV_K_CSR_VECTOR:
@@ -326,6 +338,53 @@ extern "C" spmv_status spmv_batch_run(spmv_batch_t B, const void *const *xs, voi
         spmv_status st = spmv_run(B->plans[l], xs[l], ys[l], s);
         if (st != SPMV_OK) return st;
     }
+    return SPMV_OK;
+}
+
+extern "C" spmv_status spmv_batch_tune(spmv_batch_t B, const void *const *xs, void *const *ys,
+                                       int32_t reps, void *stream, int32_t *grid_out) {
+    if (!B || !xs || !ys) {
+        set_error("spmv_batch_tune: NULL argument");
+        return SPMV_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (reps < 1) reps = 5;
+    if (B->mode == 0 && B->total_tiles > 0) {
+        int dev = 0, cus = 0;
+        SMAT_HIP(hipGetDevice(&dev));
+        SMAT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+        hipEvent_t a, b;
+        SMAT_HIP(hipEventCreate(&a));
+        SMAT_HIP(hipEventCreate(&b));
+        int best_grid = B->grid;
+        float best = 1e30f;
+        spmv_status st = SPMV_OK;
+        for (int mult : {1, 2, 4, 8, 16}) {
+            B->grid = (int)std::min<int64_t>(B->total_tiles, (int64_t)cus * mult);
+            st = spmv_batch_run(B, xs, ys, stream);  // warm-up
+            std::vector<float> t;
+            for (int r = 0; r < reps && st == SPMV_OK; ++r) {
+                (void)hipEventRecord(a, s);
+                st = spmv_batch_run(B, xs, ys, stream);
+                (void)hipEventRecord(b, s);
+                (void)hipEventSynchronize(b);
+                float f = 0;
+                (void)hipEventElapsedTime(&f, a, b);
+                t.push_back(f);
+            }
+            if (st != SPMV_OK) break;
+            std::sort(t.begin(), t.end());
+            if (t[t.size() / 2] < best) {
+                best = t[t.size() / 2];
+                best_grid = B->grid;
+            }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        B->grid = best_grid;
+        if (st != SPMV_OK) return st;
+    }
+    if (grid_out) *grid_out = B->grid;
     return SPMV_OK;
 }
 

@@ -106,9 +106,10 @@ struct DiaWindow { int d0, d1; };   // diagonals [d0, d1] share one LDS window
 
 spmv_status run_csr_scalar(int elt, int64_t m, const int32_t *rp, const int32_t *col,
                            const void *val, const void *x, void *y, int block, hipStream_t s);
-spmv_status run_csr_vector(int elt, int lanes, int64_t nrows, const int32_t *rows,
-                           const int32_t *rp, const int32_t *col, const void *val, const void *x,
-                           void *y, int block, hipStream_t s);
+// `nt`: stream the matrix arrays with non-temporal loads.
+spmv_status run_csr_vector(int elt, bool nt, int lanes, int64_t nrows, const int32_t *rp,
+                           const int32_t *col, const void *val, const void *x, void *y, int block,
+                           hipStream_t s);
 // One launch over all length bins.  Launch position q (q = 0..7) serves bin
 // 7 - q; first[q] is its first workgroup, first[8] the grid size.  Bin b holds
 // rows[row_begin[b] .. row_begin[b+1]); bin 7 gives a 256-thread workgroup to
@@ -117,7 +118,7 @@ struct AdaptiveLaunch {
     unsigned first[9];
     unsigned row_begin[9];
 };
-spmv_status run_csr_adaptive(int elt, const AdaptiveLaunch &a, const int32_t *rows,
+spmv_status run_csr_adaptive(int elt, bool nt, const AdaptiveLaunch &a, const int32_t *rows,
                              const int32_t *rp, const int32_t *col, const void *val,
                              const void *x, void *y, hipStream_t s);
 // split rows: segments (row, begin, end) reduce into partials, then fix-up
@@ -125,16 +126,16 @@ spmv_status run_csr_split(int elt, int64_t nseg, const int64_t *segs, double *pa
                           int64_t nrows, const int64_t *row_seg_begin, const int32_t *rows,
                           const int32_t *col, const void *val, const void *x, void *y,
                           hipStream_t s);
-spmv_status run_ell(int elt, int64_t m, int64_t m_pad, int K, const int32_t *ecol,
+spmv_status run_ell(int elt, bool nt, int64_t m, int64_t m_pad, int K, const int32_t *ecol,
                     const void *eval, const void *x, void *y, int block, int unroll,
                     hipStream_t s);
-spmv_status run_dia(int elt, bool lds, int64_t m, int64_t n, int64_t m_pad, int D,
-                    const int32_t *offs_dev, const int32_t *offs_host, int nwin,
-                    const DiaWindow *win_dev, int max_span, const void *data, const void *x,
-                    void *y, int block, int rows_per_thread, hipStream_t s);
-spmv_status run_coo(int elt, int64_t m, int64_t nnz, const int32_t *row_idx, const int32_t *col,
-                    const void *val, const void *x, void *y, int chunk, double *head,
-                    double *tail, uint32_t *flags, hipStream_t s);
+spmv_status run_dia(int elt, bool nt, bool lds, int64_t m, int64_t n, int64_t m_pad, int D,
+                    const int32_t *offs_dev, int nwin, const DiaWindow *win_dev, int max_span,
+                    const void *data, const void *x, void *y, int block, int rows_per_thread,
+                    hipStream_t s);
+spmv_status run_coo(int elt, bool nt, int64_t m, int64_t nnz, const int32_t *row_idx,
+                    const int32_t *col, const void *val, const void *x, void *y, int chunk,
+                    double *head, double *tail, uint32_t *flags, hipStream_t s);
 spmv_status run_fill_zero(int elt, int64_t m, void *y, hipStream_t s);
 
 // ----------------------------------------------------------------- MLP

@@ -40,19 +40,17 @@ __global__ __launch_bounds__(1024) void k_csr_scalar(int64_t m, const int32_t *_
 // ---------------------------------------------------------------- CSR vector
 // L lanes per row (L = 1..64, a sub-wavefront group); lanes stride the row so
 // each trip of the group loads L consecutive entries; xor-shuffle reduction.
-// `rows` (optional) lists the rows to process, e.g. one length bin.
-template <typename T, int L>
-__global__ __launch_bounds__(256) void k_csr_vector(int64_t nrows, const int32_t *__restrict__ rows,
-                                                    const int32_t *__restrict__ rp,
-                                                    const int32_t *__restrict__ col,
-                                                    const T *__restrict__ val,
-                                                    const T *__restrict__ x, T *__restrict__ y) {
+template <typename T, int L, bool NT>
+__global__ __launch_bounds__(1024) void k_csr_vector(int64_t nrows,
+                                                     const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ col,
+                                                     const T *__restrict__ val,
+                                                     const T *__restrict__ x, T *__restrict__ y) {
     int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    int64_t r = gt / L;
+    int64_t row = gt / L;
     int lane = threadIdx.x & (L - 1);
-    if (r >= nrows) return;  // whole lane groups leave together
-    int64_t row = rows ? (int64_t)rows[r] : r;
-    double acc = csr_row_lanes<T, L>(row, lane, rp, col, val, x);
+    if (row >= nrows) return;  // whole lane groups leave together
+    double acc = csr_row_lanes<T, L, NT>(row, lane, rp, col, val, x);
     if (lane == 0) y[row] = (T)acc;
 }
 
@@ -63,7 +61,7 @@ __global__ __launch_bounds__(256) void k_csr_vector(int64_t nrows, const int32_t
 constexpr int kRowBlock = 512;     // split-row segments
 constexpr int kAdaptBlock = 256;
 
-template <typename T, int L>
+template <typename T, int L, bool NT>
 __device__ __forceinline__ void adaptive_lanes(unsigned local, unsigned rbeg, unsigned rend,
                                                const int32_t *__restrict__ rows,
                                                const int32_t *__restrict__ rp,
@@ -74,12 +72,12 @@ __device__ __forceinline__ void adaptive_lanes(unsigned local, unsigned rbeg, un
     int lane = threadIdx.x & (L - 1);
     if (r < rend) {
         int64_t row = rows[r];
-        double acc = csr_row_lanes<T, L>(row, lane, rp, col, val, x);
+        double acc = csr_row_lanes<T, L, NT>(row, lane, rp, col, val, x);
         if (lane == 0) y[row] = (T)acc;
     }
 }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kAdaptBlock) void k_csr_adaptive(AdaptiveLaunch a,
                                                               const int32_t *__restrict__ rows,
                                                               const int32_t *__restrict__ rp,
@@ -97,17 +95,17 @@ __global__ __launch_bounds__(kAdaptBlock) void k_csr_adaptive(AdaptiveLaunch a,
     switch (b) {
     case 7: {
         int64_t row = rows[rb + local];
-        double s = csr_row_block<T, kAdaptBlock>(row, rp, col, val, x, part);
+        double s = csr_row_block<T, kAdaptBlock, NT>(row, rp, col, val, x, part);
         if (threadIdx.x == 0) y[row] = (T)s;
         break;
     }
-    case 6: adaptive_lanes<T, 64>(local, rb, re, rows, rp, col, val, x, y); break;
-    case 5: adaptive_lanes<T, 32>(local, rb, re, rows, rp, col, val, x, y); break;
-    case 4: adaptive_lanes<T, 16>(local, rb, re, rows, rp, col, val, x, y); break;
-    case 3: adaptive_lanes<T, 8>(local, rb, re, rows, rp, col, val, x, y); break;
-    case 2: adaptive_lanes<T, 4>(local, rb, re, rows, rp, col, val, x, y); break;
-    case 1: adaptive_lanes<T, 2>(local, rb, re, rows, rp, col, val, x, y); break;
-    default: adaptive_lanes<T, 1>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 6: adaptive_lanes<T, 64, NT>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 5: adaptive_lanes<T, 32, NT>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 4: adaptive_lanes<T, 16, NT>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 3: adaptive_lanes<T, 8, NT>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 2: adaptive_lanes<T, 4, NT>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 1: adaptive_lanes<T, 2, NT>(local, rb, re, rows, rp, col, val, x, y); break;
+    default: adaptive_lanes<T, 1, NT>(local, rb, re, rows, rp, col, val, x, y); break;
     }
 }
 
@@ -124,7 +122,7 @@ __global__ __launch_bounds__(kRowBlock) void k_csr_segment(const int64_t *__rest
     double acc = 0.0;
 #pragma unroll 4
     for (int64_t p = b + threadIdx.x; p < e; p += kRowBlock)
-        acc = fma((double)ld_stream(val + p), (double)x[ld_stream(col + p)], acc);
+        acc = fma((double)val[p], (double)x[col[p]], acc);
     for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
     __syncthreads();
@@ -150,14 +148,14 @@ __global__ void k_csr_segment_fixup(int64_t nrows, const int64_t *__restrict__ r
 // Slot-major layout: thread i reads slot k of row i at k*m_pad + i, so a
 // wavefront reads 64 consecutive values and 64 consecutive columns per slot.
 // U slots are loaded before any is used, to keep more loads in flight.
-template <typename T, int U>
+template <typename T, int U, bool NT>
 __global__ __launch_bounds__(1024) void k_ell(int64_t m, int64_t m_pad, int K,
                                               const int32_t *__restrict__ ecol,
                                               const T *__restrict__ eval, const T *__restrict__ x,
                                               T *__restrict__ y) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= m) return;
-    y[i] = (T)ell_row<T, U>(i, m_pad, K, ecol, eval, x);
+    y[i] = (T)ell_row<T, U, NT>(i, m_pad, K, ecol, eval, x);
 }
 
 // ---------------------------------------------------------------- DIA
@@ -167,7 +165,7 @@ __global__ __launch_bounds__(1024) void k_ell(int64_t m, int64_t m_pad, int K,
 // the window reads its shifted view from there, while the diagonal values
 // stream from HBM with unit stride.  Summation runs over diagonals in
 // ascending offset order, i.e. ascending column order as in CSR.
-template <typename T, int RPT>
+template <typename T, int RPT, bool NT>
 __global__ __launch_bounds__(256) void k_dia_lds(int64_t m, int64_t n, int64_t m_pad,
                                                  const int32_t *__restrict__ offs, int nwin,
                                                  const DiaWindow *__restrict__ win,
@@ -176,18 +174,18 @@ __global__ __launch_bounds__(256) void k_dia_lds(int64_t m, int64_t n, int64_t m
     extern __shared__ unsigned char smem_raw[];
     T *xs = reinterpret_cast<T *>(smem_raw);
     const int64_t r0 = (int64_t)blockIdx.x * blockDim.x * RPT;
-    dia_tile_lds<T, RPT>(r0, m, n, m_pad, offs, nwin, win, data, x, y, xs);
+    dia_tile_lds<T, RPT, NT>(r0, m, n, m_pad, offs, nwin, win, data, x, y, xs);
 }
 
 // DIA without LDS: x comes through L1/L2 (neighbouring diagonals hit the same
 // cache lines).
-template <typename T, int RPT>
+template <typename T, int RPT, bool NT>
 __global__ __launch_bounds__(256) void k_dia_direct(int64_t m, int64_t n, int64_t m_pad, int D,
                                                     const int32_t *__restrict__ offs,
                                                     const T *__restrict__ data,
                                                     const T *__restrict__ x, T *__restrict__ y) {
     const int64_t r0 = (int64_t)blockIdx.x * blockDim.x * RPT;
-    dia_tile_direct<T, RPT>(r0, m, n, m_pad, D, offs, data, x, y);
+    dia_tile_direct<T, RPT, NT>(r0, m, n, m_pad, D, offs, data, x, y);
 }
 
 // ---------------------------------------------------------------- COO
@@ -211,7 +209,7 @@ __device__ __forceinline__ void coo_emit(int row, double v, int first_row, bool 
         y[row] = (T)v;
 }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(256) void k_coo(int64_t m, int64_t nnz, int E,
                                              const int32_t *__restrict__ ri,
                                              const int32_t *__restrict__ col,
@@ -243,8 +241,8 @@ __global__ __launch_bounds__(256) void k_coo(int64_t m, int64_t nnz, int E,
     for (int64_t it = c0; it < c1; it += kWave) {
         const int64_t p = it + lane;
         const bool valid = p < c1;
-        const int r = valid ? ld_stream(ri + p) : INT_MAX;
-        double v = valid ? fma((double)ld_stream(val + p), (double)x[ld_stream(col + p)], 0.0) : 0.0;
+        const int r = valid ? ld<NT>(ri + p) : INT_MAX;
+        double v = valid ? fma((double)ld<NT>(val + p), (double)x[ld<NT>(col + p)], 0.0) : 0.0;
         // rows skipped between consecutive entries have no entries: zero them
         int rb = __shfl_up(r, 1, kWave);
         if (lane == 0) rb = before;
@@ -317,22 +315,23 @@ __global__ void k_fill_zero(int64_t m, T *y) {
     if (i < m) y[i] = T(0);
 }
 
-template <typename T>
-spmv_status csr_vector_dispatch(int lanes, int64_t nrows, const int32_t *rows, const int32_t *rp,
-                                const int32_t *col, const T *val, const T *x, T *y, int block,
-                                hipStream_t s) {
+// ---------------------------------------------------------------- dispatch
+
+template <typename T, bool NT>
+spmv_status csr_vector_dispatch(int lanes, int64_t nrows, const int32_t *rp, const int32_t *col,
+                                const T *val, const T *x, T *y, int block, hipStream_t s) {
     if (nrows == 0) return SPMV_OK;
     if (block <= 0) block = 256;
     block = block < lanes ? lanes : block;
     unsigned g = grid_for(nrows * lanes, block);
     switch (lanes) {
-    case 1: k_csr_vector<T, 1><<<g, block, 0, s>>>(nrows, rows, rp, col, val, x, y); break;
-    case 2: k_csr_vector<T, 2><<<g, block, 0, s>>>(nrows, rows, rp, col, val, x, y); break;
-    case 4: k_csr_vector<T, 4><<<g, block, 0, s>>>(nrows, rows, rp, col, val, x, y); break;
-    case 8: k_csr_vector<T, 8><<<g, block, 0, s>>>(nrows, rows, rp, col, val, x, y); break;
-    case 16: k_csr_vector<T, 16><<<g, block, 0, s>>>(nrows, rows, rp, col, val, x, y); break;
-    case 32: k_csr_vector<T, 32><<<g, block, 0, s>>>(nrows, rows, rp, col, val, x, y); break;
-    case 64: k_csr_vector<T, 64><<<g, block, 0, s>>>(nrows, rows, rp, col, val, x, y); break;
+    case 1: k_csr_vector<T, 1, NT><<<g, block, 0, s>>>(nrows, rp, col, val, x, y); break;
+    case 2: k_csr_vector<T, 2, NT><<<g, block, 0, s>>>(nrows, rp, col, val, x, y); break;
+    case 4: k_csr_vector<T, 4, NT><<<g, block, 0, s>>>(nrows, rp, col, val, x, y); break;
+    case 8: k_csr_vector<T, 8, NT><<<g, block, 0, s>>>(nrows, rp, col, val, x, y); break;
+    case 16: k_csr_vector<T, 16, NT><<<g, block, 0, s>>>(nrows, rp, col, val, x, y); break;
+    case 32: k_csr_vector<T, 32, NT><<<g, block, 0, s>>>(nrows, rp, col, val, x, y); break;
+    case 64: k_csr_vector<T, 64, NT><<<g, block, 0, s>>>(nrows, rp, col, val, x, y); break;
     default:
         set_error("csr_vector: lanes must be a power of two in [1, 64], got %d", lanes);
         return SPMV_EINVAL;
@@ -341,53 +340,86 @@ spmv_status csr_vector_dispatch(int lanes, int64_t nrows, const int32_t *rows, c
     return SPMV_OK;
 }
 
-template <typename T>
+template <typename T, bool NT>
 spmv_status ell_dispatch(int64_t m, int64_t m_pad, int K, const int32_t *ecol, const T *eval,
                          const T *x, T *y, int block, int unroll, hipStream_t s) {
     if (m == 0) return SPMV_OK;
     if (block <= 0) block = 256;
     unsigned g = grid_for(m, block);
     switch (unroll) {
-    case 1: k_ell<T, 1><<<g, block, 0, s>>>(m, m_pad, K, ecol, eval, x, y); break;
-    case 2: k_ell<T, 2><<<g, block, 0, s>>>(m, m_pad, K, ecol, eval, x, y); break;
-    default: k_ell<T, 4><<<g, block, 0, s>>>(m, m_pad, K, ecol, eval, x, y); break;
+    case 1: k_ell<T, 1, NT><<<g, block, 0, s>>>(m, m_pad, K, ecol, eval, x, y); break;
+    case 2: k_ell<T, 2, NT><<<g, block, 0, s>>>(m, m_pad, K, ecol, eval, x, y); break;
+    default: k_ell<T, 4, NT><<<g, block, 0, s>>>(m, m_pad, K, ecol, eval, x, y); break;
     }
     SMAT_LAUNCHED("ell");
     return SPMV_OK;
 }
 
-template <typename T>
+template <typename T, bool NT>
 spmv_status dia_dispatch(bool lds, int64_t m, int64_t n, int64_t m_pad, int D,
                          const int32_t *offs, int nwin, const DiaWindow *win, int max_span,
                          const T *data, const T *x, T *y, int block, int rpt, hipStream_t s) {
     if (m == 0) return SPMV_OK;
-    if (block <= 0) block = 256;
+    if (block <= 0 || block > 256) block = 256;
     if (rpt != 1 && rpt != 2 && rpt != 4 && rpt != 8) rpt = 4;
     int64_t tile = (int64_t)block * rpt;
     unsigned g = grid_for(m, (int)tile);
     if (lds) {
         size_t sh = (size_t)(tile + max_span) * sizeof(T);
         switch (rpt) {
-        case 1: k_dia_lds<T, 1><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
-        case 2: k_dia_lds<T, 2><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
-        case 4: k_dia_lds<T, 4><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
-        default: k_dia_lds<T, 8><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
+        case 1: k_dia_lds<T, 1, NT><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
+        case 2: k_dia_lds<T, 2, NT><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
+        case 4: k_dia_lds<T, 4, NT><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
+        default: k_dia_lds<T, 8, NT><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
         }
     } else {
         switch (rpt) {
-        case 1: k_dia_direct<T, 1><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
-        case 2: k_dia_direct<T, 2><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
-        case 4: k_dia_direct<T, 4><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
-        default: k_dia_direct<T, 8><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
+        case 1: k_dia_direct<T, 1, NT><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
+        case 2: k_dia_direct<T, 2, NT><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
+        case 4: k_dia_direct<T, 4, NT><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
+        default: k_dia_direct<T, 8, NT><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
         }
     }
     SMAT_LAUNCHED(lds ? "dia_lds" : "dia_direct");
     return SPMV_OK;
 }
 
+template <typename T, bool NT>
+spmv_status coo_dispatch(int64_t m, int64_t nnz, const int32_t *ri, const int32_t *col,
+                         const T *val, const T *x, T *y, int chunk, double *head, double *tail,
+                         uint32_t *flags, hipStream_t s) {
+    int64_t per = (int64_t)chunk * kWave;
+    int64_t nchunks = (nnz + per - 1) / per;
+    unsigned g = grid_for(nchunks * kWave, 256);
+    k_coo<T, NT><<<g, 256, 0, s>>>(m, nnz, chunk, ri, col, val, x, y, head, tail, flags);
+    SMAT_LAUNCHED("coo");
+    k_coo_fixup<T><<<grid_for(nchunks, 256), 256, 0, s>>>(nchunks, per, nnz, ri, head, tail,
+                                                          flags, y);
+    SMAT_LAUNCHED("coo_fixup");
+    return SPMV_OK;
+}
+
+template <typename T>
+spmv_status adaptive_dispatch(bool nt, const AdaptiveLaunch &a, const int32_t *rows,
+                              const int32_t *rp, const int32_t *col, const T *val, const T *x,
+                              T *y, hipStream_t s) {
+    const unsigned nblk = a.first[8];
+    if (nblk == 0) return SPMV_OK;
+    if (nt)
+        k_csr_adaptive<T, true><<<nblk, kAdaptBlock, 0, s>>>(a, rows, rp, col, val, x, y);
+    else
+        k_csr_adaptive<T, false><<<nblk, kAdaptBlock, 0, s>>>(a, rows, rp, col, val, x, y);
+    SMAT_LAUNCHED("csr_adaptive");
+    return SPMV_OK;
+}
+
 }  // namespace
 
-#define SMAT_BY_ELT(elt, CALL_F, CALL_D) ((elt) == 8 ? (CALL_D) : (CALL_F))
+// Typed entry points: elt selects float (4) or double (8), nt the streaming
+// cache policy.
+#define SMAT_TYPED(elt, nt, CALL)                                                      \
+    ((elt) == 8 ? ((nt) ? CALL(double, true) : CALL(double, false))                    \
+                : ((nt) ? CALL(float, true) : CALL(float, false)))
 
 spmv_status run_csr_scalar(int elt, int64_t m, const int32_t *rp, const int32_t *col,
                            const void *val, const void *x, void *y, int block, hipStream_t s) {
@@ -404,30 +436,24 @@ spmv_status run_csr_scalar(int elt, int64_t m, const int32_t *rp, const int32_t 
     return SPMV_OK;
 }
 
-spmv_status run_csr_vector(int elt, int lanes, int64_t nrows, const int32_t *rows,
-                           const int32_t *rp, const int32_t *col, const void *val, const void *x,
-                           void *y, int block, hipStream_t s) {
-    return SMAT_BY_ELT(elt,
-                       csr_vector_dispatch<float>(lanes, nrows, rows, rp, col, (const float *)val,
-                                                  (const float *)x, (float *)y, block, s),
-                       csr_vector_dispatch<double>(lanes, nrows, rows, rp, col,
-                                                   (const double *)val, (const double *)x,
-                                                   (double *)y, block, s));
+spmv_status run_csr_vector(int elt, bool nt, int lanes, int64_t nrows, const int32_t *rp,
+                           const int32_t *col, const void *val, const void *x, void *y, int block,
+                           hipStream_t s) {
+#define CALL(T, NT)                                                                          \
+    csr_vector_dispatch<T, NT>(lanes, nrows, rp, col, (const T *)val, (const T *)x, (T *)y, \
+                               block, s)
+    return SMAT_TYPED(elt, nt, CALL);
+#undef CALL
 }
 
-spmv_status run_csr_adaptive(int elt, const AdaptiveLaunch &a, const int32_t *rows,
+spmv_status run_csr_adaptive(int elt, bool nt, const AdaptiveLaunch &a, const int32_t *rows,
                              const int32_t *rp, const int32_t *col, const void *val,
                              const void *x, void *y, hipStream_t s) {
-    const unsigned nblk = a.first[8];
-    if (nblk == 0) return SPMV_OK;
     if (elt == 8)
-        k_csr_adaptive<double><<<nblk, kAdaptBlock, 0, s>>>(
-            a, rows, rp, col, (const double *)val, (const double *)x, (double *)y);
-    else
-        k_csr_adaptive<float><<<nblk, kAdaptBlock, 0, s>>>(
-            a, rows, rp, col, (const float *)val, (const float *)x, (float *)y);
-    SMAT_LAUNCHED("csr_adaptive");
-    return SPMV_OK;
+        return adaptive_dispatch<double>(nt, a, rows, rp, col, (const double *)val,
+                                         (const double *)x, (double *)y, s);
+    return adaptive_dispatch<float>(nt, a, rows, rp, col, (const float *)val, (const float *)x,
+                                    (float *)y, s);
 }
 
 spmv_status run_csr_split(int elt, int64_t nseg, const int64_t *segs, double *partials,
@@ -452,54 +478,38 @@ spmv_status run_csr_split(int elt, int64_t nseg, const int64_t *segs, double *pa
     return SPMV_OK;
 }
 
-spmv_status run_ell(int elt, int64_t m, int64_t m_pad, int K, const int32_t *ecol,
+spmv_status run_ell(int elt, bool nt, int64_t m, int64_t m_pad, int K, const int32_t *ecol,
                     const void *eval, const void *x, void *y, int block, int unroll,
                     hipStream_t s) {
-    return SMAT_BY_ELT(elt,
-                       ell_dispatch<float>(m, m_pad, K, ecol, (const float *)eval,
-                                           (const float *)x, (float *)y, block, unroll, s),
-                       ell_dispatch<double>(m, m_pad, K, ecol, (const double *)eval,
-                                            (const double *)x, (double *)y, block, unroll, s));
+#define CALL(T, NT)                                                                             \
+    ell_dispatch<T, NT>(m, m_pad, K, ecol, (const T *)eval, (const T *)x, (T *)y, block, unroll, \
+                        s)
+    return SMAT_TYPED(elt, nt, CALL);
+#undef CALL
 }
 
-spmv_status run_dia(int elt, bool lds, int64_t m, int64_t n, int64_t m_pad, int D,
-                    const int32_t *offs_dev, const int32_t *offs_host, int nwin,
-                    const DiaWindow *win_dev, int max_span, const void *data, const void *x,
-                    void *y, int block, int rows_per_thread, hipStream_t s) {
-    (void)offs_host;
+spmv_status run_dia(int elt, bool nt, bool lds, int64_t m, int64_t n, int64_t m_pad, int D,
+                    const int32_t *offs_dev, int nwin, const DiaWindow *win_dev, int max_span,
+                    const void *data, const void *x, void *y, int block, int rows_per_thread,
+                    hipStream_t s) {
     if (D == 0) return run_fill_zero(elt, m, y, s);
-    return SMAT_BY_ELT(elt,
-                       dia_dispatch<float>(lds, m, n, m_pad, D, offs_dev, nwin, win_dev, max_span,
-                                           (const float *)data, (const float *)x, (float *)y,
-                                           block, rows_per_thread, s),
-                       dia_dispatch<double>(lds, m, n, m_pad, D, offs_dev, nwin, win_dev,
-                                            max_span, (const double *)data, (const double *)x,
-                                            (double *)y, block, rows_per_thread, s));
+#define CALL(T, NT)                                                                      \
+    dia_dispatch<T, NT>(lds, m, n, m_pad, D, offs_dev, nwin, win_dev, max_span,          \
+                        (const T *)data, (const T *)x, (T *)y, block, rows_per_thread, s)
+    return SMAT_TYPED(elt, nt, CALL);
+#undef CALL
 }
 
-spmv_status run_coo(int elt, int64_t m, int64_t nnz, const int32_t *row_idx, const int32_t *col,
-                    const void *val, const void *x, void *y, int chunk, double *head,
-                    double *tail, uint32_t *flags, hipStream_t s) {
+spmv_status run_coo(int elt, bool nt, int64_t m, int64_t nnz, const int32_t *row_idx,
+                    const int32_t *col, const void *val, const void *x, void *y, int chunk,
+                    double *head, double *tail, uint32_t *flags, hipStream_t s) {
     if (m == 0) return SPMV_OK;
     if (nnz == 0) return run_fill_zero(elt, m, y, s);
-    int64_t per = (int64_t)chunk * kWave;
-    int64_t nchunks = (nnz + per - 1) / per;
-    unsigned g = grid_for(nchunks * kWave, 256);
-    if (elt == 8) {
-        k_coo<double><<<g, 256, 0, s>>>(m, nnz, chunk, row_idx, col, (const double *)val,
-                                        (const double *)x, (double *)y, head, tail, flags);
-        SMAT_LAUNCHED("coo");
-        k_coo_fixup<double><<<grid_for(nchunks, 256), 256, 0, s>>>(nchunks, per, nnz, row_idx,
-                                                                   head, tail, flags, (double *)y);
-    } else {
-        k_coo<float><<<g, 256, 0, s>>>(m, nnz, chunk, row_idx, col, (const float *)val,
-                                       (const float *)x, (float *)y, head, tail, flags);
-        SMAT_LAUNCHED("coo");
-        k_coo_fixup<float><<<grid_for(nchunks, 256), 256, 0, s>>>(nchunks, per, nnz, row_idx,
-                                                                  head, tail, flags, (float *)y);
-    }
-    SMAT_LAUNCHED("coo_fixup");
-    return SPMV_OK;
+#define CALL(T, NT)                                                                         \
+    coo_dispatch<T, NT>(m, nnz, row_idx, col, (const T *)val, (const T *)x, (T *)y, chunk, \
+                        head, tail, flags, s)
+    return SMAT_TYPED(elt, nt, CALL);
+#undef CALL
 }
 
 spmv_status run_fill_zero(int elt, int64_t m, void *y, hipStream_t s) {

@@ -1,25 +1,24 @@
 // Per-row / per-tile SpMV device functions shared by the stand-alone kernels
 // and the persistent multilevel kernel, so both compute every output with the
 // same operations in the same order (bitwise-identical results).
+//
+// NT selects the cache policy of the matrix streams (values, column indices,
+// diagonals): non-temporal loads keep them from displacing the reused x
+// vector in L2, which helps banded matrices and can hurt gathers from
+// large, randomly indexed x.  It is a tuning parameter (spmv_params
+// stream_nt); the arithmetic is identical either way.
 #pragma once
 
 #include "internal.hpp"
 
-// Matrix arrays are read once per SpMV: load them non-temporally so that they
-// do not push the reused x vector out of L2.
-#ifndef SMAT_STREAM_NT
-#define SMAT_STREAM_NT 1
-#endif
-
 namespace smat {
 
-template <typename T>
-__device__ __forceinline__ T ld_stream(const T *p) {
-#if SMAT_STREAM_NT
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
+template <bool NT, typename T>
+__device__ __forceinline__ T ld(const T *p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
 }
 
 // Plain CSR row: one thread, storage order.
@@ -36,7 +35,7 @@ __device__ __forceinline__ double csr_row_seq(int64_t i, const int32_t *__restri
 
 // CSR row by a group of L lanes (lane = 0..L-1); lanes stride the row and
 // reduce by xor shuffles.  Every lane of the group returns the row sum.
-template <typename T, int L>
+template <typename T, int L, bool NT>
 __device__ __forceinline__ double csr_row_lanes(int64_t row, int lane,
                                                 const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ col,
@@ -44,16 +43,9 @@ __device__ __forceinline__ double csr_row_lanes(int64_t row, int lane,
                                                 const T *__restrict__ x) {
     int32_t b = rp[row], e = rp[row + 1];
     double acc = 0.0;
-    if (L == kWave) {
-        // a full wavefront consumes whole cache lines per trip: stream them
 #pragma unroll 4
-        for (int32_t p = b + lane; p < e; p += L)
-            acc = fma((double)ld_stream(val + p), (double)x[ld_stream(col + p)], acc);
-    } else {
-        // narrower groups come back to the same lines on later trips
-#pragma unroll 4
-        for (int32_t p = b + lane; p < e; p += L) acc = fma((double)val[p], (double)x[col[p]], acc);
-    }
+    for (int32_t p = b + lane; p < e; p += L)
+        acc = fma((double)ld<NT>(val + p), (double)x[ld<NT>(col + p)], acc);
 #pragma unroll
     for (int off = L / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, L);
     return acc;
@@ -61,7 +53,7 @@ __device__ __forceinline__ double csr_row_lanes(int64_t row, int lane,
 
 // CSR row by a whole workgroup of B threads (B a multiple of 64); thread 0
 // returns the row sum.  `part` is LDS scratch of B / 64 doubles.
-template <typename T, int B>
+template <typename T, int B, bool NT>
 __device__ __forceinline__ double csr_row_block(int64_t row, const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ col,
                                                 const T *__restrict__ val,
@@ -70,7 +62,7 @@ __device__ __forceinline__ double csr_row_block(int64_t row, const int32_t *__re
     double acc = 0.0;
 #pragma unroll 4
     for (int32_t p = b + threadIdx.x; p < e; p += B)
-        acc = fma((double)ld_stream(val + p), (double)x[ld_stream(col + p)], acc);
+        acc = fma((double)ld<NT>(val + p), (double)x[ld<NT>(col + p)], acc);
     for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
     if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = acc;
     __syncthreads();
@@ -82,7 +74,7 @@ __device__ __forceinline__ double csr_row_block(int64_t row, const int32_t *__re
 }
 
 // ELL row: slots in order, U slots loaded ahead of use.
-template <typename T, int U>
+template <typename T, int U, bool NT>
 __device__ __forceinline__ double ell_row(int64_t i, int64_t m_pad, int K,
                                           const int32_t *__restrict__ ecol,
                                           const T *__restrict__ eval, const T *__restrict__ x) {
@@ -94,8 +86,8 @@ __device__ __forceinline__ double ell_row(int64_t i, int64_t m_pad, int K,
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             int64_t s = (int64_t)(k + u) * m_pad + i;
-            c[u] = ld_stream(ecol + s);
-            v[u] = ld_stream(eval + s);
+            c[u] = ld<NT>(ecol + s);
+            v[u] = ld<NT>(eval + s);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
@@ -103,15 +95,15 @@ __device__ __forceinline__ double ell_row(int64_t i, int64_t m_pad, int K,
     }
     for (; k < K; ++k) {
         int64_t s = (int64_t)k * m_pad + i;
-        int32_t c = ld_stream(ecol + s);
-        if (c >= 0) acc = fma((double)ld_stream(eval + s), (double)x[c], acc);
+        int32_t c = ld<NT>(ecol + s);
+        if (c >= 0) acc = fma((double)ld<NT>(eval + s), (double)x[c], acc);
     }
     return acc;
 }
 
 // DIA tile with x windows staged in LDS; every thread of the workgroup must
 // call it (it synchronises).  Rows r0 + threadIdx.x + q*blockDim.x, q < RPT.
-template <typename T, int RPT>
+template <typename T, int RPT, bool NT>
 __device__ __forceinline__ void dia_tile_lds(int64_t r0, int64_t m, int64_t n, int64_t m_pad,
                                              const int32_t *__restrict__ offs, int nwin,
                                              const DiaWindow *__restrict__ win,
@@ -138,7 +130,7 @@ __device__ __forceinline__ void dia_tile_lds(int64_t r0, int64_t m, int64_t n, i
             for (int q = 0; q < RPT; ++q) {
                 int il = threadIdx.x + q * blockDim.x;
                 if (r0 + il < m)
-                    acc[q] = fma((double)ld_stream(dd + il), (double)xs[il + sh], acc[q]);
+                    acc[q] = fma((double)ld<NT>(dd + il), (double)xs[il + sh], acc[q]);
             }
         }
     }
@@ -150,7 +142,7 @@ __device__ __forceinline__ void dia_tile_lds(int64_t r0, int64_t m, int64_t n, i
 }
 
 // DIA tile reading x through the caches.
-template <typename T, int RPT>
+template <typename T, int RPT, bool NT>
 __device__ __forceinline__ void dia_tile_direct(int64_t r0, int64_t m, int64_t n, int64_t m_pad,
                                                 int D, const int32_t *__restrict__ offs,
                                                 const T *__restrict__ data,
@@ -158,32 +150,7 @@ __device__ __forceinline__ void dia_tile_direct(int64_t r0, int64_t m, int64_t n
     double acc[RPT];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
-    int d = 0;
-    // two diagonals per trip: all their loads are issued before the FMAs
-    for (; d + 2 <= D; d += 2) {
-        const int64_t off0 = offs[d], off1 = offs[d + 1];
-        const T *d0 = data + (int64_t)d * m_pad;
-        const T *d1 = d0 + m_pad;
-        T v0[RPT], v1[RPT], x0[RPT], x1[RPT];
-        bool k0[RPT], k1[RPT];
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            int64_t i = r0 + threadIdx.x + q * blockDim.x;
-            int64_t j0 = i + off0, j1 = i + off1;
-            k0[q] = i < m && j0 >= 0 && j0 < n;
-            k1[q] = i < m && j1 >= 0 && j1 < n;
-            v0[q] = k0[q] ? ld_stream(d0 + i) : T(0);
-            x0[q] = k0[q] ? x[j0] : T(0);
-            v1[q] = k1[q] ? ld_stream(d1 + i) : T(0);
-            x1[q] = k1[q] ? x[j1] : T(0);
-        }
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            if (k0[q]) acc[q] = fma((double)v0[q], (double)x0[q], acc[q]);
-            if (k1[q]) acc[q] = fma((double)v1[q], (double)x1[q], acc[q]);
-        }
-    }
-    for (; d < D; ++d) {
+    for (int d = 0; d < D; ++d) {
         const int64_t off = offs[d];
         const T *dd = data + (int64_t)d * m_pad;
 #pragma unroll
@@ -191,7 +158,7 @@ __device__ __forceinline__ void dia_tile_direct(int64_t r0, int64_t m, int64_t n
             int64_t i = r0 + threadIdx.x + q * blockDim.x;
             int64_t j = i + off;
             if (i < m && j >= 0 && j < n)
-                acc[q] = fma((double)ld_stream(dd + i), (double)x[j], acc[q]);
+                acc[q] = fma((double)ld<NT>(dd + i), (double)x[j], acc[q]);
         }
     }
 #pragma unroll

@@ -92,7 +92,9 @@ class Selector:
     def load(cls, path):
         with open(path) as fh:
             d = json.load(fh)
-        return cls(d["params"], d["mean"], d["std"])
+        sel = cls(d["params"], d["mean"], d["std"])
+        sel.tau = d.get("meta", {}).get("tau")
+        return sel
 
     def score(self, raw, stream=None):
         """raw: float32 device tensor [rows, 12] -> scores [rows, K_COUNT]."""
@@ -126,7 +128,7 @@ class Plan:
 
     def __init__(self, row_ptr, col, val, n=None, selector="rules", model=None,
                  tau=None, topk=None, reps=None, disable=(), mem_cap=0, params=None,
-                 stream=None):
+                 autotune=False, stream=None):
         torch = _torch()
         m = row_ptr.numel() - 1
         n = m if n is None else int(n)
@@ -156,6 +158,10 @@ class Plan:
             mask |= 1 << (k if isinstance(k, int) else C.KERNELS.index(k))
         o.disable_mask = mask
         o.mem_cap_bytes = int(mem_cap)
+        o.autotune = 1 if autotune else 0
+        if selector == "mlp" and tau is None and model is not None and \
+                getattr(model, "tau", None) is not None:
+            o.confidence_tau = model.tau
         if params:
             o.use_params = 1
             for k, v in params.items():
@@ -242,6 +248,16 @@ class Batch:
         C.check(C.lib().spmv_batch_run(self.handle, xa, ya, _stream_handle(stream)),
                 "spmv_batch_run")
         return ys
+
+    def tune(self, xs, ys, reps=5, stream=None):
+        """Pick the persistent grid size by timing; returns the grid."""
+        n = len(self.plans)
+        xa = (ctypes.c_void_p * n)(*[x.data_ptr() for x in xs])
+        ya = (ctypes.c_void_p * n)(*[y.data_ptr() for y in ys])
+        g = ctypes.c_int32(0)
+        C.check(C.lib().spmv_batch_tune(self.handle, xa, ya, int(reps), _stream_handle(stream),
+                                        ctypes.byref(g)), "spmv_batch_tune")
+        return g.value
 
     def close(self):
         h = getattr(self, "handle", None)
