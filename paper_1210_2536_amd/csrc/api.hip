@@ -199,8 +199,9 @@ spmv_status validate_and_extract(const spmv_csr &A, hipStream_t s, spmv_features
 // ------------------------------------------------------------------ params
 
 int default_lanes(const spmv_features &F) {
-    // about two entries per lane for a row of mean length
-    int L = pow2_ceil((int64_t)std::ceil(F.aver_rd)) / 2;
+    // about four entries per lane for a row of mean length: enough loads per
+    // lane in flight, few idle lanes
+    int L = pow2_ceil((int64_t)std::ceil(F.aver_rd)) / 4;
     return std::max(1, std::min(64, L));
 }
 
@@ -214,11 +215,22 @@ spmv_params default_params(int kernel, const spmv_features &F) {
     p.dia_span = 64;
     p.coo_chunk = 8;
     p.ell_unroll = 4;
-    // streaming loads pay off when x is reused through the cache (banded
-    // matrices); random gathers from a large x do better with the default
-    // policy (measured on gfx950)
-    p.stream_nt = F.dia_feasible ? 1 : 2;
+    p.stream_nt = 0;  // resolved per kernel by resolve_params
     (void)kernel;
+    return p;
+}
+
+// Fill in the per-kernel defaults left open (0) in `p`.  Streaming loads pay
+// off for the fully coalesced ELL and DIA streams of banded matrices, whose x
+// is reused through the cache; the CSR kernels revisit partly consumed cache
+// lines and random gathers from a large x do better with the default policy
+// (measured on gfx950).
+spmv_params resolve_params(int kernel, spmv_params p, const spmv_features &F) {
+    if (p.stream_nt == 0) {
+        bool dense_stream = kernel == SPMV_K_ELL || kernel == SPMV_K_DIA ||
+                            kernel == SPMV_K_DIA_DIRECT;
+        p.stream_nt = (dense_stream && F.dia_feasible) ? 1 : 2;
+    }
     return p;
 }
 
@@ -263,8 +275,8 @@ spmv_status check_params(const spmv_params &p) {
         set_error("params.ell_unroll must be 1, 2 or 4");
         return SPMV_EINVAL;
     }
-    if (p.stream_nt != 1 && p.stream_nt != 2) {
-        set_error("params.stream_nt must be 1 (on) or 2 (off)");
+    if (p.stream_nt < 0 || p.stream_nt > 2) {
+        set_error("params.stream_nt must be 0 (default), 1 (on) or 2 (off)");
         return SPMV_EINVAL;
     }
     return SPMV_OK;
@@ -344,7 +356,8 @@ void raw_features(const spmv_features &F, int dtype, float out[12]) {
 // ------------------------------------------------------------------ conversion
 
 spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W, int kernel,
-                          const spmv_params &prm, hipStream_t s, Variant &V) {
+                          const spmv_params &prm_in, hipStream_t s, Variant &V) {
+    const spmv_params prm = resolve_params(kernel, prm_in, F);
     V.kernel = kernel;
     V.prm = prm;
     const int64_t m = P.m, n = P.n, nnz = P.nnz;
