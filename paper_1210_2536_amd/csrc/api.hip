@@ -206,14 +206,16 @@ int default_lanes(const spmv_features &F) {
 }
 
 spmv_params default_params(int kernel, const spmv_features &F) {
+    // Sizes that keep a few thousand workgroups in flight on 256 compute
+    // units: small matrices get small workgroups and tiles.
     spmv_params p{};
-    p.block = 256;
+    p.block = F.m >= (512 << 10) ? 256 : F.m >= (64 << 10) ? 128 : 64;
     p.vector_lanes = default_lanes(F);
     p.adaptive_rows_per_lane = 2;
     p.adaptive_wg_min = 4096;
-    p.dia_rows_per_thread = 4;
+    p.dia_rows_per_thread = F.m >= (4 << 20) ? 4 : F.m >= (1 << 20) ? 2 : 1;
     p.dia_span = 64;
-    p.coo_chunk = 8;
+    p.coo_chunk = F.nnz >= (8 << 20) ? 8 : F.nnz >= (1 << 20) ? 4 : 2;
     p.ell_unroll = 4;
     p.stream_nt = 0;  // resolved per kernel by resolve_params
     (void)kernel;
