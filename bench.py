@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--workload", default="sweep",
                     choices=["sweep", "large", "multilevel", "multilevel32", "c1"])
     ap.add_argument("--selector", default="auto", help="auto|mlp|rules|exhaustive|<kernel>")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep default kernel parameters for the chosen kernels")
     ap.add_argument("--no-hitrate", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
@@ -88,13 +90,15 @@ def main():
         val = torch.from_numpy(A.val.astype(dt)).to(dev)
         x = torch.from_numpy(S.uniform_vector(A.n, xseed).astype(dt)).to(dev)
         y = torch.empty(A.m, dtype=val.dtype, device=dev)
-        tuned = Plan(rp, col, val, n=A.n, selector=selector, model=model)
+        tuned = Plan(rp, col, val, n=A.n, selector=selector, model=model,
+                     autotune=not a.no_autotune)
         plain = None if a.no_plain else Plan(rp, col, val, n=A.n, selector="csr_scalar")
         info = tuned.info()
         rec = dict(name=A.name, dtype=np.dtype(dt).name, m=A.m, n=A.n, nnz=A.nnz,
                    kernel=info["kernel_name"], format=info["format_name"],
                    plan_ms=info["t_plan_ms"], bytes=workloads.plan_bytes(info),
-                   confidence=info["confidence"], n_measured=info["n_measured"])
+                   confidence=info["confidence"], n_measured=info["n_measured"],
+                   params=info["params"], rules_kernel=capi.KERNELS[info["rules_kernel"]])
         recs.append(dict(rec=rec, tuned=tuned, plain=plain, x=x, y=y))
         del rp, col, val
     torch.cuda.synchronize()
@@ -169,7 +173,7 @@ def main():
         log(f"plain CSR: {plain_ms_step:.3f} ms/step")
 
     # ---- selector hit rate against exhaustive timing (same session)
-    hit_rate = None
+    hit_rate = rules_hit_rate = None
     if not a.no_hitrate:
         hits = 0
         slow = []
@@ -187,12 +191,16 @@ def main():
             got = table.get(r["rec"]["kernel"], float("inf"))
             r["rec"]["exhaustive_ms"] = table
             r["rec"]["hit"] = bool(got <= 1.05 * best)
+            r["rec"]["rules_hit"] = bool(table.get(r["rec"]["rules_kernel"], float("inf"))
+                                         <= 1.05 * best)
             hits += r["rec"]["hit"]
             slow.append(got / best)
             ex.close()
             del rp, col, val
         hit_rate = hits / len(recs)
-        log(f"hit rate {hit_rate:.3f}, geomean slowdown {np.exp(np.mean(np.log(slow))):.4f}")
+        rules_hit_rate = sum(r["rec"]["rules_hit"] for r in recs) / len(recs)
+        log(f"hit rate {hit_rate:.3f} (rules {rules_hit_rate:.3f}), geomean slowdown "
+            f"{np.exp(np.mean(np.log(slow))):.4f}")
 
     # ---- CPU oracle baseline on a bounded sample of the same workload
     cpu = None
@@ -254,6 +262,7 @@ def main():
         "plain_csr_gflops": round(flops / (plain_ms_step * 1e-3) / 1e9, 3) if plain_ms_step else None,
         "tuned_vs_plain": round(speedup, 4) if speedup else None,
         "hit_rate": round(hit_rate, 4) if hit_rate is not None else None,
+        "rules_hit_rate": round(rules_hit_rate, 4) if hit_rate is not None else None,
         "plan_cost_plain_csr_units_median": round(float(np.median(plan_units)), 2) if plan_units else None,
         "roofline": {"bound": "hbm", "kernel": f"{dominant[0]} ({dominant[1]})",
                      "achieved": round(dom_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",

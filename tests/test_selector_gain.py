@@ -1,0 +1,78 @@
+"""What the learned selector gains over the rule-based method.
+
+CPU part: the committed held-out timing tables (every feasible kernel timed
+on MI355X for 500 seeded matrices x {float32, float64}, never used in
+training) are scored by the committed network through the float64 oracle
+forward pass, independently of the GPU inference kernel.  A choice is a hit
+when its measured time is within 5% of the exhaustive best.
+
+GPU part: a fresh sample is planned live with the network and with the rules
+and both choices are judged against exhaustive timing in the same session.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mlp as OM
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+WEIGHTS = os.path.join(ROOT, "paper_1210_2536_amd", "weights", "selector_gfx950.json")
+HELD = os.path.join(ROOT, "paper_1210_2536_amd", "data", "heldout_0000_0500.npz")
+
+
+def _hit(choice, times):
+    best = times.min(axis=1)
+    return times[np.arange(len(times)), choice] <= 1.05 * best
+
+
+def test_network_beats_rules_on_heldout_tables():
+    with open(WEIGHTS) as fh:
+        w = json.load(fh)
+    d = np.load(HELD)
+    times, raw, rules = d["times"], d["raw"], d["rules"]
+    assert len(times) == 1000
+    C = w["n_out"]
+    params = OM.unflatten(np.array(w["params"], dtype=np.float64), C)
+    z = OM.preprocess(raw.astype(np.float64), np.array(w["mean"]), np.array(w["std"]))
+    s, _ = OM.forward(params, z)
+    s = np.where(np.isfinite(times), s, np.inf)
+    mlp_choice = s.argmin(axis=1)
+    mlp_hits = _hit(mlp_choice, times)
+    rule_hits = _hit(rules, times)
+    # the selector target: within 5% of exhaustive best on >= 90% of matrices
+    assert mlp_hits.mean() >= 0.90, mlp_hits.mean()
+    assert mlp_hits.mean() >= rule_hits.mean() + 0.3, (mlp_hits.mean(), rule_hits.mean())
+    slow_mlp = np.exp(np.mean(np.log(times[np.arange(len(times)), mlp_choice] / times.min(1))))
+    slow_rules = np.exp(np.mean(np.log(times[np.arange(len(times)), rules] / times.min(1))))
+    assert slow_mlp < slow_rules
+    print(f"held-out hit rate: network {mlp_hits.mean():.3f}, rules {rule_hits.mean():.3f}; "
+          f"geomean slowdown {slow_mlp:.4f} vs {slow_rules:.4f}")
+
+
+@pytest.mark.gpu
+def test_live_selection_network_vs_rules():
+    import torch
+    from paper_1210_2536_amd import capi, synth
+    from paper_1210_2536_amd.spmv import Plan, Selector
+    sel = Selector.load(WEIGHTS)
+    hits_mlp = hits_rules = total = 0
+    for i in range(24):
+        # held-out seeds beyond the committed tables, moderate sizes
+        A = synth.selector_matrix(10_000 + i, heldout=True, nnz_cap=4_000_000, n_hi=5.5)
+        for dt in (np.float32, np.float64):
+            rp = torch.from_numpy(A.row_ptr.astype(np.int32)).cuda()
+            col = torch.from_numpy(A.col).cuda()
+            val = torch.from_numpy(A.val.astype(dt)).cuda()
+            ex = Plan(rp, col, val, n=A.n, selector="exhaustive", reps=9).info()
+            nm = ex["n_measured"]
+            table = dict(zip(ex["measured_kernel"][:nm], ex["measured_ms"][:nm]))
+            best = min(table.values())
+            pm = Plan(rp, col, val, n=A.n, selector="mlp", model=sel, tau=0.0).info()
+            hits_mlp += table[pm["kernel"]] <= 1.05 * best
+            hits_rules += table[ex["rules_kernel"]] <= 1.05 * best
+            total += 1
+    print(f"live hit rate: network {hits_mlp / total:.3f}, rules {hits_rules / total:.3f}")
+    assert hits_mlp >= hits_rules
+    assert hits_mlp / total >= 0.7
