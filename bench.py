@@ -120,13 +120,31 @@ def main():
         r["rec"]["tuned_ms"] = time_run(r["tuned"], r["x"], r["y"])
         if r["plain"] is not None:
             r["rec"]["plain_ms"] = time_run(r["plain"], r["x"], r["y"])
-    cls_time = {}
+    # Kernel symbol of each plan: the compiled kernel it launches (format
+    # kernel, value type and the template parameters of its launch).
+    def symbol(rec):
+        p, k = rec["params"], rec["kernel"]
+        t = "double" if rec["dtype"] == "float64" else "float"
+        nt = "true" if p["stream_nt"] == 1 else "false"
+        if k == "csr_vector":
+            return f"k_csr_vector<{t}, {p['vector_lanes']}, {nt}>"
+        if k == "csr_adaptive":
+            return f"k_csr_adaptive<{t}, {nt}>"
+        if k == "ell":
+            return f"k_ell<{t}, {p['ell_unroll']}, {nt}>"
+        if k in ("dia", "dia_direct"):
+            return f"k_{'dia_lds' if k == 'dia' else 'dia_direct'}<{t}, {p['dia_rows_per_thread']}, {nt}>"
+        if k == "coo":
+            return f"k_coo<{t}, {nt}> + k_coo_fixup<{t}>"
+        return f"k_csr_scalar<{t}>"
+
+    sym_time = {}
     for r in recs:
-        key = (r["rec"]["kernel"], r["rec"]["dtype"])
-        cls_time[key] = cls_time.get(key, 0.0) + r["rec"]["tuned_ms"]
-    dominant = max(cls_time, key=cls_time.get)
-    log(f"dominant kernel class {dominant}: {cls_time[dominant]:.3f} ms of "
-        f"{sum(cls_time.values()):.3f} ms per step")
+        r["rec"]["symbol"] = symbol(r["rec"])
+        sym_time[r["rec"]["symbol"]] = sym_time.get(r["rec"]["symbol"], 0.0) + r["rec"]["tuned_ms"]
+    dominant = max(sym_time, key=sym_time.get)
+    log(f"dominant kernel {dominant}: {sym_time[dominant]:.3f} ms of "
+        f"{sum(sym_time.values()):.3f} ms per step")
 
     # ---- timed region: K steps of every tuned SpMV
     def steps(which, K, events=False):
@@ -134,7 +152,7 @@ def main():
         for _ in range(K):
             for r in recs:
                 p = r[which]
-                if events and (r["rec"]["kernel"], r["rec"]["dtype"]) == dominant:
+                if events and r["rec"]["symbol"] == dominant:
                     e0 = torch.cuda.Event(enable_timing=True)
                     e1 = torch.cuda.Event(enable_timing=True)
                     e0.record()
@@ -284,7 +302,7 @@ def main():
         "hit_rate": round(hit_rate, 4) if hit_rate is not None else None,
         "rules_hit_rate": round(rules_hit_rate, 4) if hit_rate is not None else None,
         "plan_cost_plain_csr_units_median": round(float(np.median(plan_units)), 2) if plan_units else None,
-        "roofline": {"bound": "hbm", "kernel": f"{dominant[0]} ({dominant[1]})",
+        "roofline": {"bound": "hbm", "kernel": dominant, "launches_per_step": len(evs) // a.steps,
                      "achieved": round(dom_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(dom_achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "avg_launch_ms": round(dom_avg_ms, 5),
