@@ -65,7 +65,9 @@ typedef enum {
     SPMV_K_DIA = 4,           /* DIA, x windows staged in LDS                   */
     SPMV_K_DIA_DIRECT = 5,    /* DIA, x read through the caches                 */
     SPMV_K_COO = 6,           /* COO, wavefront segmented reduction             */
-    SPMV_K_COUNT = 7
+    SPMV_K_CSR_PANEL = 7,     /* CSR cut into column panels whose slice of x
+                                 fits in L2, one binned launch per panel     */
+    SPMV_K_COUNT = 8
 } spmv_kernel;
 
 /* How plan creation chooses the kernel (Section 6). */
@@ -103,8 +105,10 @@ typedef struct {
     int32_t coo_chunk;          /* COO: entries per lane per wavefront chunk  */
     int32_t ell_unroll;         /* ELL: slots fetched per loop trip (1, 2, 4) */
     int32_t stream_nt;          /* matrix arrays loaded non-temporally: 1 on,
-                                   2 off (0 = default: on when the matrix is
-                                   DIA-feasible, i.e. banded)                */
+                                   2 off (0 = default: on for ELL and DIA of
+                                   banded matrices, off otherwise)           */
+    int32_t panel_kib;          /* CSR_PANEL: bytes of x per column panel, in
+                                   KiB (default 2048)                        */
 } spmv_params;
 
 typedef struct spmv_selector_s *spmv_selector_t;

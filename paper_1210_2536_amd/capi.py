@@ -14,9 +14,11 @@ LIB_PATH = os.environ.get("SMAT_SPMV_LIB") or os.path.join(HERE, "libsmat_spmv.s
 
 SPMV_F32, SPMV_F64 = 0, 1
 SPMV_OK, SPMV_EINVAL, SPMV_ENOMEM, SPMV_EDEVICE, SPMV_EUNSUPPORTED = 0, -1, -2, -3, -4
-KERNELS = ("csr_scalar", "csr_vector", "csr_adaptive", "ell", "dia", "dia_direct", "coo")
-K_CSR_SCALAR, K_CSR_VECTOR, K_CSR_ADAPTIVE, K_ELL, K_DIA, K_DIA_DIRECT, K_COO = range(7)
-K_COUNT = 7
+KERNELS = ("csr_scalar", "csr_vector", "csr_adaptive", "ell", "dia", "dia_direct", "coo",
+           "csr_panel")
+K_CSR_SCALAR, K_CSR_VECTOR, K_CSR_ADAPTIVE, K_ELL, K_DIA, K_DIA_DIRECT, K_COO, K_CSR_PANEL = \
+    range(8)
+K_COUNT = 8
 FORMATS = ("csr", "coo", "ell", "dia")
 SELECT_RULES, SELECT_MLP, SELECT_EXHAUSTIVE, SELECT_FORCED = range(4)
 
@@ -33,7 +35,8 @@ class spmv_csr(ctypes.Structure):
 class spmv_params(ctypes.Structure):
     _fields_ = [("block", i32), ("vector_lanes", i32), ("adaptive_rows_per_lane", i32),
                 ("adaptive_wg_min", i32), ("dia_rows_per_thread", i32), ("dia_span", i32),
-                ("coo_chunk", i32), ("ell_unroll", i32), ("stream_nt", i32)]
+                ("coo_chunk", i32), ("ell_unroll", i32), ("stream_nt", i32),
+                ("panel_kib", i32)]
 
 
 class spmv_plan_opts(ctypes.Structure):

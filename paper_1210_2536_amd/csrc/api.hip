@@ -218,8 +218,18 @@ spmv_params default_params(int kernel, const spmv_features &F) {
     p.coo_chunk = F.nnz >= (8 << 20) ? 8 : F.nnz >= (1 << 20) ? 4 : 2;
     p.ell_unroll = 4;
     p.stream_nt = 0;  // resolved per kernel by resolve_params
+    p.panel_kib = 2048;
     (void)kernel;
     return p;
+}
+
+// Column-panel geometry: width w columns (x bytes per panel <= panel_kib KiB,
+// a multiple of 64 columns) and panel count P.
+void panel_geometry(const spmv_features &F, int elt, const spmv_params &p, int64_t *w, int *P) {
+    int64_t width = ((int64_t)p.panel_kib * 1024 / elt) / 64 * 64;
+    if (width < 64) width = 64;
+    *w = width;
+    *P = (int)std::min<int64_t>((F.n + width - 1) / width, 1 << 20);
 }
 
 // Fill in the per-kernel defaults left open (0) in `p`.  Streaming loads pay
@@ -246,6 +256,7 @@ void merge_params(spmv_params &p, const spmv_params &u) {
     if (u.coo_chunk > 0) p.coo_chunk = u.coo_chunk;
     if (u.ell_unroll > 0) p.ell_unroll = u.ell_unroll;
     if (u.stream_nt > 0) p.stream_nt = u.stream_nt;
+    if (u.panel_kib > 0) p.panel_kib = u.panel_kib;
 }
 
 spmv_status check_params(const spmv_params &p) {
@@ -279,6 +290,10 @@ spmv_status check_params(const spmv_params &p) {
     }
     if (p.stream_nt < 0 || p.stream_nt > 2) {
         set_error("params.stream_nt must be 0 (default), 1 (on) or 2 (off)");
+        return SPMV_EINVAL;
+    }
+    if (p.panel_kib < 1 || p.panel_kib > (1 << 20)) {
+        set_error("params.panel_kib must be in [1, 2^20]");
         return SPMV_EINVAL;
     }
     return SPMV_OK;
@@ -319,6 +334,20 @@ uint32_t feasible_mask(const spmv_features &F, int dtype, int64_t m_pad, uint64_
     {
         int64_t per = (int64_t)p.coo_chunk * kWave;
         if (!f64 || F.max_rd <= kCooMaxChunksPerRow * per) mask |= 1u << SPMV_K_COO;
+    }
+    {
+        // Column panels pay off only when x does not fit one panel; float32
+        // rounds the running sum once per panel, so at most 16 panels keep
+        // it inside 2e-6 (|A||x|)_i; no row may need splitting.
+        int64_t w;
+        int P;
+        panel_geometry(F, elt, p, &w, &P);
+        uint64_t bytes = (uint64_t)F.nnz * (uint64_t)(elt + 4) +
+                         (uint64_t)P * (uint64_t)(F.m + 1) * 4u;
+        bool ok = P >= 2 && F.nnz > 0 && F.max_rd <= kSplitMin && bytes <= cap &&
+                  (uint64_t)P * (uint64_t)(F.m + 1) < (1ull << 31);
+        if (dtype == SPMV_F32 && P > 16) ok = false;
+        if (ok) mask |= 1u << SPMV_K_CSR_PANEL;
     }
     return mask;
 }
@@ -441,7 +470,15 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
         SMAT_HIP(hipStreamSynchronize(s));
         return SPMV_OK;
     }
-    case SPMV_K_CSR_ADAPTIVE: {
+    case SPMV_K_CSR_ADAPTIVE:
+    case SPMV_K_CSR_PANEL: {
+        const bool panels = kernel == SPMV_K_CSR_PANEL;
+        int shift = 0;
+        if (panels) {
+            panel_geometry(F, elt, prm, &V.panel_w, &V.P);
+            while ((2 << shift) <= V.P && shift < 6) ++shift;  // floor(log2 P)
+        }
+        V.alaunch.lane_shift = shift;
         BinSpec spec;
         const int rpl = prm.adaptive_rows_per_lane;
         for (int b = 0; b < 6; ++b) {  // widths 1..32
@@ -469,7 +506,7 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
                 int b = 7 - q;
                 V.alaunch.first[q] = blocks;
                 unsigned cnt = V.bin_off[b + 1] - V.bin_off[b];
-                unsigned per = b == 7 ? 1u : (unsigned)(256 >> b);
+                unsigned per = b == 7 ? 1u : (unsigned)(256 >> std::max(0, b - shift));
                 blocks += (cnt + per - 1) / per;
             }
             V.alaunch.first[8] = blocks;
@@ -514,6 +551,27 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
             SMAT_HIP(hipStreamSynchronize(s));
         }
         V.bin_scratch.release();
+        if (panels) {
+            if (ns > 0) {
+                set_error("column panels cannot hold rows longer than %lld entries",
+                          (long long)kSplitMin);
+                return SPMV_EUNSUPPORTED;
+            }
+            const int64_t L = (int64_t)V.P * (m + 1);
+            Dev inv, cnt, scan;
+            SMAT_TRY(inv.alloc(sizeof(int32_t) * std::max<int64_t>(1, m)));
+            SMAT_TRY(cnt.alloc(sizeof(int32_t) * (size_t)L));
+            SMAT_TRY(scan.alloc(sizeof(unsigned) * (size_t)(L / 4096 + 2)));
+            SMAT_TRY(V.prow.alloc(sizeof(int32_t) * (size_t)(L + 1)));
+            SMAT_TRY(V.pcol.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(1, nnz)));
+            SMAT_TRY(V.pval.alloc((size_t)elt * (size_t)std::max<int64_t>(1, nnz)));
+            SMAT_TRY(launch_csr_to_panels(m, nnz, P.rp.as<int32_t>(), P.col.as<int32_t>(), P.val.p,
+                                          elt, V.bin_rows.as<int32_t>(), V.P, V.panel_w,
+                                          inv.as<int32_t>(), cnt.as<int32_t>(),
+                                          V.prow.as<int32_t>(), scan.as<unsigned>(),
+                                          V.pcol.as<int32_t>(), V.pval.p, s));
+            SMAT_HIP(hipStreamSynchronize(s));
+        }
         return SPMV_OK;
     }
     default:
@@ -545,6 +603,9 @@ spmv_status run_variant(const spmv_plan_s &P, const Variant &V, const void *x, v
                                    P.col.as<int32_t>(), P.val.p, x, y, s));
         return SPMV_OK;
     }
+    case SPMV_K_CSR_PANEL:
+        return run_csr_panels(elt, nt, V.alaunch, V.bin_rows.as<int32_t>(), V.P, m,
+                              V.prow.as<int32_t>(), V.pcol.as<int32_t>(), V.pval.p, x, y, s);
     case SPMV_K_ELL:
         return run_ell(elt, nt, m, P.m_pad, V.K, V.ecol.as<int32_t>(), V.eval.p, x, y,
                        V.prm.block, V.prm.ell_unroll, s);
@@ -663,6 +724,19 @@ std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_
                     add(p);
                 }
         break;
+    case SPMV_K_CSR_PANEL:
+        for (int kib : {512, 1024, 2048, 4096})
+            for (int nt : nts) {
+                spmv_params p = b;
+                p.panel_kib = kib;
+                p.stream_nt = nt;
+                int64_t w;
+                int P;
+                panel_geometry(F, dtype == SPMV_F64 ? 8 : 4, p, &w, &P);
+                if (P < 2 || (dtype == SPMV_F32 && P > 16)) continue;
+                add(p);
+            }
+        break;
     case SPMV_K_COO:
         for (int c : {2, 4, 8, 16})
             for (int nt : nts) {
@@ -736,7 +810,7 @@ extern "C" const char *spmv_last_error(void) { return g_err; }
 
 extern "C" const char *spmv_kernel_name(int32_t k) {
     static const char *names[] = {"csr_scalar", "csr_vector", "csr_adaptive", "ell",
-                                  "dia",        "dia_direct", "coo"};
+                                  "dia",        "dia_direct", "coo",          "csr_panel"};
     return (k >= 0 && k < SPMV_K_COUNT) ? names[k] : "invalid";
 }
 
@@ -978,7 +1052,7 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
     }
     auto t_end = std::chrono::steady_clock::now();
     I.kernel = chosen;
-    I.format = (chosen <= SPMV_K_CSR_ADAPTIVE) ? SPMV_FMT_CSR
+    I.format = (chosen <= SPMV_K_CSR_ADAPTIVE || chosen == SPMV_K_CSR_PANEL) ? SPMV_FMT_CSR
                : chosen == SPMV_K_ELL          ? SPMV_FMT_ELL
                : chosen == SPMV_K_COO          ? SPMV_FMT_COO
                                                : SPMV_FMT_DIA;
@@ -1079,6 +1153,11 @@ extern "C" spmv_status spmv_convert_roundtrip(spmv_plan_t P, int32_t *rp, int32_
         SMAT_TRY(launch_ell_to_csr(m, P->m_pad, V.K, V.ecol.as<int32_t>(), V.eval.p, elt, rp, col,
                                    val, counts.as<int32_t>(), scan.as<unsigned>(), s));
         break;
+    case SPMV_K_CSR_PANEL:
+        SMAT_TRY(launch_panels_to_csr(m, V.bin_rows.as<int32_t>(), V.P, V.prow.as<int32_t>(),
+                                      V.pcol.as<int32_t>(), V.pval.p, elt, rp, col, val,
+                                      counts.as<int32_t>(), scan.as<unsigned>(), s));
+        break;
     case SPMV_K_DIA:
     case SPMV_K_DIA_DIRECT:
         SMAT_TRY(launch_dia_to_csr(m, P->n, P->m_pad, V.D, V.dia_off.as<int32_t>(), V.dia_data.p,
@@ -1122,7 +1201,7 @@ extern "C" spmv_status spmv_plan_export(spmv_plan_t P, int32_t which, void *dst,
         if (V.kernel == SPMV_K_DIA || V.kernel == SPMV_K_DIA_DIRECT) { src = V.dia_present.p; n = sizeof(uint32_t) * (((size_t)V.D * P->m_pad + 31) / 32); }
         break;
     case 6:
-        if (V.kernel == SPMV_K_CSR_ADAPTIVE) { src = V.bin_rows.p; n = sizeof(int32_t) * P->m; }
+        if (V.kernel == SPMV_K_CSR_ADAPTIVE || V.kernel == SPMV_K_CSR_PANEL) { src = V.bin_rows.p; n = sizeof(int32_t) * P->m; }
         break;
     default:
         break;

@@ -117,10 +117,27 @@ spmv_status run_csr_vector(int elt, bool nt, int lanes, int64_t nrows, const int
 struct AdaptiveLaunch {
     unsigned first[9];
     unsigned row_begin[9];
+    int lane_shift;   // column panels: lane width of bin b is 2^max(0, b - shift)
 };
 spmv_status run_csr_adaptive(int elt, bool nt, const AdaptiveLaunch &a, const int32_t *rows,
                              const int32_t *rp, const int32_t *col, const void *val,
                              const void *x, void *y, hipStream_t s);
+// Column panels: P launches; prow is P x (m+1) position-indexed segment starts.
+spmv_status run_csr_panels(int elt, bool nt, const AdaptiveLaunch &a, const int32_t *rows, int P,
+                           int64_t m, const int32_t *prow, const int32_t *pcol, const void *pval,
+                           const void *x, void *y, hipStream_t s);
+// Build column panels of width w from a CSR matrix whose rows are visited in
+// the binned order `rows`.  cnt: P*(m+1) ints; prow: P*(m+1)+1 ints; inv: m
+// ints; scan: P*(m+1)/4096+1 unsigned.
+spmv_status launch_csr_to_panels(int64_t m, int64_t nnz, const int32_t *rp, const int32_t *col,
+                                 const void *val, int elt, const int32_t *rows, int P, int64_t w,
+                                 int32_t *inv, int32_t *cnt, int32_t *prow, unsigned *scan,
+                                 int32_t *pcol, void *pval, hipStream_t s);
+// Inverse: rebuild CSR (row_ptr m+1, col, val) from the panels.
+spmv_status launch_panels_to_csr(int64_t m, const int32_t *rows, int P, const int32_t *prow,
+                                 const int32_t *pcol, const void *pval, int elt, int32_t *rp,
+                                 int32_t *col, void *val, int32_t *counts, unsigned *scan,
+                                 hipStream_t s);
 // split rows: segments (row, begin, end) reduce into partials, then fix-up
 spmv_status run_csr_split(int elt, int64_t nseg, const int64_t *segs, double *partials,
                           int64_t nrows, const int64_t *row_seg_begin, const int32_t *rows,

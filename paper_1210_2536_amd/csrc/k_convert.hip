@@ -169,6 +169,101 @@ __global__ void k_dia_gather(int64_t m, int64_t m_pad, int D, const int32_t *__r
     }
 }
 
+// ---- column panels (cache blocking of x)
+// first index in [b, e) whose column is >= v (columns sorted within a row)
+__device__ __forceinline__ int32_t col_lower_bound(const int32_t *__restrict__ col, int32_t b,
+                                                   int32_t e, int64_t v) {
+    while (b < e) {
+        int32_t mid = b + ((e - b) >> 1);
+        if ((int64_t)col[mid] < v)
+            b = mid + 1;
+        else
+            e = mid;
+    }
+    return b;
+}
+
+__global__ void k_inverse_perm(int64_t m, const int32_t *__restrict__ rows,
+                               int32_t *__restrict__ inv) {
+    int64_t pos = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (pos < m) inv[rows[pos]] = (int32_t)pos;
+}
+
+// cnt[p*(m+1) + pos] = entries of row rows[pos] in panel p; position m is a
+// zero pad so one exclusive scan over the whole array yields every panel's
+// segment starts and, at position m, the panel's end.
+__global__ void k_panel_count(int64_t m, const int32_t *__restrict__ rp,
+                              const int32_t *__restrict__ col, const int32_t *__restrict__ rows,
+                              int P, int64_t w, int32_t *__restrict__ cnt) {
+    int64_t pos = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (pos > m) return;
+    if (pos == m) {
+        for (int p = 0; p < P; ++p) cnt[(int64_t)p * (m + 1) + m] = 0;
+        return;
+    }
+    int64_t row = rows[pos];
+    int32_t b = rp[row], e = rp[row + 1];
+    int32_t prev = b;
+    for (int p = 0; p < P; ++p) {
+        int32_t next = p == P - 1 ? e : col_lower_bound(col, prev, e, (int64_t)(p + 1) * w);
+        cnt[(int64_t)p * (m + 1) + pos] = next - prev;
+        prev = next;
+    }
+}
+
+template <typename U>
+__global__ void k_panel_scatter(int64_t m, int64_t nnz, const int32_t *__restrict__ rp,
+                                const int32_t *__restrict__ col, const U *__restrict__ val,
+                                const int32_t *__restrict__ inv, int64_t w,
+                                const int32_t *__restrict__ prow, int32_t *__restrict__ pcol,
+                                U *__restrict__ pval) {
+    int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    int64_t p0 = t * kEntryRun;
+    if (p0 >= nnz) return;
+    int64_t p1 = p0 + kEntryRun < nnz ? p0 + kEntryRun : nnz;
+    int64_t row = row_of_entry(rp, m, p0);
+    int64_t rend = rp[row + 1];
+    for (int64_t p = p0; p < p1; ++p) {
+        while (p >= rend) rend = rp[++row + 1];
+        int32_t c = col[p];
+        int64_t panel = c / w;
+        int32_t seg = col_lower_bound(col, rp[row], (int32_t)rend, panel * w);
+        int64_t dst = prow[panel * (m + 1) + inv[row]] + (p - seg);
+        pcol[dst] = c;
+        pval[dst] = val[p];
+    }
+}
+
+__global__ void k_panel_rowcount(int64_t m, const int32_t *__restrict__ rows, int P,
+                                 const int32_t *__restrict__ prow, int32_t *__restrict__ counts) {
+    int64_t pos = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (pos >= m) return;
+    int32_t tot = 0;
+    for (int p = 0; p < P; ++p) {
+        const int32_t *pr = prow + (int64_t)p * (m + 1);
+        tot += pr[pos + 1] - pr[pos];
+    }
+    counts[rows[pos]] = tot;
+}
+
+template <typename U>
+__global__ void k_panel_gather(int64_t m, const int32_t *__restrict__ rows, int P,
+                               const int32_t *__restrict__ prow, const int32_t *__restrict__ pcol,
+                               const U *__restrict__ pval, const int32_t *__restrict__ rp,
+                               int32_t *__restrict__ col, U *__restrict__ val) {
+    int64_t pos = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (pos >= m) return;
+    int64_t o = rp[rows[pos]];
+    for (int p = 0; p < P; ++p) {
+        const int32_t *pr = prow + (int64_t)p * (m + 1);
+        for (int32_t j = pr[pos]; j < pr[pos + 1]; ++j) {
+            col[o] = pcol[j];
+            val[o] = pval[j];
+            ++o;
+        }
+    }
+}
+
 // ---- row binning: bin b holds rows with upper[b-1] < len <= upper[b]
 __device__ __forceinline__ int bin_of(int len, const BinSpec &spec) {
     int b = 0;
@@ -334,6 +429,49 @@ spmv_status launch_dia_to_csr(int64_t m, int64_t n, int64_t m_pad, int D, const 
         k_dia_gather<uint32_t><<<grid_for(m, kBlock), kBlock, 0, s>>>(
             m, m_pad, D, offs, (const uint32_t *)data, present, rp, col, (uint32_t *)val);
     SMAT_LAUNCHED("dia_gather");
+    return SPMV_OK;
+}
+
+spmv_status launch_csr_to_panels(int64_t m, int64_t nnz, const int32_t *rp, const int32_t *col,
+                                 const void *val, int elt, const int32_t *rows, int P, int64_t w,
+                                 int32_t *inv, int32_t *cnt, int32_t *prow, unsigned *scan,
+                                 int32_t *pcol, void *pval, hipStream_t s) {
+    if (m == 0) return SPMV_OK;
+    k_inverse_perm<<<grid_for(m, kBlock), kBlock, 0, s>>>(m, rows, inv);
+    SMAT_LAUNCHED("inverse_perm");
+    k_panel_count<<<grid_for(m + 1, kBlock), kBlock, 0, s>>>(m, rp, col, rows, P, w, cnt);
+    SMAT_LAUNCHED("panel_count");
+    spmv_status st = launch_exclusive_scan_rows((int64_t)P * (m + 1), cnt, prow, scan, s);
+    if (st != SPMV_OK) return st;
+    if (nnz == 0) return SPMV_OK;
+    unsigned g = grid_for((nnz + kEntryRun - 1) / kEntryRun, kBlock);
+    if (elt == 8)
+        k_panel_scatter<uint64_t><<<g, kBlock, 0, s>>>(m, nnz, rp, col, (const uint64_t *)val, inv,
+                                                       w, prow, pcol, (uint64_t *)pval);
+    else
+        k_panel_scatter<uint32_t><<<g, kBlock, 0, s>>>(m, nnz, rp, col, (const uint32_t *)val, inv,
+                                                       w, prow, pcol, (uint32_t *)pval);
+    SMAT_LAUNCHED("panel_scatter");
+    return SPMV_OK;
+}
+
+spmv_status launch_panels_to_csr(int64_t m, const int32_t *rows, int P, const int32_t *prow,
+                                 const int32_t *pcol, const void *pval, int elt, int32_t *rp,
+                                 int32_t *col, void *val, int32_t *counts, unsigned *scan,
+                                 hipStream_t s) {
+    if (m > 0) {
+        k_panel_rowcount<<<grid_for(m, kBlock), kBlock, 0, s>>>(m, rows, P, prow, counts);
+        SMAT_LAUNCHED("panel_rowcount");
+    }
+    spmv_status st = launch_exclusive_scan_rows(m, counts, rp, scan, s);
+    if (st != SPMV_OK || m == 0) return st;
+    if (elt == 8)
+        k_panel_gather<uint64_t><<<grid_for(m, kBlock), kBlock, 0, s>>>(
+            m, rows, P, prow, pcol, (const uint64_t *)pval, rp, col, (uint64_t *)val);
+    else
+        k_panel_gather<uint32_t><<<grid_for(m, kBlock), kBlock, 0, s>>>(
+            m, rows, P, prow, pcol, (const uint32_t *)pval, rp, col, (uint32_t *)val);
+    SMAT_LAUNCHED("panel_gather");
     return SPMV_OK;
 }
 

@@ -109,6 +109,69 @@ __global__ __launch_bounds__(kAdaptBlock) void k_csr_adaptive(AdaptiveLaunch a,
     }
 }
 
+// ---------------------------------------------------------------- CSR panels
+// Cache blocking of x for matrices whose columns are spread over an x too
+// large for L2: the columns are cut into P panels whose slice of x fits in
+// L2; one launch per panel adds that panel's part of every row to y (ACC
+// after the first panel), so the random column gathers hit L2 instead of
+// the next level.  Rows keep the length-binned order and lane widths of the
+// adaptive kernel, scaled down by the panel count (lane_shift); prow holds,
+// per panel and per binned position, the start of that row's segment.
+template <typename T, int L, bool NT, bool ACC>
+__device__ __forceinline__ void panel_lanes(unsigned local, unsigned rbeg, unsigned rend,
+                                            const int32_t *__restrict__ rows,
+                                            const int32_t *__restrict__ prow,
+                                            const int32_t *__restrict__ col,
+                                            const T *__restrict__ val, const T *__restrict__ x,
+                                            T *__restrict__ y) {
+    int64_t r = (int64_t)rbeg + (int64_t)local * (kAdaptBlock / L) + threadIdx.x / L;
+    int lane = threadIdx.x & (L - 1);
+    if (r < rend) {
+        double acc = lanes_sum<T, L, NT>(prow[r], prow[r + 1], lane, col, val, x);
+        if (lane == 0) {
+            int64_t row = rows[r];
+            y[row] = ACC ? (T)((double)y[row] + acc) : (T)acc;
+        }
+    }
+}
+
+template <typename T, bool NT, bool ACC>
+__global__ __launch_bounds__(kAdaptBlock) void k_csr_panel(AdaptiveLaunch a,
+                                                           const int32_t *__restrict__ rows,
+                                                           const int32_t *__restrict__ prow,
+                                                           const int32_t *__restrict__ col,
+                                                           const T *__restrict__ val,
+                                                           const T *__restrict__ x,
+                                                           T *__restrict__ y) {
+    __shared__ double part[kAdaptBlock / kWave];
+    const unsigned bid = blockIdx.x;
+    int q = 0;
+    while (q < 7 && bid >= a.first[q + 1]) ++q;
+    const int b = 7 - q;
+    const unsigned local = bid - a.first[q];
+    const unsigned rb = a.row_begin[b], re = a.row_begin[b + 1];
+    if (b == 7) {
+        const unsigned r = rb + local;
+        double s = block_sum<T, kAdaptBlock, NT>(prow[r], prow[r + 1], col, val, x, part);
+        if (threadIdx.x == 0) {
+            int64_t row = rows[r];
+            y[row] = ACC ? (T)((double)y[row] + s) : (T)s;
+        }
+        return;
+    }
+    int lb = b - a.lane_shift;
+    lb = lb < 0 ? 0 : lb;
+    switch (lb) {
+    case 6: panel_lanes<T, 64, NT, ACC>(local, rb, re, rows, prow, col, val, x, y); break;
+    case 5: panel_lanes<T, 32, NT, ACC>(local, rb, re, rows, prow, col, val, x, y); break;
+    case 4: panel_lanes<T, 16, NT, ACC>(local, rb, re, rows, prow, col, val, x, y); break;
+    case 3: panel_lanes<T, 8, NT, ACC>(local, rb, re, rows, prow, col, val, x, y); break;
+    case 2: panel_lanes<T, 4, NT, ACC>(local, rb, re, rows, prow, col, val, x, y); break;
+    case 1: panel_lanes<T, 2, NT, ACC>(local, rb, re, rows, prow, col, val, x, y); break;
+    default: panel_lanes<T, 1, NT, ACC>(local, rb, re, rows, prow, col, val, x, y); break;
+    }
+}
+
 // Rows longer than one workgroup may sum alone: segments of a row reduce to
 // partials (one workgroup each), then one thread per row adds them in order.
 template <typename T>
@@ -413,7 +476,38 @@ spmv_status adaptive_dispatch(bool nt, const AdaptiveLaunch &a, const int32_t *r
     return SPMV_OK;
 }
 
+template <typename T, bool NT>
+spmv_status panel_dispatch(const AdaptiveLaunch &a, const int32_t *rows, int P, int64_t m,
+                           const int32_t *prow, const int32_t *pcol, const T *pval, const T *x,
+                           T *y, hipStream_t s) {
+    const unsigned nblk = a.first[8];
+    if (nblk == 0) return SPMV_OK;
+    for (int p = 0; p < P; ++p) {
+        const int32_t *pr = prow + (int64_t)p * (m + 1);
+        if (p == 0)
+            k_csr_panel<T, NT, false><<<nblk, kAdaptBlock, 0, s>>>(a, rows, pr, pcol, pval, x, y);
+        else
+            k_csr_panel<T, NT, true><<<nblk, kAdaptBlock, 0, s>>>(a, rows, pr, pcol, pval, x, y);
+        SMAT_LAUNCHED("csr_panel");
+    }
+    return SPMV_OK;
+}
+
 }  // namespace
+
+spmv_status run_csr_panels(int elt, bool nt, const AdaptiveLaunch &a, const int32_t *rows, int P,
+                           int64_t m, const int32_t *prow, const int32_t *pcol, const void *pval,
+                           const void *x, void *y, hipStream_t s) {
+    if (elt == 8)
+        return nt ? panel_dispatch<double, true>(a, rows, P, m, prow, pcol, (const double *)pval,
+                                                 (const double *)x, (double *)y, s)
+                  : panel_dispatch<double, false>(a, rows, P, m, prow, pcol, (const double *)pval,
+                                                  (const double *)x, (double *)y, s);
+    return nt ? panel_dispatch<float, true>(a, rows, P, m, prow, pcol, (const float *)pval,
+                                            (const float *)x, (float *)y, s)
+              : panel_dispatch<float, false>(a, rows, P, m, prow, pcol, (const float *)pval,
+                                             (const float *)x, (float *)y, s);
+}
 
 // Typed entry points: elt selects float (4) or double (8), nt the streaming
 // cache policy.

@@ -54,12 +54,16 @@ struct Variant {
     unsigned bin_off[kAdaptiveBins + 1] = {};
     int bin_lanes[kAdaptiveBins] = {};
     AdaptiveLaunch alaunch{};
+    // CSR column panels
+    Dev prow, pcol, pval;
+    int P = 0;
+    int64_t panel_w = 0;
     int64_t nsplit_rows = 0, nsplit_segs = 0;
     uint64_t bytes() const {
         return row_idx.bytes + coo_head.bytes + coo_tail.bytes + coo_flags.bytes + ecol.bytes +
                eval.bytes + dia_off.bytes + dia_data.bytes + dia_present.bytes + dia_win.bytes +
                bin_rows.bytes + bin_scratch.bytes + split_segs.bytes + split_partials.bytes +
-               split_begin.bytes + split_rows.bytes;
+               split_begin.bytes + split_rows.bytes + prow.bytes + pcol.bytes + pval.bytes;
     }
 };
 

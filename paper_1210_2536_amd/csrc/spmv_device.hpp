@@ -36,12 +36,10 @@ __device__ __forceinline__ double csr_row_seq(int64_t i, const int32_t *__restri
 // CSR row by a group of L lanes (lane = 0..L-1); lanes stride the row and
 // reduce by xor shuffles.  Every lane of the group returns the row sum.
 template <typename T, int L, bool NT>
-__device__ __forceinline__ double csr_row_lanes(int64_t row, int lane,
-                                                const int32_t *__restrict__ rp,
-                                                const int32_t *__restrict__ col,
-                                                const T *__restrict__ val,
-                                                const T *__restrict__ x) {
-    int32_t b = rp[row], e = rp[row + 1];
+__device__ __forceinline__ double lanes_sum(int32_t b, int32_t e, int lane,
+                                            const int32_t *__restrict__ col,
+                                            const T *__restrict__ val,
+                                            const T *__restrict__ x) {
     double acc = 0.0;
 #pragma unroll 4
     for (int32_t p = b + lane; p < e; p += L)
@@ -51,14 +49,21 @@ __device__ __forceinline__ double csr_row_lanes(int64_t row, int lane,
     return acc;
 }
 
-// CSR row by a whole workgroup of B threads (B a multiple of 64); thread 0
-// returns the row sum.  `part` is LDS scratch of B / 64 doubles.
-template <typename T, int B, bool NT>
-__device__ __forceinline__ double csr_row_block(int64_t row, const int32_t *__restrict__ rp,
+template <typename T, int L, bool NT>
+__device__ __forceinline__ double csr_row_lanes(int64_t row, int lane,
+                                                const int32_t *__restrict__ rp,
                                                 const int32_t *__restrict__ col,
                                                 const T *__restrict__ val,
-                                                const T *__restrict__ x, double *part) {
-    int32_t b = rp[row], e = rp[row + 1];
+                                                const T *__restrict__ x) {
+    return lanes_sum<T, L, NT>(rp[row], rp[row + 1], lane, col, val, x);
+}
+
+// Entries [b, e) summed by a whole workgroup of B threads (B a multiple of
+// 64); thread 0 returns the sum.  `part` is LDS scratch of B / 64 doubles.
+template <typename T, int B, bool NT>
+__device__ __forceinline__ double block_sum(int32_t b, int32_t e, const int32_t *__restrict__ col,
+                                            const T *__restrict__ val, const T *__restrict__ x,
+                                            double *part) {
     double acc = 0.0;
 #pragma unroll 4
     for (int32_t p = b + threadIdx.x; p < e; p += B)
@@ -71,6 +76,14 @@ __device__ __forceinline__ double csr_row_block(int64_t row, const int32_t *__re
         for (int w = 0; w < B / kWave; ++w) s += part[w];
     __syncthreads();
     return s;
+}
+
+template <typename T, int B, bool NT>
+__device__ __forceinline__ double csr_row_block(int64_t row, const int32_t *__restrict__ rp,
+                                                const int32_t *__restrict__ col,
+                                                const T *__restrict__ val,
+                                                const T *__restrict__ x, double *part) {
+    return block_sum<T, B, NT>(rp[row], rp[row + 1], col, val, x, part);
 }
 
 // ELL row: slots in order, U slots loaded ahead of use.

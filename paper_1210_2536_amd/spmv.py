@@ -117,7 +117,14 @@ DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weig
 
 
 def default_selector():
-    return Selector.load(DEFAULT_WEIGHTS) if os.path.exists(DEFAULT_WEIGHTS) else None
+    """The shipped trained selector, or None if absent or trained for another kernel set."""
+    if not os.path.exists(DEFAULT_WEIGHTS):
+        return None
+    with open(DEFAULT_WEIGHTS) as fh:
+        meta = json.load(fh)
+    if meta.get("n_out") != C.K_COUNT or list(meta.get("kernels", [])) != list(C.KERNELS):
+        return None
+    return Selector.load(DEFAULT_WEIGHTS)
 
 
 class Plan:

@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 
 from oracle import mlp as OM
+from paper_1210_2536_amd import capi
 from paper_1210_2536_amd import synth as S
 
 from gpu_util import assert_parity, dev, note, vec
@@ -48,7 +49,7 @@ def test_batch_equals_per_level_runs(kernel, dtype):
 def test_mlp_forward_backward_adam_match_oracle():
     import torch
     from paper_1210_2536_amd import spmv as G
-    C = 7
+    C = capi.K_COUNT
     rng = np.random.default_rng(60)
     n_par = OM.n_params(C)
     assert G.mlp_param_count(C) == n_par
@@ -81,7 +82,7 @@ def test_selector_inference_matches_training_forward_and_oracle():
     import torch
     from paper_1210_2536_amd import spmv as G
     from oracle import features as OF
-    C = 7
+    C = capi.K_COUNT
     rng = np.random.default_rng(61)
     flat = rng.normal(0, 0.3, OM.n_params(C)).astype(np.float32)
     mats = [S.stencil_5pt(32), S.zipf_g2(np.random.default_rng([62, 0]), 4000),

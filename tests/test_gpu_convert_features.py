@@ -45,14 +45,15 @@ def test_roundtrip_bit_exact_and_layouts(dtype):
         val = _poisoned(A.val, dtype)
         B = S.CSR(A.m, A.n, A.row_ptr, A.col, val, A.name)
         f = OF.extract(A.m, A.n, A.row_ptr, A.col)
-        for k in ("csr_vector", "csr_adaptive", "coo", "ell", "dia", "dia_direct"):
+        for k in ("csr_vector", "csr_adaptive", "coo", "ell", "dia", "dia_direct", "csr_panel"):
             if k == "ell" and not f["ell_feasible"]:
                 continue
             if k.startswith("dia") and not f["dia_feasible"]:
                 continue
             note(f"[convert] {A.name} {np.dtype(dtype).name} {k}")
             rp, col, v = dev(B, dtype)
-            p = Plan(rp, col, v, n=A.n, selector=k)
+            kw = {"params": {"panel_kib": 1}} if k == "csr_panel" else {}
+            p = Plan(rp, col, v, n=A.n, selector=k, **kw)
             rp2, col2, v2 = p.roundtrip()
             assert np.array_equal(rp2.cpu().numpy(), A.row_ptr.astype(np.int32))
             assert np.array_equal(col2.cpu().numpy(), A.col)
@@ -72,7 +73,7 @@ def test_roundtrip_bit_exact_and_layouts(dtype):
                 assert np.array_equal(p.export(3).cpu().numpy().view(np.int32), offs)
                 assert np.array_equal(p.export(4).cpu().numpy(), data.view(np.uint8))
                 assert np.array_equal(p.export(5).cpu().numpy().view(np.uint32), words)
-            if k == "csr_adaptive":
+            if k in ("csr_adaptive", "csr_panel"):
                 order = p.export(6).cpu().numpy().view(np.int32)
                 assert np.array_equal(np.sort(order), np.arange(A.m))
 

@@ -15,7 +15,8 @@ from gpu_util import assert_parity, dev, note, vec
 
 pytestmark = pytest.mark.gpu
 
-KERNELS = ("csr_scalar", "csr_vector", "csr_adaptive", "ell", "dia", "dia_direct", "coo")
+KERNELS = ("csr_scalar", "csr_vector", "csr_adaptive", "ell", "dia", "dia_direct", "coo",
+           "csr_panel")
 DTYPES = (np.float64, np.float32)
 
 
@@ -139,6 +140,15 @@ def test_tiny_tiles_force_every_boundary(dtype):
         for k, y in _run_all(A, dtype, x, kernels=("coo", "csr_adaptive", "csr_vector"),
                              params=prm).items():
             assert_parity(y, A, x, dtype)
+    # column panels of 1 KiB of x: many panels, running sums carried across them
+    for prm in ({"panel_kib": 1}, {"panel_kib": 8, "stream_nt": 1}):
+        for k, y in _run_all(A, dtype, x, kernels=("csr_panel",), params=prm).items():
+            assert_parity(y, A, x, dtype)
+    for gen in range(4):
+        G = (S.band_g0, S.uniform_g1, S.zipf_g2, S.blocks_g3)[gen](np.random.default_rng([46, gen]), 9000)
+        xg = S.uniform_vector(G.n, [46, gen])
+        for k, y in _run_all(G, dtype, xg, kernels=("csr_panel",), params={"panel_kib": 8}).items():
+            assert_parity(y, G, xg, dtype)
     B = S.stencil_27pt(12)
     xb = S.uniform_vector(B.n, 44)
     for prm in ({"dia_span": 0}, {"dia_span": 1, "dia_rows_per_thread": 1},
