@@ -28,6 +28,10 @@ def _plan(A, dtype, kernel, **kw):
 
 def _feasible(A, kernel):
     f = OF.extract(A.m, A.n, A.row_ptr, A.col)
+    if kernel == "csr_panel":
+        # rows longer than one 256-thread workgroup can sum (1,024,000 entries)
+        # are not held by column panels (SPMV_EUNSUPPORTED, checked below)
+        return f["max_RD"] <= 1_024_000
     if kernel == "ell":
         return f["ell_feasible"]
     if kernel in ("dia", "dia_direct"):
@@ -124,10 +128,15 @@ def _edge_matrices():
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
 def test_edge_cases(dtype):
+    from paper_1210_2536_amd import capi as C
     for A in _edge_matrices():
         x = S.uniform_vector(A.n, [42, A.m])
         for k, y in _run_all(A, dtype, x).items():
             assert_parity(y, A, x, dtype)
+        if not _feasible(A, "csr_panel"):
+            with pytest.raises(C.SpmvError) as ei:
+                _plan(A, dtype, "csr_panel")
+            assert ei.value.status == C.SPMV_EUNSUPPORTED
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
