@@ -108,7 +108,10 @@ typedef struct {
                                    2 off (0 = default: on for ELL and DIA of
                                    banded matrices, off otherwise)           */
     int32_t panel_kib;          /* CSR_PANEL: bytes of x per column panel, in
-                                   KiB (default 2048)                        */
+                                   KiB, sequential mode (default 2048)       */
+    int32_t panel_xcd;          /* CSR_PANEL: 1 = eight panels in one launch,
+                                   one per XCD, partial sums added after
+                                   (default); 2 = panels one after another   */
 } spmv_params;
 
 typedef struct spmv_selector_s *spmv_selector_t;

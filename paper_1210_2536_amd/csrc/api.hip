@@ -219,14 +219,22 @@ spmv_params default_params(int kernel, const spmv_features &F) {
     p.ell_unroll = 4;
     p.stream_nt = 0;  // resolved per kernel by resolve_params
     p.panel_kib = 2048;
+    p.panel_xcd = 1;
     (void)kernel;
     return p;
 }
 
-// Column-panel geometry: width w columns (x bytes per panel <= panel_kib KiB,
-// a multiple of 64 columns) and panel count P.
+constexpr int kXcds = 8;  // gfx950: eight accelerator complex dies, one L2 each
+
+// Column-panel geometry: width w columns (a multiple of 64) and panel count P.
+// XCD mode: P = 8 equal panels; sequential mode: x bytes per panel <=
+// panel_kib KiB.
 void panel_geometry(const spmv_features &F, int elt, const spmv_params &p, int64_t *w, int *P) {
-    int64_t width = ((int64_t)p.panel_kib * 1024 / elt) / 64 * 64;
+    int64_t width;
+    if (p.panel_xcd != 2)
+        width = ((F.n + kXcds - 1) / kXcds + 63) / 64 * 64;
+    else
+        width = ((int64_t)p.panel_kib * 1024 / elt) / 64 * 64;
     if (width < 64) width = 64;
     *w = width;
     *P = (int)std::min<int64_t>((F.n + width - 1) / width, 1 << 20);
@@ -257,6 +265,7 @@ void merge_params(spmv_params &p, const spmv_params &u) {
     if (u.ell_unroll > 0) p.ell_unroll = u.ell_unroll;
     if (u.stream_nt > 0) p.stream_nt = u.stream_nt;
     if (u.panel_kib > 0) p.panel_kib = u.panel_kib;
+    if (u.panel_xcd > 0) p.panel_xcd = u.panel_xcd;
 }
 
 spmv_status check_params(const spmv_params &p) {
@@ -292,8 +301,8 @@ spmv_status check_params(const spmv_params &p) {
         set_error("params.stream_nt must be 0 (default), 1 (on) or 2 (off)");
         return SPMV_EINVAL;
     }
-    if (p.panel_kib < 1 || p.panel_kib > (1 << 20)) {
-        set_error("params.panel_kib must be in [1, 2^20]");
+    if (p.panel_kib < 1 || p.panel_kib > (1 << 20) || p.panel_xcd < 0 || p.panel_xcd > 2) {
+        set_error("params.panel_kib must be in [1, 2^20] and panel_xcd 0, 1 or 2");
         return SPMV_EINVAL;
     }
     return SPMV_OK;
@@ -343,8 +352,10 @@ uint32_t feasible_mask(const spmv_features &F, int dtype, int64_t m_pad, uint64_
         int P;
         panel_geometry(F, elt, p, &w, &P);
         uint64_t bytes = (uint64_t)F.nnz * (uint64_t)(elt + 4) +
-                         (uint64_t)P * (uint64_t)(F.m + 1) * 4u;
+                         (uint64_t)P * (uint64_t)(F.m + 1) * 4u +
+                         (p.panel_xcd != 2 ? (uint64_t)P * (uint64_t)F.m * (uint64_t)elt : 0u);
         bool ok = P >= 2 && F.nnz > 0 && F.max_rd <= kSplitMin && bytes <= cap &&
+                  (uint64_t)F.n * (uint64_t)elt > (2u << 20) &&
                   (uint64_t)P * (uint64_t)(F.m + 1) < (1ull << 31);
         if (dtype == SPMV_F32 && P > 16) ok = false;
         if (ok) mask |= 1u << SPMV_K_CSR_PANEL;
@@ -570,6 +581,8 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
                                           inv.as<int32_t>(), cnt.as<int32_t>(),
                                           V.prow.as<int32_t>(), scan.as<unsigned>(),
                                           V.pcol.as<int32_t>(), V.pval.p, s));
+            if (prm.panel_xcd != 2)
+                SMAT_TRY(V.ppart.alloc((size_t)elt * (size_t)V.P * (size_t)std::max<int64_t>(1, m)));
             SMAT_HIP(hipStreamSynchronize(s));
         }
         return SPMV_OK;
@@ -605,7 +618,8 @@ spmv_status run_variant(const spmv_plan_s &P, const Variant &V, const void *x, v
     }
     case SPMV_K_CSR_PANEL:
         return run_csr_panels(elt, nt, V.alaunch, V.bin_rows.as<int32_t>(), V.P, m,
-                              V.prow.as<int32_t>(), V.pcol.as<int32_t>(), V.pval.p, x, y, s);
+                              V.prow.as<int32_t>(), V.pcol.as<int32_t>(), V.pval.p, x, y,
+                              V.prm.panel_xcd != 2 ? V.ppart.p : nullptr, s);
     case SPMV_K_ELL:
         return run_ell(elt, nt, m, P.m_pad, V.K, V.ecol.as<int32_t>(), V.eval.p, x, y,
                        V.prm.block, V.prm.ell_unroll, s);
@@ -725,10 +739,11 @@ std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_
                 }
         break;
     case SPMV_K_CSR_PANEL:
-        for (int kib : {512, 1024, 2048, 4096})
+        for (int kib : {0, 1024, 2048, 4096})  // 0: one panel per XCD, one launch
             for (int nt : nts) {
                 spmv_params p = b;
-                p.panel_kib = kib;
+                p.panel_xcd = kib == 0 ? 1 : 2;
+                p.panel_kib = kib == 0 ? b.panel_kib : kib;
                 p.stream_nt = nt;
                 int64_t w;
                 int P;

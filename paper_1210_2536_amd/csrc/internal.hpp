@@ -122,10 +122,12 @@ struct AdaptiveLaunch {
 spmv_status run_csr_adaptive(int elt, bool nt, const AdaptiveLaunch &a, const int32_t *rows,
                              const int32_t *rp, const int32_t *col, const void *val,
                              const void *x, void *y, hipStream_t s);
-// Column panels: P launches; prow is P x (m+1) position-indexed segment starts.
+// Column panels; prow is P x (m+1) position-indexed segment starts.  With
+// `partial` (P x m values) all panels run in one launch, one per XCD, and a
+// second kernel adds the partials; without it, one launch per panel.
 spmv_status run_csr_panels(int elt, bool nt, const AdaptiveLaunch &a, const int32_t *rows, int P,
                            int64_t m, const int32_t *prow, const int32_t *pcol, const void *pval,
-                           const void *x, void *y, hipStream_t s);
+                           const void *x, void *y, void *partial, hipStream_t s);
 // Build column panels of width w from a CSR matrix whose rows are visited in
 // the binned order `rows`.  cnt: P*(m+1) ints; prow: P*(m+1)+1 ints; inv: m
 // ints; scan: P*(m+1)/4096+1 unsigned.

@@ -135,16 +135,14 @@ __device__ __forceinline__ void panel_lanes(unsigned local, unsigned rbeg, unsig
     }
 }
 
+// Work of workgroup `bid` of one panel's binned launch geometry.
 template <typename T, bool NT, bool ACC>
-__global__ __launch_bounds__(kAdaptBlock) void k_csr_panel(AdaptiveLaunch a,
-                                                           const int32_t *__restrict__ rows,
-                                                           const int32_t *__restrict__ prow,
-                                                           const int32_t *__restrict__ col,
-                                                           const T *__restrict__ val,
-                                                           const T *__restrict__ x,
-                                                           T *__restrict__ y) {
-    __shared__ double part[kAdaptBlock / kWave];
-    const unsigned bid = blockIdx.x;
+__device__ __forceinline__ void panel_block(const AdaptiveLaunch &a, unsigned bid,
+                                            const int32_t *__restrict__ rows,
+                                            const int32_t *__restrict__ prow,
+                                            const int32_t *__restrict__ col,
+                                            const T *__restrict__ val, const T *__restrict__ x,
+                                            T *__restrict__ y, double *part) {
     int q = 0;
     while (q < 7 && bid >= a.first[q + 1]) ++q;
     const int b = 7 - q;
@@ -170,6 +168,50 @@ __global__ __launch_bounds__(kAdaptBlock) void k_csr_panel(AdaptiveLaunch a,
     case 1: panel_lanes<T, 2, NT, ACC>(local, rb, re, rows, prow, col, val, x, y); break;
     default: panel_lanes<T, 1, NT, ACC>(local, rb, re, rows, prow, col, val, x, y); break;
     }
+}
+
+// One panel per launch (panels processed one after another by the whole GPU).
+template <typename T, bool NT, bool ACC>
+__global__ __launch_bounds__(kAdaptBlock) void k_csr_panel(AdaptiveLaunch a,
+                                                           const int32_t *__restrict__ rows,
+                                                           const int32_t *__restrict__ prow,
+                                                           const int32_t *__restrict__ col,
+                                                           const T *__restrict__ val,
+                                                           const T *__restrict__ x,
+                                                           T *__restrict__ y) {
+    __shared__ double part[kAdaptBlock / kWave];
+    panel_block<T, NT, ACC>(a, blockIdx.x, rows, prow, col, val, x, y, part);
+}
+
+// All P panels in one launch: workgroup w serves panel w mod P.  Workgroups
+// are dispatched to the eight XCDs in turn, so with P = 8 every XCD works on
+// one panel only and its L2 holds just that slice of x -- the eight L2s then
+// cache disjoint eighths of x instead of eight copies of the same slice.
+// Each panel writes its own partial vector; k_panel_reduce adds them in
+// panel order.
+template <typename T, bool NT>
+__global__ __launch_bounds__(kAdaptBlock) void k_csr_panel_xcd(AdaptiveLaunch a, int P, int64_t m,
+                                                               const int32_t *__restrict__ rows,
+                                                               const int32_t *__restrict__ prow,
+                                                               const int32_t *__restrict__ col,
+                                                               const T *__restrict__ val,
+                                                               const T *__restrict__ x,
+                                                               T *__restrict__ partial) {
+    __shared__ double part[kAdaptBlock / kWave];
+    const int panel = (int)(blockIdx.x % (unsigned)P);
+    const unsigned bid = blockIdx.x / (unsigned)P;
+    panel_block<T, NT, false>(a, bid, rows, prow + (int64_t)panel * (m + 1), col, val, x,
+                              partial + (int64_t)panel * m, part);
+}
+
+template <typename T>
+__global__ void k_panel_reduce(int P, int64_t m, const T *__restrict__ partial,
+                               T *__restrict__ y) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double s = 0.0;
+    for (int p = 0; p < P; ++p) s += (double)partial[(int64_t)p * m + i];
+    y[i] = (T)s;
 }
 
 // Rows longer than one workgroup may sum alone: segments of a row reduce to
@@ -479,9 +521,17 @@ spmv_status adaptive_dispatch(bool nt, const AdaptiveLaunch &a, const int32_t *r
 template <typename T, bool NT>
 spmv_status panel_dispatch(const AdaptiveLaunch &a, const int32_t *rows, int P, int64_t m,
                            const int32_t *prow, const int32_t *pcol, const T *pval, const T *x,
-                           T *y, hipStream_t s) {
+                           T *y, T *partial, hipStream_t s) {
     const unsigned nblk = a.first[8];
     if (nblk == 0) return SPMV_OK;
+    if (partial) {
+        k_csr_panel_xcd<T, NT><<<nblk * (unsigned)P, kAdaptBlock, 0, s>>>(a, P, m, rows, prow,
+                                                                          pcol, pval, x, partial);
+        SMAT_LAUNCHED("csr_panel_xcd");
+        k_panel_reduce<T><<<grid_for(m, 256), 256, 0, s>>>(P, m, partial, y);
+        SMAT_LAUNCHED("panel_reduce");
+        return SPMV_OK;
+    }
     for (int p = 0; p < P; ++p) {
         const int32_t *pr = prow + (int64_t)p * (m + 1);
         if (p == 0)
@@ -497,16 +547,18 @@ spmv_status panel_dispatch(const AdaptiveLaunch &a, const int32_t *rows, int P, 
 
 spmv_status run_csr_panels(int elt, bool nt, const AdaptiveLaunch &a, const int32_t *rows, int P,
                            int64_t m, const int32_t *prow, const int32_t *pcol, const void *pval,
-                           const void *x, void *y, hipStream_t s) {
+                           const void *x, void *y, void *partial, hipStream_t s) {
     if (elt == 8)
         return nt ? panel_dispatch<double, true>(a, rows, P, m, prow, pcol, (const double *)pval,
-                                                 (const double *)x, (double *)y, s)
+                                                 (const double *)x, (double *)y,
+                                                 (double *)partial, s)
                   : panel_dispatch<double, false>(a, rows, P, m, prow, pcol, (const double *)pval,
-                                                  (const double *)x, (double *)y, s);
+                                                  (const double *)x, (double *)y,
+                                                  (double *)partial, s);
     return nt ? panel_dispatch<float, true>(a, rows, P, m, prow, pcol, (const float *)pval,
-                                            (const float *)x, (float *)y, s)
+                                            (const float *)x, (float *)y, (float *)partial, s)
               : panel_dispatch<float, false>(a, rows, P, m, prow, pcol, (const float *)pval,
-                                             (const float *)x, (float *)y, s);
+                                             (const float *)x, (float *)y, (float *)partial, s);
 }
 
 // Typed entry points: elt selects float (4) or double (8), nt the streaming

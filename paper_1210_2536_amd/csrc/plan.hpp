@@ -55,7 +55,7 @@ struct Variant {
     int bin_lanes[kAdaptiveBins] = {};
     AdaptiveLaunch alaunch{};
     // CSR column panels
-    Dev prow, pcol, pval;
+    Dev prow, pcol, pval, ppart;
     int P = 0;
     int64_t panel_w = 0;
     int64_t nsplit_rows = 0, nsplit_segs = 0;
@@ -63,7 +63,8 @@ struct Variant {
         return row_idx.bytes + coo_head.bytes + coo_tail.bytes + coo_flags.bytes + ecol.bytes +
                eval.bytes + dia_off.bytes + dia_data.bytes + dia_present.bytes + dia_win.bytes +
                bin_rows.bytes + bin_scratch.bytes + split_segs.bytes + split_partials.bytes +
-               split_begin.bytes + split_rows.bytes + prow.bytes + pcol.bytes + pval.bytes;
+               split_begin.bytes + split_rows.bytes + prow.bytes + pcol.bytes + pval.bytes +
+               ppart.bytes;
     }
 };
 
