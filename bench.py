@@ -136,6 +136,10 @@ def main():
             return f"k_{'dia_lds' if k == 'dia' else 'dia_direct'}<{t}, {p['dia_rows_per_thread']}, {nt}>"
         if k == "coo":
             return f"k_coo<{t}, {nt}> + k_coo_fixup<{t}>"
+        if k == "csr_panel":
+            if p["panel_xcd"] != 2:
+                return f"k_csr_panel_xcd<{t}, {nt}> + k_panel_reduce<{t}>"
+            return f"k_csr_panel<{t}, {nt}, false|true>"
         return f"k_csr_scalar<{t}>"
 
     sym_time = {}

@@ -20,6 +20,8 @@ K_CSR_SCALAR, K_CSR_VECTOR, K_CSR_ADAPTIVE, K_ELL, K_DIA, K_DIA_DIRECT, K_COO, K
     range(8)
 K_COUNT = 8
 FORMATS = ("csr", "coo", "ell", "dia")
+# storage format each kernel runs on (index into FORMATS); column panels are CSR
+FORMAT_OF = (0, 0, 0, 2, 3, 3, 1, 0)
 SELECT_RULES, SELECT_MLP, SELECT_EXHAUSTIVE, SELECT_FORCED = range(4)
 
 i32, i64, u32, u64, f32, f64 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,

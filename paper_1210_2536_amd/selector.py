@@ -199,7 +199,7 @@ def evaluate(sc, ds, tau=None, topk=3):
             choice[i] = cand[int(np.argmin(times[i, cand]))]
             measured[i] = len(cand)
     t_sel = times[np.arange(len(times)), choice]
-    fmt = lambda k: {0: 0, 1: 0, 2: 0, 3: 2, 4: 3, 5: 3, 6: 1}[int(k)]  # noqa: E731
+    fmt = lambda k: C.FORMAT_OF[int(k)]  # noqa: E731
     best_k = times.argmin(axis=1)
     return {
         "hit_rate": float(np.mean(t_sel <= 1.05 * best)),
