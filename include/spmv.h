@@ -166,6 +166,9 @@ typedef struct {
     double t_validate_ms, t_features_ms, t_select_ms, t_convert_ms, t_plan_ms;
     float mlp_input[12];                /* raw selector inputs of this matrix  */
     int32_t rules_kernel;               /* what SPMV_SELECT_RULES would pick   */
+    int32_t out_of_domain;              /* 1: MLP inputs outside the model's
+                                           training range, every feasible
+                                           kernel was measured               */
 } spmv_plan_info;
 
 typedef struct spmv_plan_s *spmv_plan_t;
@@ -225,6 +228,17 @@ spmv_status spmv_plan_export(spmv_plan_t plan, int32_t which, void *dst_dev, siz
 spmv_status spmv_selector_create(const float *params, int64_t n_params, const float *mean,
                                  const float *std, spmv_selector_t *out);
 spmv_status spmv_selector_destroy(spmv_selector_t sel);
+
+/* Training domain of a selector: `lo` and `hi` are host arrays of the 12 raw
+ * inputs' smallest and largest values over the matrices the model was fitted
+ * on (copied; both NULL clears the domain).  A matrix whose raw inputs leave
+ * [lo, hi] in any coordinate is outside what the model has seen, so its
+ * scores are not trusted whatever their margin: plan creation then measures
+ * every feasible kernel, as when the margin falls below the confidence
+ * threshold (Section 5, the execute-and-measure step for uncertain
+ * predictions), and reports out_of_domain = 1.  EINVAL if only one pointer
+ * is NULL or lo[i] > hi[i]. */
+spmv_status spmv_selector_set_domain(spmv_selector_t sel, const float *lo, const float *hi);
 
 /* Score raw feature rows with the selector on the GPU (inference kernel):
  * raw_dev is float32 [rows x 12], scores_dev float32 [rows x SPMV_K_COUNT]. */

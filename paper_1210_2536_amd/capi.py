@@ -65,7 +65,8 @@ class spmv_plan_info(ctypes.Structure):
                 ("ell_width", i32), ("dia_ndiags", i32), ("dia_windows", i32), ("m_pad", i64),
                 ("device_bytes", u64), ("t_validate_ms", f64), ("t_features_ms", f64),
                 ("t_select_ms", f64), ("t_convert_ms", f64), ("t_plan_ms", f64),
-                ("mlp_input", f32 * 12), ("rules_kernel", i32)]
+                ("mlp_input", f32 * 12), ("rules_kernel", i32),
+                ("out_of_domain", i32)]
 
 
 _SIGS = {
@@ -79,6 +80,7 @@ _SIGS = {
     "spmv_plan_export": (i32, [vp, i32, vp, ctypes.c_size_t, vp, vp]),
     "spmv_selector_create": (i32, [vp, i64, vp, vp, vp]),
     "spmv_selector_destroy": (i32, [vp]),
+    "spmv_selector_set_domain": (i32, [vp, vp, vp]),
     "spmv_selector_score": (i32, [vp, vp, i64, vp, vp]),
     "spmv_mlp_param_count": (i64, [i32]),
     "spmv_mlp_workspace_floats": (i64, [i64]),

@@ -997,8 +997,17 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
             if ((feas >> k) & 1u) order.push_back({sc[k], k});
         }
         std::sort(order.begin(), order.end());
+        bool outside = false;
+        if (sel->has_domain)
+            for (int j = 0; j < 12; ++j)
+                outside = outside || !(raw[j] >= sel->lo[j] && raw[j] <= sel->hi[j]);
+        I.out_of_domain = outside ? 1 : 0;
         if (order.empty()) {
             chosen = SPMV_K_CSR_ADAPTIVE;
+        } else if (outside && order.size() > 1) {
+            // extrapolation: the scores are not evidence, measure them all
+            I.confidence = order[1].first - order[0].first;
+            for (auto &o : order) cands.push_back(o.second);
         } else {
             float margin = order.size() > 1 ? order[1].first - order[0].first : 1e30f;
             I.confidence = margin;
@@ -1267,6 +1276,27 @@ extern "C" spmv_status spmv_selector_create(const float *params, int64_t n_param
     SMAT_HIP(hipMemcpy(S->mean.p, mean, sizeof(float) * 12, hipMemcpyHostToDevice));
     SMAT_HIP(hipMemcpy(S->stdv.p, stdv, sizeof(float) * 12, hipMemcpyHostToDevice));
     *out = S.release();
+    return SPMV_OK;
+}
+
+extern "C" spmv_status spmv_selector_set_domain(spmv_selector_t S, const float *lo,
+                                                const float *hi) {
+    if (!S || (!lo) != (!hi)) {
+        set_error("selector handle and both or neither of lo / hi required");
+        return SPMV_EINVAL;
+    }
+    if (!lo) {
+        S->has_domain = false;
+        return SPMV_OK;
+    }
+    for (int j = 0; j < 12; ++j)
+        if (!(lo[j] <= hi[j])) {
+            set_error("domain lo[%d] > hi[%d]", j, j);
+            return SPMV_EINVAL;
+        }
+    std::copy(lo, lo + 12, S->lo);
+    std::copy(hi, hi + 12, S->hi);
+    S->has_domain = true;
     return SPMV_OK;
 }
 

@@ -74,6 +74,8 @@ struct Variant {
 struct spmv_selector_s {
     smat::Dev params, mean, stdv;
     int n_out = 0;
+    bool has_domain = false;
+    float lo[12] = {}, hi[12] = {};   // training range of the raw inputs
 };
 
 struct spmv_plan_s {

@@ -227,12 +227,22 @@ def pick_tau(params, mean, std, ds, topk=3):
     return 1e9, evaluate(sc, ds, tau=1e9, topk=topk)
 
 
-def save(path, params, mean, std, meta):
+def domain(raw):
+    """Per-input range [lo, hi] of the raw features the model was fitted on."""
+    r = np.asarray(raw, dtype=np.float32)
+    return r.min(axis=0), r.max(axis=0)
+
+
+def save(path, params, mean, std, meta, dom=None):
     os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    d = {"params": [float(v) for v in params], "mean": [float(v) for v in mean],
+         "std": [float(v) for v in std], "n_out": C.K_COUNT, "kernels": list(C.KERNELS),
+         "meta": meta}
+    if dom is not None:
+        d["lo"] = [float(v) for v in dom[0]]
+        d["hi"] = [float(v) for v in dom[1]]
     with open(path, "w") as fh:
-        json.dump({"params": [float(v) for v in params], "mean": [float(v) for v in mean],
-                   "std": [float(v) for v in std], "n_out": C.K_COUNT,
-                   "kernels": list(C.KERNELS), "meta": meta}, fh)
+        json.dump(d, fh)
 
 
 def main(argv=None):
@@ -279,7 +289,7 @@ def main(argv=None):
             meta["heldout_mlp_tau"] = {k: v for k, v in evaluate(sc, ho, tau=tau).items()
                                        if k != "choice"}
             meta["heldout_rules"] = {k: v for k, v in evaluate_rules(ho).items() if k != "choice"}
-        save(a.out, params, mean, std, meta)
+        save(a.out, params, mean, std, meta, dom=domain(tr["raw"]))
         log(json.dumps({k: v for k, v in meta.items() if k != "loss_curve"}))
     else:
         with open(a.weights) as fh:

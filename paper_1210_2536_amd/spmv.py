@@ -87,6 +87,7 @@ class Selector:
                 "spmv_selector_create")
         self.handle = h
         self.params, self.mean, self.std = p, mu, sd
+        self.lo = self.hi = None
 
     @classmethod
     def load(cls, path):
@@ -94,7 +95,24 @@ class Selector:
             d = json.load(fh)
         sel = cls(d["params"], d["mean"], d["std"])
         sel.tau = d.get("meta", {}).get("tau")
+        if "lo" in d and "hi" in d:
+            sel.set_domain(d["lo"], d["hi"])
         return sel
+
+    def set_domain(self, lo, hi):
+        """Training range of the 12 raw inputs (None, None clears it)."""
+        if lo is None and hi is None:
+            C.check(C.lib().spmv_selector_set_domain(self.handle, None, None),
+                    "spmv_selector_set_domain")
+            self.lo = self.hi = None
+            return
+        lo = np.ascontiguousarray(lo, dtype=np.float32)
+        hi = np.ascontiguousarray(hi, dtype=np.float32)
+        assert lo.shape == (12,) and hi.shape == (12,)
+        C.check(C.lib().spmv_selector_set_domain(self.handle, lo.ctypes.data_as(ctypes.c_void_p),
+                                                 hi.ctypes.data_as(ctypes.c_void_p)),
+                "spmv_selector_set_domain")
+        self.lo, self.hi = lo, hi
 
     def score(self, raw, stream=None):
         """raw: float32 device tensor [rows, 12] -> scores [rows, K_COUNT]."""

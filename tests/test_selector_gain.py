@@ -76,3 +76,34 @@ def test_live_selection_network_vs_rules():
     print(f"live hit rate: network {hits_mlp / total:.3f}, rules {hits_rules / total:.3f}")
     assert hits_mlp >= hits_rules
     assert hits_mlp / total >= 0.7
+
+
+@pytest.mark.gpu
+def test_out_of_domain_inputs_are_measured_not_trusted():
+    """Inputs outside the training range send plan creation to measurement of
+    every feasible kernel; the kept kernel is the fastest of those measured."""
+    import torch
+    from paper_1210_2536_amd import synth
+    from paper_1210_2536_amd.spmv import Plan, Selector
+    sel = Selector.load(WEIGHTS)
+    assert sel.lo is not None  # the shipped model carries its training range
+    A = synth.selector_matrix(20_000, heldout=True, nnz_cap=2_000_000, n_hi=5.0)
+    rp = torch.from_numpy(A.row_ptr.astype(np.int32)).cuda()
+    col = torch.from_numpy(A.col).cuda()
+    val = torch.from_numpy(A.val.astype(np.float64)).cuda()
+    inside = Plan(rp, col, val, n=A.n, selector="mlp", model=sel, tau=0.0).info()
+    assert inside["out_of_domain"] == 0 and inside["n_measured"] == 0
+    raw = np.array(inside["mlp_input"], dtype=np.float32)
+    # a domain that excludes this matrix's nnz only
+    lo, hi = sel.lo.copy(), sel.hi.copy()
+    hi[1] = raw[1] - 1
+    sel.set_domain(lo, hi)
+    out = Plan(rp, col, val, n=A.n, selector="mlp", model=sel, tau=0.0).info()
+    nfeas = bin(out["feasible_mask"]).count("1")
+    assert out["out_of_domain"] == 1 and out["n_measured"] == nfeas
+    nm = out["n_measured"]
+    times = dict(zip(out["measured_kernel"][:nm], out["measured_ms"][:nm]))
+    assert out["kernel"] == min(times, key=times.get)
+    sel.set_domain(None, None)
+    again = Plan(rp, col, val, n=A.n, selector="mlp", model=sel, tau=0.0).info()
+    assert again["out_of_domain"] == 0 and again["n_measured"] == 0
