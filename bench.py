@@ -36,6 +36,47 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def kernel_sources_sha256():
+    """Digest of the HIP sources and the C header: a counter record taken on
+    other sources no longer describes the kernels being timed."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1210_2536_amd", "csrc")
+    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc)
+                   if f.endswith((".hip", ".hpp", ".h")))
+    for f in files + [os.path.join(ROOT, "include", "spmv.h")]:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` on `workload` from the counter records
+    committed under profiles/ (lines "traffic-record: {json}"), or None when no
+    record matches or the kernel sources changed since it was taken."""
+    pdir = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(pdir):
+        return None
+    digest = kernel_sources_sha256()
+    for f in sorted(os.listdir(pdir)):
+        if not f.endswith((".md", ".txt")):
+            continue
+        with open(os.path.join(pdir, f)) as fh:
+            for line in fh:
+                line = line.strip()
+                if not line.startswith("traffic-record:"):
+                    continue
+                try:
+                    r = json.loads(line[len("traffic-record:"):])
+                except ValueError:
+                    continue
+                if (r.get("kernel") == kernel and r.get("workload") == workload
+                        and r.get("sources_sha256") == digest):
+                    return int(r["bytes_per_launch"])
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -51,6 +92,10 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--detail", default="", help="write per-matrix records (JSON) here")
+    ap.add_argument("--replay", default="",
+                    help="per-matrix records of an earlier run (--detail): build every plan "
+                         "with the kernel and parameters recorded there instead of selecting "
+                         "and tuning (counter runs use it to profile the same launches)")
     return ap.parse_args()
 
 
@@ -83,6 +128,12 @@ def main():
     items = workloads.build(a.workload)
     log(f"{len(items)} matrices generated in {time.time() - t_start:.1f}s")
 
+    replay = None
+    if a.replay:
+        with open(a.replay) as fh:
+            replay = json.load(fh)["records"]
+        assert len(replay) == len(items), "replay records do not match the workload"
+
     recs = []
     for idx, (A, dt, xseed) in enumerate(items):
         rp = torch.from_numpy(A.row_ptr.astype(np.int32)).to(dev)
@@ -90,8 +141,13 @@ def main():
         val = torch.from_numpy(A.val.astype(dt)).to(dev)
         x = torch.from_numpy(S.uniform_vector(A.n, xseed).astype(dt)).to(dev)
         y = torch.empty(A.m, dtype=val.dtype, device=dev)
-        tuned = Plan(rp, col, val, n=A.n, selector=selector, model=model,
-                     autotune=not a.no_autotune)
+        if replay is not None:
+            rr = replay[idx]
+            assert rr["name"] == A.name and rr["dtype"] == np.dtype(dt).name, rr["name"]
+            tuned = Plan(rp, col, val, n=A.n, selector=rr["kernel"], params=rr["params"])
+        else:
+            tuned = Plan(rp, col, val, n=A.n, selector=selector, model=model,
+                         autotune=not a.no_autotune)
         plain = None if a.no_plain else Plan(rp, col, val, n=A.n, selector="csr_scalar")
         info = tuned.info()
         rec = dict(name=A.name, dtype=np.dtype(dt).name, m=A.m, n=A.n, nnz=A.nnz,
@@ -276,6 +332,10 @@ def main():
                          f"{fsum / 2 / 1e6:.1f}M nnz"}
         log(f"cpu oracle: {cpu['value']} GFLOP/s on {threads} threads")
 
+    workload_name = {"sweep": "sweep200_f32_f64", "large": "zipf8M_f32+lap7_256^3_f64",
+                     "multilevel": "galerkin27_160^3_6levels_f64",
+                     "multilevel32": "galerkin27_160^3_6levels_f32",
+                     "c1": "lap5_64x64_f64"}[a.workload]
     plan_units = [r["rec"]["plan_ms"] / r["rec"]["plain_ms"] for r in recs
                   if r["rec"].get("plain_ms")]
     speedup = (plain_ms_step / ms_step) if plain_ms_step else None
@@ -293,10 +353,7 @@ def main():
         "dtype": "f64-accumulate (f32 and f64 storage)" if a.workload == "sweep" else
                  ("f64" if all(dt == np.float64 for _, dt, _ in items) else "f64-accumulate"),
         "data": "synthetic",
-        "config": {"workload": {"sweep": "sweep200_f32_f64", "large": "zipf8M_f32+lap7_256^3_f64",
-                                "multilevel": "galerkin27_160^3_6levels_f64",
-                                "multilevel32": "galerkin27_160^3_6levels_f32",
-                                "c1": "lap5_64x64_f64"}[a.workload],
+        "config": {"workload": workload_name,
                    "matrices": len(items), "nnz_per_step": int(flops / 2), "selector": selector},
         "hbm_gbs": round(hbm_gbs, 1),
         "hbm_frac_peak": round(hbm_gbs / HBM_PEAK_GBS, 4),
@@ -308,7 +365,8 @@ def main():
         "plan_cost_plain_csr_units_median": round(float(np.median(plan_units)), 2) if plan_units else None,
         "roofline": {"bound": "hbm", "kernel": dominant, "launches_per_step": len(evs) // a.steps,
                      "achieved": round(dom_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(dom_achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(dom_achieved / HBM_PEAK_GBS, 4),
+                     "traffic": recorded_traffic(dominant, workload_name),
                      "avg_launch_ms": round(dom_avg_ms, 5),
                      "bytes_per_launch": int(np.mean(dom_bytes))},
         "cpu_baseline": cpu,

@@ -124,7 +124,13 @@ typedef struct {
                                    best and runner-up) below which candidates
                                    are measured; default 0.1                  */
     int32_t measure_topk;       /* candidates measured when unsure; default 3 */
-    int32_t timing_reps;        /* timed repetitions per candidate; default 5 */
+    int32_t timing_reps;        /* timed repetitions per candidate; default 5.
+                                   Each repetition times back-to-back calls
+                                   worth about 50 us (at most 64 calls) and
+                                   the median per-call time is kept; after a
+                                   prediction another kernel (or parameter
+                                   point) replaces the predicted one only
+                                   when more than 3% faster               */
     uint32_t disable_mask;      /* bit k set: never pick kernel k             */
     uint64_t mem_cap_bytes;     /* cap on padded ELL / DIA storage; 0 = 1/4 of
                                    free device memory                        */

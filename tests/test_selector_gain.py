@@ -81,7 +81,8 @@ def test_live_selection_network_vs_rules():
 @pytest.mark.gpu
 def test_out_of_domain_inputs_are_measured_not_trusted():
     """Inputs outside the training range send plan creation to measurement of
-    every feasible kernel; the kept kernel is the fastest of those measured."""
+    every feasible kernel; the kept kernel is the fastest of those measured,
+    up to the switching margin."""
     import torch
     from paper_1210_2536_amd import synth
     from paper_1210_2536_amd.spmv import Plan, Selector
@@ -103,7 +104,9 @@ def test_out_of_domain_inputs_are_measured_not_trusted():
     assert out["out_of_domain"] == 1 and out["n_measured"] == nfeas
     nm = out["n_measured"]
     times = dict(zip(out["measured_kernel"][:nm], out["measured_ms"][:nm]))
-    assert out["kernel"] == min(times, key=times.get)
+    # the predicted-best kernel is kept unless another measured one is more
+    # than 3% faster, so the kept time is within 1/0.97 of the fastest
+    assert times[out["kernel"]] <= min(times.values()) / 0.97 * (1 + 1e-12)
     sel.set_domain(None, None)
     again = Plan(rp, col, val, n=A.n, selector="mlp", model=sel, tau=0.0).info()
     assert again["out_of_domain"] == 0 and again["n_measured"] == 0
