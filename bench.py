@@ -152,7 +152,8 @@ def main():
         info = tuned.info()
         rec = dict(name=A.name, dtype=np.dtype(dt).name, m=A.m, n=A.n, nnz=A.nnz,
                    kernel=info["kernel_name"], format=info["format_name"],
-                   plan_ms=info["t_plan_ms"], bytes=workloads.plan_bytes(info),
+                   plan_ms=info["t_plan_ms"], tune_ms=info["t_tune_ms"],
+                   bytes=workloads.plan_bytes(info),
                    confidence=info["confidence"], n_measured=info["n_measured"],
                    params=info["params"], rules_kernel=capi.KERNELS[info["rules_kernel"]])
         recs.append(dict(rec=rec, tuned=tuned, plain=plain, x=x, y=y))
@@ -206,15 +207,85 @@ def main():
     log(f"dominant kernel {dominant}: {sym_time[dominant]:.3f} ms of "
         f"{sum(sym_time.values()):.3f} ms per step")
 
+    # ---- multilevel workloads: all levels in one persistent launch, one
+    # graph replay, or one launch per level; a short trial picks the mode
+    batches, ml = {}, None
+    if a.workload in ("multilevel", "multilevel32"):
+        from paper_1210_2536_amd.spmv import Batch
+        xs, ys = [r["x"] for r in recs], [r["y"] for r in recs]
+        ml = {}
+        for mode, name in ((0, "persistent"), (1, "graph")):
+            b = Batch([r["tuned"] for r in recs], mode=mode)
+            if mode == 0:
+                ml["persistent_grid"] = b.tune(xs, ys)
+            batches[name] = b
+
+        def trial(fn, K=10):
+            fn()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for _ in range(K):
+                fn()
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) * 1e3 / K
+
+        def separate():
+            for r in recs:
+                r["tuned"].run(r["x"], r["y"])
+        ml["trial_ms"] = {"separate": trial(separate)}
+        for name, b in batches.items():
+            ml["trial_ms"][name] = trial(lambda b=b: b.run(xs, ys))
+        ml["mode"] = min(ml["trial_ms"], key=ml["trial_ms"].get)
+        log(f"multilevel trial (ms/step): {ml['trial_ms']} -> {ml['mode']}")
+        if ml["mode"] == "persistent":
+            dt_name = "double" if recs[0]["rec"]["dtype"] == "float64" else "float"
+            dominant = f"k_batch_persistent<{dt_name}>"
+            sym_time = {dominant: sum(r["rec"]["tuned_ms"] for r in recs)}
+    step_mode = ml["mode"] if ml else "separate"
+    level_bytes = sum(r["rec"]["bytes"] for r in recs)
+
     # ---- timed region: K steps of every tuned SpMV
     def steps(which, K, events=False):
         evs = []
+        if which == "tuned" and step_mode != "separate":
+            b = batches[step_mode]
+            pairs = event_pairs(K) if events and step_mode == "persistent" else None
+            for _ in range(K):
+                if pairs is not None:
+                    e0, e1 = next(pairs)
+                    e0.record()
+                    b.run(xs, ys)
+                    e1.record()
+                    evs.append((e0, e1, level_bytes))
+                else:
+                    b.run(xs, ys)
+            return evs
+        return per_plan(which, K, events)
+
+    # event pairs are created (and their device events instantiated) before
+    # the timed region, so that only the two records per launch fall in it
+    pool = []
+
+    def event_pairs(n):
+        if len(pool) < n:
+            while len(pool) < n:
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                e1.record()
+                pool.append((e0, e1))
+            torch.cuda.synchronize()
+        return iter(pool[:n])
+
+    def per_plan(which, K, events=False):
+        evs = []
+        n_dom = sum(1 for r in recs if r["rec"]["symbol"] == dominant)
+        pairs = event_pairs(K * n_dom) if events else None
         for _ in range(K):
             for r in recs:
                 p = r[which]
                 if events and r["rec"]["symbol"] == dominant:
-                    e0 = torch.cuda.Event(enable_timing=True)
-                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0, e1 = next(pairs)
                     e0.record()
                     p.run(r["x"], r["y"])
                     e1.record()
@@ -228,6 +299,7 @@ def main():
     mark_src = torch.zeros(4, dtype=torch.float32, device=dev)
     mark_dst = torch.empty_like(mark_src)
     steps("tuned", a.warmup)
+    event_pairs(a.steps * max(1, sum(1 for r in recs if r["rec"]["symbol"] == dominant)))
     stream_copy(mark_dst, mark_src)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -235,6 +307,11 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     stream_copy(mark_dst, mark_src)
+    if not evs:
+        # graph replays hide the level kernels from stream events: time the
+        # dominant kernel's launches one by one, outside the timed region
+        evs = per_plan("tuned", a.steps, events=True)
+        torch.cuda.synchronize()
     # achievable-bandwidth probe: copy 1 GiB (2 GiB of traffic), median of 5
     cp_src = torch.zeros(1 << 28, dtype=torch.float32, device=dev)
     cp_dst = torch.empty_like(cp_src)
@@ -268,6 +345,9 @@ def main():
         torch.cuda.synchronize()
         plain_ms_step = (time.perf_counter() - t0) * 1e3 / a.steps
         log(f"plain CSR: {plain_ms_step:.3f} ms/step")
+
+    for b in batches.values():
+        b.close()
 
     # ---- selector hit rate against exhaustive timing (same session)
     hit_rate = rules_hit_rate = None
@@ -338,6 +418,8 @@ def main():
                      "c1": "lap5_64x64_f64"}[a.workload]
     plan_units = [r["rec"]["plan_ms"] / r["rec"]["plain_ms"] for r in recs
                   if r["rec"].get("plain_ms")]
+    select_units = [(r["rec"]["plan_ms"] - r["rec"]["tune_ms"]) / r["rec"]["plain_ms"]
+                    for r in recs if r["rec"].get("plain_ms")]
     speedup = (plain_ms_step / ms_step) if plain_ms_step else None
     out = {
         "metric": METRIC,
@@ -354,7 +436,9 @@ def main():
                  ("f64" if all(dt == np.float64 for _, dt, _ in items) else "f64-accumulate"),
         "data": "synthetic",
         "config": {"workload": workload_name,
-                   "matrices": len(items), "nnz_per_step": int(flops / 2), "selector": selector},
+                   "matrices": len(items), "nnz_per_step": int(flops / 2), "selector": selector,
+                   "step": step_mode},
+        "multilevel": ml,
         "hbm_gbs": round(hbm_gbs, 1),
         "hbm_frac_peak": round(hbm_gbs / HBM_PEAK_GBS, 4),
         "stream_copy_gbs": round(copy_gbs, 1),
@@ -363,6 +447,8 @@ def main():
         "hit_rate": round(hit_rate, 4) if hit_rate is not None else None,
         "rules_hit_rate": round(rules_hit_rate, 4) if hit_rate is not None else None,
         "plan_cost_plain_csr_units_median": round(float(np.median(plan_units)), 2) if plan_units else None,
+        "plan_cost_untuned_plain_csr_units_median":
+            round(float(np.median(select_units)), 2) if select_units else None,
         "roofline": {"bound": "hbm", "kernel": dominant, "launches_per_step": len(evs) // a.steps,
                      "achieved": round(dom_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(dom_achieved / HBM_PEAK_GBS, 4),

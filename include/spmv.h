@@ -112,6 +112,11 @@ typedef struct {
     int32_t panel_xcd;          /* CSR_PANEL: 1 = eight panels in one launch,
                                    one per XCD, partial sums added after
                                    (default); 2 = panels one after another   */
+    int32_t wide_loads;         /* DIA and ELL: 1 = a lane takes 16 bytes'
+                                   worth of consecutive rows (4 in float32,
+                                   2 in float64) and reads every diagonal or
+                                   slot of them with one 16-byte load; 2 =
+                                   one row per lane; 0 = default (1)       */
 } spmv_params;
 
 typedef struct spmv_selector_s *spmv_selector_t;
@@ -175,6 +180,8 @@ typedef struct {
     int32_t out_of_domain;              /* 1: MLP inputs outside the model's
                                            training range, every feasible
                                            kernel was measured               */
+    double t_tune_ms;                   /* parameter search (autotune), part
+                                           of t_convert_ms and t_plan_ms      */
 } spmv_plan_info;
 
 typedef struct spmv_plan_s *spmv_plan_t;

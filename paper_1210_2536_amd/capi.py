@@ -38,7 +38,7 @@ class spmv_params(ctypes.Structure):
     _fields_ = [("block", i32), ("vector_lanes", i32), ("adaptive_rows_per_lane", i32),
                 ("adaptive_wg_min", i32), ("dia_rows_per_thread", i32), ("dia_span", i32),
                 ("coo_chunk", i32), ("ell_unroll", i32), ("stream_nt", i32),
-                ("panel_kib", i32), ("panel_xcd", i32)]
+                ("panel_kib", i32), ("panel_xcd", i32), ("wide_loads", i32)]
 
 
 class spmv_plan_opts(ctypes.Structure):
@@ -66,7 +66,7 @@ class spmv_plan_info(ctypes.Structure):
                 ("device_bytes", u64), ("t_validate_ms", f64), ("t_features_ms", f64),
                 ("t_select_ms", f64), ("t_convert_ms", f64), ("t_plan_ms", f64),
                 ("mlp_input", f32 * 12), ("rules_kernel", i32),
-                ("out_of_domain", i32)]
+                ("out_of_domain", i32), ("t_tune_ms", f64)]
 
 
 _SIGS = {

@@ -225,6 +225,7 @@ spmv_params default_params(int kernel, const spmv_features &F) {
 }
 
 constexpr int kXcds = 8;  // gfx950: eight accelerator complex dies, one L2 each
+constexpr int64_t kDiaLdsMax = 64 * 1024;  // dynamic LDS of one DIA workgroup
 
 // Column-panel geometry: width w columns (a multiple of 64) and panel count P.
 // XCD mode: P = 8 equal panels; sequential mode: x bytes per panel <=
@@ -251,6 +252,7 @@ spmv_params resolve_params(int kernel, spmv_params p, const spmv_features &F) {
                             kernel == SPMV_K_DIA_DIRECT;
         p.stream_nt = (dense_stream && F.dia_feasible) ? 1 : 2;
     }
+    if (p.wide_loads == 0) p.wide_loads = 1;  // 16-byte streams measured faster on gfx950
     return p;
 }
 
@@ -266,6 +268,7 @@ void merge_params(spmv_params &p, const spmv_params &u) {
     if (u.stream_nt > 0) p.stream_nt = u.stream_nt;
     if (u.panel_kib > 0) p.panel_kib = u.panel_kib;
     if (u.panel_xcd > 0) p.panel_xcd = u.panel_xcd;
+    if (u.wide_loads > 0) p.wide_loads = u.wide_loads;
 }
 
 spmv_status check_params(const spmv_params &p) {
@@ -303,6 +306,10 @@ spmv_status check_params(const spmv_params &p) {
     }
     if (p.panel_kib < 1 || p.panel_kib > (1 << 20) || p.panel_xcd < 0 || p.panel_xcd > 2) {
         set_error("params.panel_kib must be in [1, 2^20] and panel_xcd 0, 1 or 2");
+        return SPMV_EINVAL;
+    }
+    if (p.wide_loads < 0 || p.wide_loads > 2) {
+        set_error("params.wide_loads must be 0 (default), 1 (on) or 2 (off)");
         return SPMV_EINVAL;
     }
     return SPMV_OK;
@@ -474,6 +481,17 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
         }
         V.nwin = (int)win.size();
         V.max_span = max_span;
+        if (kernel == SPMV_K_DIA) {
+            const int64_t rows = (int64_t)std::min(prm.block, 256) * prm.dia_rows_per_thread *
+                                 (prm.wide_loads == 1 ? 16 / elt : 1);
+            const int64_t lds = (rows + max_span) * elt;
+            if (lds > kDiaLdsMax) {
+                set_error("DIA tile of %lld rows with an x window span of %d needs %lld bytes "
+                          "of LDS (limit %lld)", (long long)rows, max_span, (long long)lds,
+                          (long long)kDiaLdsMax);
+                return SPMV_EUNSUPPORTED;
+            }
+        }
         SMAT_TRY(V.dia_win.alloc(sizeof(DiaWindow) * std::max<size_t>(1, win.size())));
         if (!win.empty())
             SMAT_HIP(hipMemcpyAsync(V.dia_win.p, win.data(), sizeof(DiaWindow) * win.size(),
@@ -622,13 +640,13 @@ spmv_status run_variant(const spmv_plan_s &P, const Variant &V, const void *x, v
                               V.prm.panel_xcd != 2 ? V.ppart.p : nullptr, s);
     case SPMV_K_ELL:
         return run_ell(elt, nt, m, P.m_pad, V.K, V.ecol.as<int32_t>(), V.eval.p, x, y,
-                       V.prm.block, V.prm.ell_unroll, s);
+                       V.prm.block, V.prm.ell_unroll, V.prm.wide_loads == 1, s);
     case SPMV_K_DIA:
     case SPMV_K_DIA_DIRECT:
         return run_dia(elt, nt, V.kernel == SPMV_K_DIA, m, P.n, P.m_pad, V.D,
                        V.dia_off.as<int32_t>(), V.nwin, V.dia_win.as<DiaWindow>(), V.max_span,
                        V.dia_data.p, x, y, std::min(V.prm.block, 256), V.prm.dia_rows_per_thread,
-                       s);
+                       V.prm.wide_loads == 1, s);
     case SPMV_K_COO:
         return run_coo(elt, nt, m, P.nnz, V.row_idx.as<int32_t>(), P.col.as<int32_t>(), P.val.p,
                        x, y, V.prm.coo_chunk, V.coo_head.as<double>(), V.coo_tail.as<double>(),
@@ -725,33 +743,39 @@ std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_
     case SPMV_K_ELL:
         for (int u : {2, 4})
             for (int bs : {256, 512})
-                for (int nt : nts) {
-                    spmv_params p = b;
-                    p.ell_unroll = u;
-                    p.block = bs;
-                    p.stream_nt = nt;
-                    add(p);
-                }
+                for (int nt : nts)
+                    for (int wide : {1, 2}) {
+                        spmv_params p = b;
+                        p.ell_unroll = u;
+                        p.block = bs;
+                        p.stream_nt = nt;
+                        p.wide_loads = wide;
+                        add(p);
+                    }
         break;
     case SPMV_K_DIA_DIRECT:
         for (int r : {1, 2, 4, 8})
-            for (int nt : nts) {
-                spmv_params p = b;
-                p.dia_rows_per_thread = r;
-                p.stream_nt = nt;
-                add(p);
-            }
-        break;
-    case SPMV_K_DIA:
-        for (int r : {2, 4, 8})
-            for (int sp : {32, 256})
-                for (int nt : nts) {
+            for (int nt : nts)
+                for (int wide : {1, 2}) {
                     spmv_params p = b;
                     p.dia_rows_per_thread = r;
-                    p.dia_span = sp;
                     p.stream_nt = nt;
+                    p.wide_loads = wide;
                     add(p);
                 }
+        break;
+    case SPMV_K_DIA:
+        for (int r : {1, 2, 4})
+            for (int sp : {32, 256})
+                for (int nt : nts)
+                    for (int wide : {1, 2}) {
+                        spmv_params p = b;
+                        p.dia_rows_per_thread = r;
+                        p.dia_span = sp;
+                        p.stream_nt = nt;
+                        p.wide_loads = wide;
+                        add(p);
+                    }
         break;
     case SPMV_K_CSR_PANEL:
         for (int kib : {0, 1024, 2048, 4096})  // 0: one panel per XCD, one launch
@@ -809,7 +833,7 @@ spmv_status autotune_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork
         if (same_params(p, best->prm)) continue;
         auto V = std::make_unique<Variant>();
         spmv_status st = build_variant(P, F, W, kernel, p, s, *V);
-        if (st == SPMV_ENOMEM) continue;
+        if (st == SPMV_ENOMEM || st == SPMV_EUNSUPPORTED) continue;
         if (st != SPMV_OK) return st;
         double ms = 0;
         SMAT_TRY(time_variant(P, *V, xs.p, ys.p, reps, s, &ms));
@@ -1054,7 +1078,7 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
         for (int k : cands) {
             auto V = std::make_unique<Variant>();
             spmv_status st = build_variant(*P, F, W, k, prm_base, s, *V);
-            if (st == SPMV_ENOMEM) continue;  // candidate too large right now
+            if (st == SPMV_ENOMEM || st == SPMV_EUNSUPPORTED) continue;  // cannot be built
             if (st != SPMV_OK) return st;
             double ms = 0;
             SMAT_TRY(time_variant(*P, *V, xs.p, ys.p, opts.timing_reps, s, &ms));
@@ -1088,8 +1112,13 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
             return st;
         }
     }
-    if (opts.autotune && !opts.use_params)
+    if (opts.autotune && !opts.use_params) {
+        auto t_tune0 = std::chrono::steady_clock::now();
         SMAT_TRY(autotune_variant(*P, F, W, opts.timing_reps, s, P->var));
+        SMAT_HIP(hipStreamSynchronize(s));
+        I.t_tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                                t_tune0).count();
+    }
     SMAT_HIP(hipStreamSynchronize(s));
     W.diag_hist.release();
     if (!needs_csr(chosen)) {

@@ -146,12 +146,12 @@ spmv_status run_csr_split(int elt, int64_t nseg, const int64_t *segs, double *pa
                           const int32_t *col, const void *val, const void *x, void *y,
                           hipStream_t s);
 spmv_status run_ell(int elt, bool nt, int64_t m, int64_t m_pad, int K, const int32_t *ecol,
-                    const void *eval, const void *x, void *y, int block, int unroll,
+                    const void *eval, const void *x, void *y, int block, int unroll, bool wide,
                     hipStream_t s);
 spmv_status run_dia(int elt, bool nt, bool lds, int64_t m, int64_t n, int64_t m_pad, int D,
                     const int32_t *offs_dev, int nwin, const DiaWindow *win_dev, int max_span,
                     const void *data, const void *x, void *y, int block, int rows_per_thread,
-                    hipStream_t s);
+                    bool wide, hipStream_t s);
 spmv_status run_coo(int elt, bool nt, int64_t m, int64_t nnz, const int32_t *row_idx,
                     const int32_t *col, const void *val, const void *x, void *y, int chunk,
                     double *head, double *tail, uint32_t *flags, hipStream_t s);

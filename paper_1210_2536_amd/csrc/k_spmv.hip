@@ -253,14 +253,26 @@ __global__ void k_csr_segment_fixup(int64_t nrows, const int64_t *__restrict__ r
 // Slot-major layout: thread i reads slot k of row i at k*m_pad + i, so a
 // wavefront reads 64 consecutive values and 64 consecutive columns per slot.
 // U slots are loaded before any is used, to keep more loads in flight.
-template <typename T, int U, bool NT>
+// Wide form (V > 1): a lane takes V consecutive rows, so each slot's columns
+// and values arrive in one load of V elements.
+template <typename T, int U, bool NT, int V>
 __global__ __launch_bounds__(1024) void k_ell(int64_t m, int64_t m_pad, int K,
                                               const int32_t *__restrict__ ecol,
                                               const T *__restrict__ eval, const T *__restrict__ x,
                                               T *__restrict__ y) {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= m) return;
-    y[i] = (T)ell_row<T, U, NT>(i, m_pad, K, ecol, eval, x);
+    if constexpr (V == 1) {
+        int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+        if (i >= m) return;
+        y[i] = (T)ell_row<T, U, NT>(i, m_pad, K, ecol, eval, x);
+    } else {
+        int64_t i0 = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) * V;
+        if (i0 >= m) return;
+        double acc[V];
+        ell_rows_wide<T, U, V, NT>(i0, m, m_pad, K, ecol, eval, x, acc);
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            if (i0 + e < m) y[i0 + e] = (T)acc[e];
+    }
 }
 
 // ---------------------------------------------------------------- DIA
@@ -270,7 +282,7 @@ __global__ __launch_bounds__(1024) void k_ell(int64_t m, int64_t m_pad, int K,
 // the window reads its shifted view from there, while the diagonal values
 // stream from HBM with unit stride.  Summation runs over diagonals in
 // ascending offset order, i.e. ascending column order as in CSR.
-template <typename T, int RPT, bool NT>
+template <typename T, int RPT, bool NT, int V>
 __global__ __launch_bounds__(256) void k_dia_lds(int64_t m, int64_t n, int64_t m_pad,
                                                  const int32_t *__restrict__ offs, int nwin,
                                                  const DiaWindow *__restrict__ win,
@@ -278,19 +290,19 @@ __global__ __launch_bounds__(256) void k_dia_lds(int64_t m, int64_t n, int64_t m
                                                  const T *__restrict__ x, T *__restrict__ y) {
     extern __shared__ unsigned char smem_raw[];
     T *xs = reinterpret_cast<T *>(smem_raw);
-    const int64_t r0 = (int64_t)blockIdx.x * blockDim.x * RPT;
-    dia_tile_lds<T, RPT, NT>(r0, m, n, m_pad, offs, nwin, win, data, x, y, xs);
+    const int64_t r0 = (int64_t)blockIdx.x * blockDim.x * RPT * V;
+    dia_tile_lds<T, RPT, NT, V>(r0, m, n, m_pad, offs, nwin, win, data, x, y, xs);
 }
 
 // DIA without LDS: x comes through L1/L2 (neighbouring diagonals hit the same
 // cache lines).
-template <typename T, int RPT, bool NT>
+template <typename T, int RPT, bool NT, int V>
 __global__ __launch_bounds__(256) void k_dia_direct(int64_t m, int64_t n, int64_t m_pad, int D,
                                                     const int32_t *__restrict__ offs,
                                                     const T *__restrict__ data,
                                                     const T *__restrict__ x, T *__restrict__ y) {
-    const int64_t r0 = (int64_t)blockIdx.x * blockDim.x * RPT;
-    dia_tile_direct<T, RPT, NT>(r0, m, n, m_pad, D, offs, data, x, y);
+    const int64_t r0 = (int64_t)blockIdx.x * blockDim.x * RPT * V;
+    dia_tile_direct<T, RPT, NT, V>(r0, m, n, m_pad, D, offs, data, x, y);
 }
 
 // ---------------------------------------------------------------- COO
@@ -445,46 +457,72 @@ spmv_status csr_vector_dispatch(int lanes, int64_t nrows, const int32_t *rp, con
     return SPMV_OK;
 }
 
+// Rows per lane of the wide forms: 16 bytes of values per load.
+template <typename T> constexpr int kWideRows = 16 / (int)sizeof(T);
+
+template <typename T, bool NT, int V>
+void ell_launch(unsigned g, int block, int unroll, int64_t m, int64_t m_pad, int K,
+                const int32_t *ecol, const T *eval, const T *x, T *y, hipStream_t s) {
+    switch (unroll) {
+    case 1: k_ell<T, 1, NT, V><<<g, block, 0, s>>>(m, m_pad, K, ecol, eval, x, y); break;
+    case 2: k_ell<T, 2, NT, V><<<g, block, 0, s>>>(m, m_pad, K, ecol, eval, x, y); break;
+    default: k_ell<T, 4, NT, V><<<g, block, 0, s>>>(m, m_pad, K, ecol, eval, x, y); break;
+    }
+}
+
 template <typename T, bool NT>
 spmv_status ell_dispatch(int64_t m, int64_t m_pad, int K, const int32_t *ecol, const T *eval,
-                         const T *x, T *y, int block, int unroll, hipStream_t s) {
+                         const T *x, T *y, int block, int unroll, bool wide, hipStream_t s) {
     if (m == 0) return SPMV_OK;
     if (block <= 0) block = 256;
-    unsigned g = grid_for(m, block);
-    switch (unroll) {
-    case 1: k_ell<T, 1, NT><<<g, block, 0, s>>>(m, m_pad, K, ecol, eval, x, y); break;
-    case 2: k_ell<T, 2, NT><<<g, block, 0, s>>>(m, m_pad, K, ecol, eval, x, y); break;
-    default: k_ell<T, 4, NT><<<g, block, 0, s>>>(m, m_pad, K, ecol, eval, x, y); break;
-    }
+    constexpr int W = kWideRows<T>;
+    if (wide)
+        ell_launch<T, NT, W>(grid_for((m + W - 1) / W, block), block, unroll, m, m_pad, K, ecol,
+                             eval, x, y, s);
+    else
+        ell_launch<T, NT, 1>(grid_for(m, block), block, unroll, m, m_pad, K, ecol, eval, x, y, s);
     SMAT_LAUNCHED("ell");
     return SPMV_OK;
+}
+
+template <typename T, bool NT, int V>
+void dia_launch(bool lds, unsigned g, int block, int rpt, size_t sh, int64_t m, int64_t n,
+                int64_t m_pad, int D, const int32_t *offs, int nwin, const DiaWindow *win,
+                const T *data, const T *x, T *y, hipStream_t s) {
+    if (lds) {
+        switch (rpt) {
+        case 1: k_dia_lds<T, 1, NT, V><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
+        case 2: k_dia_lds<T, 2, NT, V><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
+        case 4: k_dia_lds<T, 4, NT, V><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
+        default: k_dia_lds<T, 8, NT, V><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
+        }
+    } else {
+        switch (rpt) {
+        case 1: k_dia_direct<T, 1, NT, V><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
+        case 2: k_dia_direct<T, 2, NT, V><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
+        case 4: k_dia_direct<T, 4, NT, V><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
+        default: k_dia_direct<T, 8, NT, V><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
+        }
+    }
 }
 
 template <typename T, bool NT>
 spmv_status dia_dispatch(bool lds, int64_t m, int64_t n, int64_t m_pad, int D,
                          const int32_t *offs, int nwin, const DiaWindow *win, int max_span,
-                         const T *data, const T *x, T *y, int block, int rpt, hipStream_t s) {
+                         const T *data, const T *x, T *y, int block, int rpt, bool wide,
+                         hipStream_t s) {
     if (m == 0) return SPMV_OK;
     if (block <= 0 || block > 256) block = 256;
     if (rpt != 1 && rpt != 2 && rpt != 4 && rpt != 8) rpt = 4;
-    int64_t tile = (int64_t)block * rpt;
+    constexpr int W = kWideRows<T>;
+    const int V = wide ? W : 1;
+    int64_t tile = (int64_t)block * rpt * V;
     unsigned g = grid_for(m, (int)tile);
-    if (lds) {
-        size_t sh = (size_t)(tile + max_span) * sizeof(T);
-        switch (rpt) {
-        case 1: k_dia_lds<T, 1, NT><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
-        case 2: k_dia_lds<T, 2, NT><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
-        case 4: k_dia_lds<T, 4, NT><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
-        default: k_dia_lds<T, 8, NT><<<g, block, sh, s>>>(m, n, m_pad, offs, nwin, win, data, x, y); break;
-        }
-    } else {
-        switch (rpt) {
-        case 1: k_dia_direct<T, 1, NT><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
-        case 2: k_dia_direct<T, 2, NT><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
-        case 4: k_dia_direct<T, 4, NT><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
-        default: k_dia_direct<T, 8, NT><<<g, block, 0, s>>>(m, n, m_pad, D, offs, data, x, y); break;
-        }
-    }
+    size_t sh = lds ? (size_t)(tile + max_span) * sizeof(T) : 0;
+    if (wide)
+        dia_launch<T, NT, W>(lds, g, block, rpt, sh, m, n, m_pad, D, offs, nwin, win, data, x, y, s);
+    else
+        dia_launch<T, NT, 1>(lds, g, block, rpt, sh, m, n, m_pad, D, offs, nwin, win, data, x, y, s);
     SMAT_LAUNCHED(lds ? "dia_lds" : "dia_direct");
     return SPMV_OK;
 }
@@ -625,11 +663,11 @@ spmv_status run_csr_split(int elt, int64_t nseg, const int64_t *segs, double *pa
 }
 
 spmv_status run_ell(int elt, bool nt, int64_t m, int64_t m_pad, int K, const int32_t *ecol,
-                    const void *eval, const void *x, void *y, int block, int unroll,
+                    const void *eval, const void *x, void *y, int block, int unroll, bool wide,
                     hipStream_t s) {
 #define CALL(T, NT)                                                                             \
     ell_dispatch<T, NT>(m, m_pad, K, ecol, (const T *)eval, (const T *)x, (T *)y, block, unroll, \
-                        s)
+                        wide, s)
     return SMAT_TYPED(elt, nt, CALL);
 #undef CALL
 }
@@ -637,11 +675,11 @@ spmv_status run_ell(int elt, bool nt, int64_t m, int64_t m_pad, int K, const int
 spmv_status run_dia(int elt, bool nt, bool lds, int64_t m, int64_t n, int64_t m_pad, int D,
                     const int32_t *offs_dev, int nwin, const DiaWindow *win_dev, int max_span,
                     const void *data, const void *x, void *y, int block, int rows_per_thread,
-                    hipStream_t s) {
+                    bool wide, hipStream_t s) {
     if (D == 0) return run_fill_zero(elt, m, y, s);
 #define CALL(T, NT)                                                                      \
     dia_dispatch<T, NT>(lds, m, n, m_pad, D, offs_dev, nwin, win_dev, max_span,          \
-                        (const T *)data, (const T *)x, (T *)y, block, rows_per_thread, s)
+                        (const T *)data, (const T *)x, (T *)y, block, rows_per_thread, wide, s)
     return SMAT_TYPED(elt, nt, CALL);
 #undef CALL
 }

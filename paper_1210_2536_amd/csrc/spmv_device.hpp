@@ -114,18 +114,76 @@ __device__ __forceinline__ double ell_row(int64_t i, int64_t m_pad, int K,
     return acc;
 }
 
+// V consecutive elements of a matrix stream as one load (V * sizeof(T) bytes;
+// the address is a multiple of that size).
+template <typename T, int V, bool NT>
+__device__ __forceinline__ void ld_rows(const T *p, T (&v)[V]) {
+    if constexpr (V == 1) {
+        v[0] = ld<NT>(p);
+    } else {
+        typedef T vec __attribute__((ext_vector_type(V)));
+        vec w = ld<NT>(reinterpret_cast<const vec *>(p));
+#pragma unroll
+        for (int e = 0; e < V; ++e) v[e] = w[e];
+    }
+}
+
+// ELL rows i0 .. i0+V-1 of one lane (i0 a multiple of V, i0 < m): the slot
+// columns and values of the V rows come in one load each.  Each row's sum
+// runs over its slots in order, exactly as ell_row.
+template <typename T, int U, int V, bool NT>
+__device__ __forceinline__ void ell_rows_wide(int64_t i0, int64_t m, int64_t m_pad, int K,
+                                              const int32_t *__restrict__ ecol,
+                                              const T *__restrict__ eval,
+                                              const T *__restrict__ x, double (&acc)[V]) {
+#pragma unroll
+    for (int e = 0; e < V; ++e) acc[e] = 0.0;
+    int k = 0;
+    for (; k + U <= K; k += U) {
+        int32_t c[U][V];
+        T v[U][V];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            int64_t s = (int64_t)(k + u) * m_pad + i0;
+            ld_rows<int32_t, V, NT>(ecol + s, c[u]);
+            ld_rows<T, V, NT>(eval + s, v[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int e = 0; e < V; ++e)
+                if (i0 + e < m && c[u][e] >= 0)
+                    acc[e] = fma((double)v[u][e], (double)x[c[u][e]], acc[e]);
+    }
+    for (; k < K; ++k) {
+        int64_t s = (int64_t)k * m_pad + i0;
+        int32_t c[V];
+        T v[V];
+        ld_rows<int32_t, V, NT>(ecol + s, c);
+        ld_rows<T, V, NT>(eval + s, v);
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            if (i0 + e < m && c[e] >= 0) acc[e] = fma((double)v[e], (double)x[c[e]], acc[e]);
+    }
+}
+
 // DIA tile with x windows staged in LDS; every thread of the workgroup must
-// call it (it synchronises).  Rows r0 + threadIdx.x + q*blockDim.x, q < RPT.
-template <typename T, int RPT, bool NT>
+// call it (it synchronises).  The tile holds R = blockDim * RPT * V rows; a
+// lane takes V consecutive rows per step (one V-wide load of each diagonal),
+// steps q = 0..RPT-1 being blockDim * V rows apart.  Each row sums its
+// diagonals in ascending offset order whatever RPT and V.
+template <typename T, int RPT, bool NT, int V = 1>
 __device__ __forceinline__ void dia_tile_lds(int64_t r0, int64_t m, int64_t n, int64_t m_pad,
                                              const int32_t *__restrict__ offs, int nwin,
                                              const DiaWindow *__restrict__ win,
                                              const T *__restrict__ data,
                                              const T *__restrict__ x, T *__restrict__ y, T *xs) {
-    const int R = blockDim.x * RPT;
-    double acc[RPT];
+    const int R = blockDim.x * RPT * V;
+    double acc[RPT][V];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[q][e] = 0.0;
     for (int w = 0; w < nwin; ++w) {
         const int d0 = win[w].d0, d1 = win[w].d1;
         const int lo = offs[d0], hi = offs[d1];
@@ -141,43 +199,60 @@ __device__ __forceinline__ void dia_tile_lds(int64_t r0, int64_t m, int64_t n, i
             const T *dd = data + (int64_t)d * m_pad + r0;
 #pragma unroll
             for (int q = 0; q < RPT; ++q) {
-                int il = threadIdx.x + q * blockDim.x;
-                if (r0 + il < m)
-                    acc[q] = fma((double)ld<NT>(dd + il), (double)xs[il + sh], acc[q]);
+                const int il = (threadIdx.x + q * blockDim.x) * V;
+                if (r0 + il < m) {
+                    T v[V];
+                    ld_rows<T, V, NT>(dd + il, v);
+#pragma unroll
+                    for (int e = 0; e < V; ++e)
+                        acc[q][e] = fma((double)v[e], (double)xs[il + e + sh], acc[q][e]);
+                }
             }
         }
     }
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-        int64_t i = r0 + threadIdx.x + q * blockDim.x;
-        if (i < m) y[i] = (T)acc[q];
+        const int64_t i0 = r0 + (int64_t)(threadIdx.x + q * blockDim.x) * V;
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            if (i0 + e < m) y[i0 + e] = (T)acc[q][e];
     }
 }
 
-// DIA tile reading x through the caches.
-template <typename T, int RPT, bool NT>
+// DIA tile reading x through the caches (same row layout as dia_tile_lds).
+template <typename T, int RPT, bool NT, int V = 1>
 __device__ __forceinline__ void dia_tile_direct(int64_t r0, int64_t m, int64_t n, int64_t m_pad,
                                                 int D, const int32_t *__restrict__ offs,
                                                 const T *__restrict__ data,
                                                 const T *__restrict__ x, T *__restrict__ y) {
-    double acc[RPT];
+    double acc[RPT][V];
 #pragma unroll
-    for (int q = 0; q < RPT; ++q) acc[q] = 0.0;
+    for (int q = 0; q < RPT; ++q)
+#pragma unroll
+        for (int e = 0; e < V; ++e) acc[q][e] = 0.0;
     for (int d = 0; d < D; ++d) {
         const int64_t off = offs[d];
         const T *dd = data + (int64_t)d * m_pad;
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
-            int64_t i = r0 + threadIdx.x + q * blockDim.x;
-            int64_t j = i + off;
-            if (i < m && j >= 0 && j < n)
-                acc[q] = fma((double)ld<NT>(dd + i), (double)x[j], acc[q]);
+            const int64_t i0 = r0 + (int64_t)(threadIdx.x + q * blockDim.x) * V;
+            if (i0 < m) {
+                T v[V];
+                ld_rows<T, V, NT>(dd + i0, v);
+#pragma unroll
+                for (int e = 0; e < V; ++e) {
+                    const int64_t j = i0 + e + off;
+                    if (j >= 0 && j < n) acc[q][e] = fma((double)v[e], (double)x[j], acc[q][e]);
+                }
+            }
         }
     }
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-        int64_t i = r0 + threadIdx.x + q * blockDim.x;
-        if (i < m) y[i] = (T)acc[q];
+        const int64_t i0 = r0 + (int64_t)(threadIdx.x + q * blockDim.x) * V;
+#pragma unroll
+        for (int e = 0; e < V; ++e)
+            if (i0 + e < m) y[i0 + e] = (T)acc[q][e];
     }
 }
 

@@ -166,6 +166,23 @@ def test_tiny_tiles_force_every_boundary(dtype):
                 {"dia_rows_per_thread": 8}, {"ell_unroll": 1}, {"ell_unroll": 2}):
         for k, y in _run_all(B, dtype, xb, kernels=("dia", "dia_direct", "ell"), params=prm).items():
             assert_parity(y, B, xb, dtype)
+    # wide loads (a lane owns 16 bytes of consecutive rows) and one row per
+    # lane, on 1728 rows and on 2197 rows (not a multiple of the row group)
+    Cm = S.stencil_7pt(13)
+    xc = S.uniform_vector(Cm.n, 47)
+    for M, xm in ((B, xb), (Cm, xc)):
+        ref = {}
+        for prm in ({"wide_loads": 1}, {"wide_loads": 2},
+                    {"wide_loads": 1, "block": 64, "dia_rows_per_thread": 1, "ell_unroll": 1},
+                    {"wide_loads": 1, "dia_rows_per_thread": 8, "dia_span": 0},
+                    {"wide_loads": 1, "dia_span": 1, "ell_unroll": 2, "stream_nt": 1}):
+            for k, y in _run_all(M, dtype, xm, kernels=("dia", "dia_direct", "ell"),
+                                 params=prm).items():
+                assert_parity(y, M, xm, dtype)
+                # same per-row operations in the same order: bitwise equal
+                if k in ref:
+                    assert np.array_equal(ref[k], y), (M.name, k, prm)
+                ref.setdefault(k, y)
 
 
 def test_empty_matrices():
