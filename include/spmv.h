@@ -107,16 +107,20 @@ typedef struct {
     int32_t stream_nt;          /* matrix arrays loaded non-temporally: 1 on,
                                    2 off (0 = default: on for ELL and DIA of
                                    banded matrices, off otherwise)           */
-    int32_t panel_kib;          /* CSR_PANEL: bytes of x per column panel, in
-                                   KiB, sequential mode (default 2048)       */
-    int32_t panel_xcd;          /* CSR_PANEL: 1 = eight panels in one launch,
-                                   one per XCD, partial sums added after
-                                   (default); 2 = panels one after another   */
+    int32_t panel_kib;          /* CSR_PANEL: most bytes of x per column
+                                   panel, in KiB (default 4096)              */
+    int32_t panel_xcd;          /* CSR_PANEL: 1 = all panels in one launch,
+                                   eight at a time, one per XCD, each panel
+                                   summing into its own partial vector that a
+                                   second kernel adds in panel order
+                                   (default); 2 = one launch per panel, the
+                                   running sums carried in y               */
     int32_t wide_loads;         /* DIA and ELL: 1 = a lane takes 16 bytes'
                                    worth of consecutive rows (4 in float32,
                                    2 in float64) and reads every diagonal or
                                    slot of them with one 16-byte load; 2 =
-                                   one row per lane; 0 = default (1)       */
+                                   one row per lane; 0 = default (1 from
+                                   2^20 rows on, 2 below)                  */
 } spmv_params;
 
 typedef struct spmv_selector_s *spmv_selector_t;

@@ -218,7 +218,7 @@ spmv_params default_params(int kernel, const spmv_features &F) {
     p.coo_chunk = F.nnz >= (8 << 20) ? 8 : F.nnz >= (1 << 20) ? 4 : 2;
     p.ell_unroll = 4;
     p.stream_nt = 0;  // resolved per kernel by resolve_params
-    p.panel_kib = 2048;
+    p.panel_kib = 4096;
     p.panel_xcd = 1;
     (void)kernel;
     return p;
@@ -228,14 +228,21 @@ constexpr int kXcds = 8;  // gfx950: eight accelerator complex dies, one L2 each
 constexpr int64_t kDiaLdsMax = 64 * 1024;  // dynamic LDS of one DIA workgroup
 
 // Column-panel geometry: width w columns (a multiple of 64) and panel count P.
-// XCD mode: P = 8 equal panels; sequential mode: x bytes per panel <=
-// panel_kib KiB.
+// XCD mode: P = 8 G panels, G the fewest groups of eight whose panels hold
+// at most panel_kib KiB of x (trailing panels may be empty); sequential
+// mode: x bytes per panel <= panel_kib KiB.
 void panel_geometry(const spmv_features &F, int elt, const spmv_params &p, int64_t *w, int *P) {
-    int64_t width;
-    if (p.panel_xcd != 2)
-        width = ((F.n + kXcds - 1) / kXcds + 63) / 64 * 64;
-    else
-        width = ((int64_t)p.panel_kib * 1024 / elt) / 64 * 64;
+    const int64_t kib = std::max<int64_t>(1, p.panel_kib);
+    if (p.panel_xcd != 2) {
+        const int64_t xbytes = std::max<int64_t>(1, F.n) * elt;
+        const int64_t G = std::min<int64_t>((xbytes + kXcds * kib * 1024 - 1) / (kXcds * kib * 1024),
+                                            (1 << 20) / kXcds);
+        int64_t width = ((std::max<int64_t>(1, F.n) + kXcds * G - 1) / (kXcds * G) + 63) / 64 * 64;
+        *w = std::max<int64_t>(64, width);
+        *P = (int)(kXcds * G);
+        return;
+    }
+    int64_t width = (kib * 1024 / elt) / 64 * 64;
     if (width < 64) width = 64;
     *w = width;
     *P = (int)std::min<int64_t>((F.n + width - 1) / width, 1 << 20);
@@ -252,7 +259,10 @@ spmv_params resolve_params(int kernel, spmv_params p, const spmv_features &F) {
                             kernel == SPMV_K_DIA_DIRECT;
         p.stream_nt = (dense_stream && F.dia_feasible) ? 1 : 2;
     }
-    if (p.wide_loads == 0) p.wide_loads = 1;  // 16-byte streams measured faster on gfx950
+    // 16-byte streams pay off once a quarter or half as many lanes still fill
+    // the chip many times over (measured: faster from about a million rows,
+    // slower on smaller matrices)
+    if (p.wide_loads == 0) p.wide_loads = F.m >= (1 << 20) ? 1 : 2;
     return p;
 }
 
@@ -352,9 +362,11 @@ uint32_t feasible_mask(const spmv_features &F, int dtype, int64_t m_pad, uint64_
         if (!f64 || F.max_rd <= kCooMaxChunksPerRow * per) mask |= 1u << SPMV_K_COO;
     }
     {
-        // Column panels pay off only when x does not fit one panel; float32
-        // rounds the running sum once per panel, so at most 16 panels keep
-        // it inside 2e-6 (|A||x|)_i; no row may need splitting.
+        // Column panels pay off only when x does not fit one panel.  In
+        // sequential mode float32 rounds the running sum once per panel, so
+        // at most 16 panels keep it inside 2e-6 (|A||x|)_i (XCD mode rounds
+        // each panel's own partial once: at most 2^-24 sum_p |partial_p| <=
+        // 2^-24 (|A||x|)_i for any P); no row may need splitting.
         int64_t w;
         int P;
         panel_geometry(F, elt, p, &w, &P);
@@ -364,7 +376,7 @@ uint32_t feasible_mask(const spmv_features &F, int dtype, int64_t m_pad, uint64_
         bool ok = P >= 2 && F.nnz > 0 && F.max_rd <= kSplitMin && bytes <= cap &&
                   (uint64_t)F.n * (uint64_t)elt > (2u << 20) &&
                   (uint64_t)P * (uint64_t)(F.m + 1) < (1ull << 31);
-        if (dtype == SPMV_F32 && P > 16) ok = false;
+        if (dtype == SPMV_F32 && p.panel_xcd == 2 && P > 16) ok = false;
         if (ok) mask |= 1u << SPMV_K_CSR_PANEL;
     }
     return mask;
@@ -777,20 +789,27 @@ std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_
                         add(p);
                     }
         break;
-    case SPMV_K_CSR_PANEL:
-        for (int kib : {0, 1024, 2048, 4096})  // 0: one panel per XCD, one launch
-            for (int nt : nts) {
+    case SPMV_K_CSR_PANEL: {
+        std::vector<std::pair<int, int>> seen;  // (mode, P): kib values giving equal panels
+        for (int mode : {1, 2})  // 1: eight panels at a time, one launch; 2: sequential
+            for (int kib : {1024, 2048, 4096}) {
                 spmv_params p = b;
-                p.panel_xcd = kib == 0 ? 1 : 2;
-                p.panel_kib = kib == 0 ? b.panel_kib : kib;
-                p.stream_nt = nt;
+                p.panel_xcd = mode;
+                p.panel_kib = kib;
                 int64_t w;
                 int P;
                 panel_geometry(F, dtype == SPMV_F64 ? 8 : 4, p, &w, &P);
-                if (P < 2 || (dtype == SPMV_F32 && P > 16)) continue;
-                add(p);
+                if (P < 2 || (mode == 2 && dtype == SPMV_F32 && P > 16)) continue;
+                if (std::find(seen.begin(), seen.end(), std::make_pair(mode, P)) != seen.end())
+                    continue;
+                seen.push_back({mode, P});
+                for (int nt : nts) {
+                    p.stream_nt = nt;
+                    add(p);
+                }
             }
         break;
+    }
     case SPMV_K_COO:
         for (int c : {2, 4, 8, 16})
             for (int nt : nts) {

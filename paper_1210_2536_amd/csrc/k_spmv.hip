@@ -183,10 +183,12 @@ __global__ __launch_bounds__(kAdaptBlock) void k_csr_panel(AdaptiveLaunch a,
     panel_block<T, NT, ACC>(a, blockIdx.x, rows, prow, col, val, x, y, part);
 }
 
-// All P panels in one launch: workgroup w serves panel w mod P.  Workgroups
-// are dispatched to the eight XCDs in turn, so with P = 8 every XCD works on
-// one panel only and its L2 holds just that slice of x -- the eight L2s then
-// cache disjoint eighths of x instead of eight copies of the same slice.
+// All P = 8 G panels in one launch.  Workgroups are dispatched to the eight
+// XCDs in turn, so workgroup w runs on XCD w mod 8; it serves panel
+// (w mod 8) + 8 g, where g = w / (8 nblk) is the group of 8 panels the launch
+// is working through (groups follow each other in dispatch order).  Every
+// XCD thus works on one panel at a time and its L2 holds just that slice of
+// x -- the eight L2s cache disjoint slices instead of copies of the same one.
 // Each panel writes its own partial vector; k_panel_reduce adds them in
 // panel order.
 template <typename T, bool NT>
@@ -198,10 +200,13 @@ __global__ __launch_bounds__(kAdaptBlock) void k_csr_panel_xcd(AdaptiveLaunch a,
                                                                const T *__restrict__ x,
                                                                T *__restrict__ partial) {
     __shared__ double part[kAdaptBlock / kWave];
-    const int panel = (int)(blockIdx.x % (unsigned)P);
-    const unsigned bid = blockIdx.x / (unsigned)P;
+    const unsigned nblk = a.first[8];
+    const unsigned w = blockIdx.x;
+    const int panel = (int)(w % 8u + 8u * (w / (8u * nblk)));
+    const unsigned bid = (w / 8u) % nblk;
     panel_block<T, NT, false>(a, bid, rows, prow + (int64_t)panel * (m + 1), col, val, x,
                               partial + (int64_t)panel * m, part);
+    (void)P;
 }
 
 template <typename T>

@@ -239,10 +239,22 @@ __device__ __forceinline__ void dia_tile_direct(int64_t r0, int64_t m, int64_t n
             if (i0 < m) {
                 T v[V];
                 ld_rows<T, V, NT>(dd + i0, v);
+                const int64_t j0 = i0 + off;
+                if (V > 1 && j0 >= 0 && j0 + V <= n) {
+                    // x[j0 .. j0+V) in one load; j0 is only element-aligned
+                    typedef T vec __attribute__((ext_vector_type(V)));
+                    vec xv;
+                    __builtin_memcpy(&xv, x + j0, sizeof(vec));
 #pragma unroll
-                for (int e = 0; e < V; ++e) {
-                    const int64_t j = i0 + e + off;
-                    if (j >= 0 && j < n) acc[q][e] = fma((double)v[e], (double)x[j], acc[q][e]);
+                    for (int e = 0; e < V; ++e)
+                        acc[q][e] = fma((double)v[e], (double)xv[e], acc[q][e]);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < V; ++e) {
+                        const int64_t j = j0 + e;
+                        if (j >= 0 && j < n)
+                            acc[q][e] = fma((double)v[e], (double)x[j], acc[q][e]);
+                    }
                 }
             }
         }

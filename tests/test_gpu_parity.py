@@ -149,15 +149,17 @@ def test_tiny_tiles_force_every_boundary(dtype):
         for k, y in _run_all(A, dtype, x, kernels=("coo", "csr_adaptive", "csr_vector"),
                              params=prm).items():
             assert_parity(y, A, x, dtype)
-    # column panels: one per XCD in one launch (default), or 1 KiB / 8 KiB of x
-    # per panel one after another with running sums carried across them
-    for prm in ({}, {"panel_kib": 1, "panel_xcd": 2}, {"panel_kib": 8, "panel_xcd": 2, "stream_nt": 1}):
+    # column panels in one launch, eight at a time (one per XCD): one group
+    # (default), two groups (16 KiB panels), 160 panels of 1 KiB; or panels of
+    # 1 KiB / 8 KiB of x one after another with running sums carried across
+    for prm in ({}, {"panel_kib": 16}, {"panel_kib": 1}, {"panel_kib": 1, "panel_xcd": 2},
+                {"panel_kib": 8, "panel_xcd": 2, "stream_nt": 1}):
         for k, y in _run_all(A, dtype, x, kernels=("csr_panel",), params=prm).items():
             assert_parity(y, A, x, dtype)
     for gen in range(4):
         G = (S.band_g0, S.uniform_g1, S.zipf_g2, S.blocks_g3)[gen](np.random.default_rng([46, gen]), 9000)
         xg = S.uniform_vector(G.n, [46, gen])
-        for prm in ({}, {"panel_kib": 8, "panel_xcd": 2}):
+        for prm in ({}, {"panel_kib": 4}, {"panel_kib": 8, "panel_xcd": 2}):
             for k, y in _run_all(G, dtype, xg, kernels=("csr_panel",), params=prm).items():
                 assert_parity(y, G, xg, dtype)
     B = S.stencil_27pt(12)
