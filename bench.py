@@ -187,10 +187,12 @@ def main():
             return f"k_csr_vector<{t}, {p['vector_lanes']}, {nt}>"
         if k == "csr_adaptive":
             return f"k_csr_adaptive<{t}, {nt}>"
+        v = (16 // (8 if t == "double" else 4)) if p["wide_loads"] == 1 else 1
         if k == "ell":
-            return f"k_ell<{t}, {p['ell_unroll']}, {nt}>"
+            return f"k_ell<{t}, {p['ell_unroll']}, {nt}, {v}>"
         if k in ("dia", "dia_direct"):
-            return f"k_{'dia_lds' if k == 'dia' else 'dia_direct'}<{t}, {p['dia_rows_per_thread']}, {nt}>"
+            return (f"k_{'dia_lds' if k == 'dia' else 'dia_direct'}"
+                    f"<{t}, {p['dia_rows_per_thread']}, {nt}, {v}>")
         if k == "coo":
             return f"k_coo<{t}, {nt}> + k_coo_fixup<{t}>"
         if k == "csr_panel":
@@ -217,7 +219,8 @@ def main():
         for mode, name in ((0, "persistent"), (1, "graph")):
             b = Batch([r["tuned"] for r in recs], mode=mode)
             if mode == 0:
-                ml["persistent_grid"] = b.tune(xs, ys)
+                b.tune(xs, ys)
+                ml["persistent_grid"], ml["persistent_split"] = b.shape()
             batches[name] = b
 
         def trial(fn, K=10):

@@ -26,8 +26,8 @@
  *     Launch failures are SPMV_EDEVICE; faults inside a kernel surface at the
  *     caller's next synchronisation.
  *   - Thread safety: distinct plans may be used from distinct threads; one
- *     plan must not run on two streams at the same time (its COO carry and
- *     batch ticket scratch are per plan).
+ *     plan must not run on two streams at the same time (its COO carries,
+ *     split-row partials and panel partial sums are per-plan scratch).
  */
 #ifndef SMAT_SPMV_H
 #define SMAT_SPMV_H
@@ -286,19 +286,28 @@ spmv_status spmv_mlp_adam(float *params_dev, const float *grad_dev, float *adam_
 /* Multilevel batch (the AMG setting of Section 1): run y_l = A_l x_l for all
  * plans in one launch (mode 0, persistent work-queue kernel) or as one
  * captured HIP graph (mode 1).  Plans stay owned by the caller and must
- * outlive the batch.  Persistent mode covers CSR_SCALAR, CSR_VECTOR, ELL,
- * DIA and DIA_DIRECT levels; levels with other kernels are launched
- * separately on the same stream, after the persistent kernel. */
+ * outlive the batch.  Persistent mode covers CSR_SCALAR, CSR_VECTOR,
+ * CSR_ADAPTIVE (unless rows were split into segments), ELL, DIA and
+ * DIA_DIRECT levels, each with its plan's tile shape; levels with other
+ * kernels are launched separately on the same stream, after the persistent
+ * kernel. */
 spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplans, int32_t mode,
                               spmv_batch_t *out);
 spmv_status spmv_batch_run(spmv_batch_t batch, const void *const *xs_dev, void *const *ys_dev,
                            void *stream);
 /* Autotune the persistent launch: time grids of 1, 2, 4, 8 and 16 workgroups
- * per compute unit on the given vectors (outputs are overwritten) and keep
- * the fastest; *grid_out (if not NULL) receives the chosen grid.  No-op for
- * graph mode.  Synchronises `stream`. */
+ * per compute unit, each with 0, 1 or 2 of the leading levels run as their
+ * own kernels before the persistent launch (a level large enough to fill the
+ * GPU alone keeps its own tuned kernel; at least one level stays in the
+ * persistent launch), on the given vectors (outputs are overwritten), and
+ * keep the fastest; *grid_out (if not NULL) receives the chosen grid.  No-op
+ * for graph mode.  Synchronises `stream`. */
 spmv_status spmv_batch_tune(spmv_batch_t batch, const void *const *xs_dev, void *const *ys_dev,
                             int32_t reps, void *stream, int32_t *grid_out);
+/* Persistent-mode launch shape in effect: workgroups of the persistent launch
+ * and the number of leading levels launched on their own (both 0 in graph
+ * mode).  Either pointer may be NULL. */
+spmv_status spmv_batch_shape(spmv_batch_t batch, int32_t *grid, int32_t *split);
 spmv_status spmv_batch_destroy(spmv_batch_t batch);
 
 /* Achievable-bandwidth probe: dst_dev[i] = src_dev[i] for `bytes` bytes

@@ -91,6 +91,7 @@ _SIGS = {
     "spmv_batch_run": (i32, [vp, vp, vp, vp]),
     "spmv_batch_destroy": (i32, [vp]),
     "spmv_batch_tune": (i32, [vp, vp, vp, i32, vp, vp]),
+    "spmv_batch_shape": (i32, [vp, vp, vp]),
     "spmv_stream_copy": (i32, [vp, vp, ctypes.c_size_t, vp]),
     "spmv_status_string": (ctypes.c_char_p, [i32]),
     "spmv_last_error": (ctypes.c_char_p, []),

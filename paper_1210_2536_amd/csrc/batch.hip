@@ -2,8 +2,10 @@
 // hierarchy (the paper's motivation, Section 1: AMG spends most of its time
 // in SpMV over a series of diverse level matrices).  Coarse levels are far
 // too small to fill the GPU on their own, so
-//   mode 0: one persistent launch; workgroups take (level, tile) items from a
-//           global ticket, largest levels first;
+//   mode 0: one persistent launch; workgroup w takes the (level, tile) work
+//           items w, w + grid, w + 2 grid, ... of the list that runs through
+//           the levels in order (largest first), so consecutive workgroups
+//           share a level's tiles and no counter or atomic is involved;
 //   mode 1: the per-level launches captured once into a HIP graph and
 //           replayed.
 // K12 stream copy (achievable HBM bandwidth probe) lives here as well.
@@ -20,14 +22,19 @@ constexpr int kMaxLevels = 16;
 constexpr int kPBlock = 256;   // persistent workgroup size
 constexpr int kPDiaRpt = 4;    // rows per thread of a DIA tile
 
-enum LevelKind { LK_SCALAR = 0, LK_VECTOR = 1, LK_ELL = 3, LK_DIA = 4, LK_DIA_DIRECT = 5 };
+enum LevelKind {
+    LK_SCALAR = 0, LK_VECTOR = 1, LK_ADAPTIVE = 2, LK_ELL = 3, LK_DIA = 4, LK_DIA_DIRECT = 5
+};
 
+// One level: its kernel kind, the tile shape of its plan (wide: a lane owns
+// 16 bytes of consecutive rows in DIA / ELL) and its arrays.
 struct LevelDesc {
-    int kind, lanes, K, D, nwin, nt;
+    int kind, lanes, K, D, nwin, nt, wide;
     int64_t m, n, m_pad, tile_rows, tile_begin;
-    const int32_t *rp, *col, *ecol, *offs;
+    const int32_t *rp, *col, *ecol, *offs, *rows;
     const void *val, *eval, *data;
     const DiaWindow *win;
+    AdaptiveLaunch alaunch;
 };
 
 struct Ptrs {
@@ -49,7 +56,8 @@ __device__ __forceinline__ void vector_tile(const LevelDesc &d, int64_t tile, co
 // kernels, so each row is computed exactly as by the level's own run.
 template <typename T, bool NT>
 __device__ __forceinline__ void batch_item(const LevelDesc &d, int64_t tile, const T *x, T *y,
-                                           T *xs) {
+                                           T *xs, double *part) {
+    constexpr int W = 16 / (int)sizeof(T);
     switch (d.kind) {
     case LK_SCALAR: {
         int64_t i = tile * kPBlock + threadIdx.x;
@@ -67,35 +75,55 @@ __device__ __forceinline__ void batch_item(const LevelDesc &d, int64_t tile, con
         default: vector_tile<T, 64, NT>(d, tile, x, y); break;
         }
         break;
-    case LK_ELL: {
-        int64_t i = tile * kPBlock + threadIdx.x;
-        if (i < d.m) y[i] = (T)ell_row<T, 4, NT>(i, d.m_pad, d.K, d.ecol, (const T *)d.eval, x);
+    case LK_ADAPTIVE:
+        adaptive_block<T, NT>(d.alaunch, (unsigned)tile, d.rows, d.rp, d.col, (const T *)d.val,
+                              x, y, part);
         break;
-    }
+    case LK_ELL:
+        if (d.wide) {
+            int64_t i0 = (tile * kPBlock + threadIdx.x) * W;
+            if (i0 < d.m) {
+                double acc[W];
+                ell_rows_wide<T, 4, W, NT>(i0, d.m, d.m_pad, d.K, d.ecol, (const T *)d.eval, x,
+                                           acc);
+#pragma unroll
+                for (int e = 0; e < W; ++e)
+                    if (i0 + e < d.m) y[i0 + e] = (T)acc[e];
+            }
+        } else {
+            int64_t i = tile * kPBlock + threadIdx.x;
+            if (i < d.m) y[i] = (T)ell_row<T, 4, NT>(i, d.m_pad, d.K, d.ecol, (const T *)d.eval, x);
+        }
+        break;
     case LK_DIA:
-        dia_tile_lds<T, kPDiaRpt, NT>(tile * d.tile_rows, d.m, d.n, d.m_pad, d.offs, d.nwin,
-                                      d.win, (const T *)d.data, x, y, xs);
+        if (d.wide)
+            dia_tile_lds<T, kPDiaRpt, NT, W>(tile * d.tile_rows, d.m, d.n, d.m_pad, d.offs,
+                                             d.nwin, d.win, (const T *)d.data, x, y, xs);
+        else
+            dia_tile_lds<T, kPDiaRpt, NT>(tile * d.tile_rows, d.m, d.n, d.m_pad, d.offs, d.nwin,
+                                          d.win, (const T *)d.data, x, y, xs);
         break;
     default:
-        dia_tile_direct<T, kPDiaRpt, NT>(tile * d.tile_rows, d.m, d.n, d.m_pad, d.D, d.offs,
-                                         (const T *)d.data, x, y);
+        if (d.wide)
+            dia_tile_direct<T, kPDiaRpt, NT, W>(tile * d.tile_rows, d.m, d.n, d.m_pad, d.D,
+                                                d.offs, (const T *)d.data, x, y);
+        else
+            dia_tile_direct<T, kPDiaRpt, NT>(tile * d.tile_rows, d.m, d.n, d.m_pad, d.D, d.offs,
+                                             (const T *)d.data, x, y);
         break;
     }
 }
 
+// Work items base .. total-1 (items below `base` belong to levels launched
+// on their own before this kernel), strided over the grid.
 template <typename T>
 __global__ __launch_bounds__(kPBlock) void k_batch_persistent(const LevelDesc *__restrict__ L,
-                                                              int nlev, int64_t total, Ptrs P,
-                                                              unsigned long long *ticket) {
+                                                              int nlev, int64_t base,
+                                                              int64_t total, Ptrs P) {
     extern __shared__ unsigned char smem_raw[];
     T *xs = reinterpret_cast<T *>(smem_raw);
-    __shared__ long long item;
-    for (;;) {
-        if (threadIdx.x == 0) item = (long long)atomicAdd(&ticket[0], 1ull);
-        __syncthreads();
-        const int64_t t = item;
-        __syncthreads();
-        if (t >= total) break;
+    __shared__ double part[kPBlock / kWave];
+    for (int64_t t = base + blockIdx.x; t < total; t += gridDim.x) {
         int l = 0;
         while (l + 1 < nlev && t >= L[l + 1].tile_begin) ++l;
         const LevelDesc &d = L[l];
@@ -103,18 +131,10 @@ __global__ __launch_bounds__(kPBlock) void k_batch_persistent(const LevelDesc *_
         const T *x = (const T *)P.x[l];
         T *y = (T *)P.y[l];
         if (d.nt)
-            batch_item<T, true>(d, tile, x, y, xs);
+            batch_item<T, true>(d, tile, x, y, xs, part);
         else
-            batch_item<T, false>(d, tile, x, y, xs);
+            batch_item<T, false>(d, tile, x, y, xs, part);
         __syncthreads();  // LDS reuse by the next item
-    }
-    // the last workgroup out re-arms the ticket for the next launch
-    if (threadIdx.x == 0) {
-        unsigned long long prev = atomicAdd(&ticket[1], 1ull);
-        if (prev == gridDim.x - 1) {
-            atomicExch(&ticket[0], 0ull);
-            atomicExch(&ticket[1], 0ull);
-        }
     }
 }
 
@@ -163,8 +183,10 @@ struct spmv_batch_s {
     int elt = 8;
     std::vector<spmv_plan_t> plans;
     std::vector<int> persistent_levels;  // indices handled inside the persistent kernel
+    std::vector<int64_t> tile_begin;     // first work item of each of them
     std::vector<int> extra_levels;       // launched separately
-    smat::Dev desc, ticket;
+    int split = 0;  // leading persistent levels launched as their own kernels instead
+    smat::Dev desc;
     int64_t total_tiles = 0;
     size_t lds_bytes = 0;
     int grid = 0;
@@ -221,6 +243,9 @@ extern "C" spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplan
         d.col = P.col.as<int32_t>();
         d.val = P.val.p;
         d.nt = V.prm.stream_nt == 1;
+        d.wide = V.prm.wide_loads == 1 ? 1 : 0;
+        const int64_t wrows = d.wide ? 16 / P.elt : 1;
+        int64_t ntiles = -1;  // work items of this level (default: rows / tile_rows)
         switch (V.kernel) {
         case SPMV_K_CSR_SCALAR: d.kind = LK_SCALAR; d.tile_rows = kPBlock; break;
         case SPMV_K_CSR_VECTOR:
@@ -228,9 +253,18 @@ extern "C" spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplan
             d.lanes = V.prm.vector_lanes;
             d.tile_rows = kPBlock / d.lanes;
             break;
+        case SPMV_K_CSR_ADAPTIVE:
+            // one work item per workgroup of the level's binned launch; rows
+            // split into segments need their own kernels
+            d.kind = V.nsplit_rows > 0 ? -1 : LK_ADAPTIVE;
+            d.alaunch = V.alaunch;
+            d.rows = V.bin_rows.as<int32_t>();
+            d.tile_rows = 1;
+            ntiles = V.alaunch.first[8];
+            break;
         case SPMV_K_ELL:
             d.kind = LK_ELL;
-            d.tile_rows = kPBlock;
+            d.tile_rows = kPBlock * wrows;
             d.K = V.K;
             d.ecol = V.ecol.as<int32_t>();
             d.eval = V.eval.p;
@@ -238,7 +272,7 @@ extern "C" spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplan
         case SPMV_K_DIA:
         case SPMV_K_DIA_DIRECT:
             d.kind = V.kernel == SPMV_K_DIA ? LK_DIA : LK_DIA_DIRECT;
-            d.tile_rows = (int64_t)kPBlock * kPDiaRpt;
+            d.tile_rows = (int64_t)kPBlock * kPDiaRpt * wrows;
             d.D = V.D;
             d.nwin = V.nwin;
             d.offs = V.dia_off.as<int32_t>();
@@ -257,7 +291,8 @@ extern "C" spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplan
             continue;
         }
         d.tile_begin = tiles;
-        tiles += (P.m + d.tile_rows - 1) / d.tile_rows;
+        B->tile_begin.push_back(tiles);
+        tiles += ntiles >= 0 ? ntiles : (P.m + d.tile_rows - 1) / d.tile_rows;
         B->persistent_levels.push_back(l);
         descs.push_back(d);
     }
@@ -268,12 +303,9 @@ extern "C" spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplan
     }
     spmv_status st = B->desc.alloc(sizeof(LevelDesc) * std::max<size_t>(1, descs.size()));
     if (st != SPMV_OK) return st;
-    st = B->ticket.alloc(2 * sizeof(unsigned long long));
-    if (st != SPMV_OK) return st;
     if (!descs.empty())
         SMAT_HIP(hipMemcpy(B->desc.p, descs.data(), sizeof(LevelDesc) * descs.size(),
                            hipMemcpyHostToDevice));
-    SMAT_HIP(hipMemset(B->ticket.p, 0, B->ticket.bytes));
     int dev = 0, cus = 0;
     SMAT_HIP(hipGetDevice(&dev));
     SMAT_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
@@ -323,15 +355,23 @@ extern "C" spmv_status spmv_batch_run(spmv_batch_t B, const void *const *xs, voi
         P.y[k] = ys[l];
         ++k;
     }
-    if (B->total_tiles > 0) {
+    for (int i = 0; i < B->split; ++i) {
+        const int l = B->persistent_levels[i];
+        spmv_status st = spmv_run(B->plans[l], xs[l], ys[l], s);
+        if (st != SPMV_OK) return st;
+    }
+    const int64_t base = B->split < (int)B->tile_begin.size() ? B->tile_begin[B->split]
+                                                              : B->total_tiles;
+    if (B->total_tiles > base) {
+        const int grid = (int)std::min<int64_t>(B->grid, B->total_tiles - base);
         if (B->elt == 8)
-            k_batch_persistent<double><<<B->grid, kPBlock, B->lds_bytes, s>>>(
-                B->desc.as<LevelDesc>(), (int)B->persistent_levels.size(), B->total_tiles, P,
-                B->ticket.as<unsigned long long>());
+            k_batch_persistent<double><<<grid, kPBlock, B->lds_bytes, s>>>(
+                B->desc.as<LevelDesc>(), (int)B->persistent_levels.size(), base,
+                B->total_tiles, P);
         else
-            k_batch_persistent<float><<<B->grid, kPBlock, B->lds_bytes, s>>>(
-                B->desc.as<LevelDesc>(), (int)B->persistent_levels.size(), B->total_tiles, P,
-                B->ticket.as<unsigned long long>());
+            k_batch_persistent<float><<<grid, kPBlock, B->lds_bytes, s>>>(
+                B->desc.as<LevelDesc>(), (int)B->persistent_levels.size(), base,
+                B->total_tiles, P);
         SMAT_LAUNCHED("batch_persistent");
     }
     for (int l : B->extra_levels) {
@@ -356,35 +396,54 @@ extern "C" spmv_status spmv_batch_tune(spmv_batch_t B, const void *const *xs, vo
         hipEvent_t a, b;
         SMAT_HIP(hipEventCreate(&a));
         SMAT_HIP(hipEventCreate(&b));
-        int best_grid = B->grid;
+        int best_grid = B->grid, best_split = 0;
         float best = 1e30f;
         spmv_status st = SPMV_OK;
-        for (int mult : {1, 2, 4, 8, 16}) {
-            B->grid = (int)std::min<int64_t>(B->total_tiles, (int64_t)cus * mult);
-            st = spmv_batch_run(B, xs, ys, stream);  // warm-up
-            std::vector<float> t;
-            for (int r = 0; r < reps && st == SPMV_OK; ++r) {
-                (void)hipEventRecord(a, s);
-                st = spmv_batch_run(B, xs, ys, stream);
-                (void)hipEventRecord(b, s);
-                (void)hipEventSynchronize(b);
-                float f = 0;
-                (void)hipEventElapsedTime(&f, a, b);
-                t.push_back(f);
-            }
-            if (st != SPMV_OK) break;
-            std::sort(t.begin(), t.end());
-            if (t[t.size() / 2] < best) {
-                best = t[t.size() / 2];
-                best_grid = B->grid;
+        const int npers = (int)B->persistent_levels.size();
+        // leading levels large enough to fill the GPU alone may run faster as
+        // their own (tuned) kernels; at least one level stays persistent
+        for (int split = 0; split <= std::min(2, npers - 1) && st == SPMV_OK; ++split) {
+            B->split = split;
+            for (int mult : {1, 2, 4, 8, 16}) {
+                B->grid = (int)std::min<int64_t>(std::max<int64_t>(1, B->total_tiles),
+                                                 (int64_t)cus * mult);
+                st = spmv_batch_run(B, xs, ys, stream);  // warm-up
+                std::vector<float> t;
+                for (int r = 0; r < reps && st == SPMV_OK; ++r) {
+                    (void)hipEventRecord(a, s);
+                    st = spmv_batch_run(B, xs, ys, stream);
+                    (void)hipEventRecord(b, s);
+                    (void)hipEventSynchronize(b);
+                    float f = 0;
+                    (void)hipEventElapsedTime(&f, a, b);
+                    t.push_back(f);
+                }
+                if (st != SPMV_OK) break;
+                std::sort(t.begin(), t.end());
+                if (t[t.size() / 2] < best) {
+                    best = t[t.size() / 2];
+                    best_grid = B->grid;
+                    best_split = split;
+                }
             }
         }
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);
         B->grid = best_grid;
+        B->split = best_split;
         if (st != SPMV_OK) return st;
     }
     if (grid_out) *grid_out = B->grid;
+    return SPMV_OK;
+}
+
+extern "C" spmv_status spmv_batch_shape(spmv_batch_t B, int32_t *grid, int32_t *split) {
+    if (!B) {
+        set_error("spmv_batch_shape: NULL batch");
+        return SPMV_EINVAL;
+    }
+    if (grid) *grid = B->mode == 0 ? B->grid : 0;
+    if (split) *split = B->mode == 0 ? B->split : 0;
     return SPMV_OK;
 }
 

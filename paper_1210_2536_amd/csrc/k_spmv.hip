@@ -59,23 +59,6 @@ __global__ __launch_bounds__(1024) void k_csr_vector(int64_t nrows,
 // longest bin first: launch position q serves bin 7 - q, where bin 7 gives a
 // whole 256-thread workgroup to each row and bins 6..0 give 64..1 lanes.
 constexpr int kRowBlock = 512;     // split-row segments
-constexpr int kAdaptBlock = 256;
-
-template <typename T, int L, bool NT>
-__device__ __forceinline__ void adaptive_lanes(unsigned local, unsigned rbeg, unsigned rend,
-                                               const int32_t *__restrict__ rows,
-                                               const int32_t *__restrict__ rp,
-                                               const int32_t *__restrict__ col,
-                                               const T *__restrict__ val, const T *__restrict__ x,
-                                               T *__restrict__ y) {
-    int64_t r = (int64_t)rbeg + (int64_t)local * (kAdaptBlock / L) + threadIdx.x / L;
-    int lane = threadIdx.x & (L - 1);
-    if (r < rend) {
-        int64_t row = rows[r];
-        double acc = csr_row_lanes<T, L, NT>(row, lane, rp, col, val, x);
-        if (lane == 0) y[row] = (T)acc;
-    }
-}
 
 template <typename T, bool NT>
 __global__ __launch_bounds__(kAdaptBlock) void k_csr_adaptive(AdaptiveLaunch a,
@@ -86,27 +69,7 @@ __global__ __launch_bounds__(kAdaptBlock) void k_csr_adaptive(AdaptiveLaunch a,
                                                               const T *__restrict__ x,
                                                               T *__restrict__ y) {
     __shared__ double part[kAdaptBlock / kWave];
-    const unsigned bid = blockIdx.x;
-    int q = 0;
-    while (q < 7 && bid >= a.first[q + 1]) ++q;
-    const int b = 7 - q;
-    const unsigned local = bid - a.first[q];
-    const unsigned rb = a.row_begin[b], re = a.row_begin[b + 1];
-    switch (b) {
-    case 7: {
-        int64_t row = rows[rb + local];
-        double s = csr_row_block<T, kAdaptBlock, NT>(row, rp, col, val, x, part);
-        if (threadIdx.x == 0) y[row] = (T)s;
-        break;
-    }
-    case 6: adaptive_lanes<T, 64, NT>(local, rb, re, rows, rp, col, val, x, y); break;
-    case 5: adaptive_lanes<T, 32, NT>(local, rb, re, rows, rp, col, val, x, y); break;
-    case 4: adaptive_lanes<T, 16, NT>(local, rb, re, rows, rp, col, val, x, y); break;
-    case 3: adaptive_lanes<T, 8, NT>(local, rb, re, rows, rp, col, val, x, y); break;
-    case 2: adaptive_lanes<T, 4, NT>(local, rb, re, rows, rp, col, val, x, y); break;
-    case 1: adaptive_lanes<T, 2, NT>(local, rb, re, rows, rp, col, val, x, y); break;
-    default: adaptive_lanes<T, 1, NT>(local, rb, re, rows, rp, col, val, x, y); break;
-    }
+    adaptive_block<T, NT>(a, blockIdx.x, rows, rp, col, val, x, y, part);
 }
 
 // ---------------------------------------------------------------- CSR panels

@@ -86,6 +86,58 @@ __device__ __forceinline__ double csr_row_block(int64_t row, const int32_t *__re
     return block_sum<T, B, NT>(rp[row], rp[row + 1], col, val, x, part);
 }
 
+// Length-binned CSR (one launch serves every bin, longest first).  Workgroup
+// `bid` of the launch geometry `a` finds its bin b (7: a whole workgroup per
+// row; 6..0: 64..1 lanes per row) and its rows in the binned order `rows`.
+constexpr int kAdaptBlock = 256;
+
+template <typename T, int L, bool NT>
+__device__ __forceinline__ void adaptive_lanes(unsigned local, unsigned rbeg, unsigned rend,
+                                               const int32_t *__restrict__ rows,
+                                               const int32_t *__restrict__ rp,
+                                               const int32_t *__restrict__ col,
+                                               const T *__restrict__ val, const T *__restrict__ x,
+                                               T *__restrict__ y) {
+    int64_t r = (int64_t)rbeg + (int64_t)local * (kAdaptBlock / L) + threadIdx.x / L;
+    int lane = threadIdx.x & (L - 1);
+    if (r < rend) {
+        int64_t row = rows[r];
+        double acc = csr_row_lanes<T, L, NT>(row, lane, rp, col, val, x);
+        if (lane == 0) y[row] = (T)acc;
+    }
+}
+
+// Every thread of the (kAdaptBlock-thread) workgroup must call it; `part` is
+// LDS scratch of kAdaptBlock / 64 doubles.
+template <typename T, bool NT>
+__device__ __forceinline__ void adaptive_block(const AdaptiveLaunch &a, unsigned bid,
+                                               const int32_t *__restrict__ rows,
+                                               const int32_t *__restrict__ rp,
+                                               const int32_t *__restrict__ col,
+                                               const T *__restrict__ val, const T *__restrict__ x,
+                                               T *__restrict__ y, double *part) {
+    int q = 0;
+    while (q < 7 && bid >= a.first[q + 1]) ++q;
+    const int b = 7 - q;
+    const unsigned local = bid - a.first[q];
+    const unsigned rb = a.row_begin[b], re = a.row_begin[b + 1];
+    switch (b) {
+    case 7: {
+        int64_t row = rows[rb + local];
+        double s = csr_row_block<T, kAdaptBlock, NT>(row, rp, col, val, x, part);
+        if (threadIdx.x == 0) y[row] = (T)s;
+        break;
+    }
+    case 6: adaptive_lanes<T, 64, NT>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 5: adaptive_lanes<T, 32, NT>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 4: adaptive_lanes<T, 16, NT>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 3: adaptive_lanes<T, 8, NT>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 2: adaptive_lanes<T, 4, NT>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 1: adaptive_lanes<T, 2, NT>(local, rb, re, rows, rp, col, val, x, y); break;
+    default: adaptive_lanes<T, 1, NT>(local, rb, re, rows, rp, col, val, x, y); break;
+    }
+}
+
 // ELL row: slots in order, U slots loaded ahead of use.
 template <typename T, int U, bool NT>
 __device__ __forceinline__ double ell_row(int64_t i, int64_t m_pad, int K,

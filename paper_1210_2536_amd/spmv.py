@@ -284,6 +284,13 @@ class Batch:
                                         ctypes.byref(g)), "spmv_batch_tune")
         return g.value
 
+    def shape(self):
+        """(persistent grid, leading levels launched on their own)."""
+        g, k = ctypes.c_int32(0), ctypes.c_int32(0)
+        C.check(C.lib().spmv_batch_shape(self.handle, ctypes.byref(g), ctypes.byref(k)),
+                "spmv_batch_shape")
+        return g.value, k.value
+
     def close(self):
         h = getattr(self, "handle", None)
         if h and C._lib is not None:

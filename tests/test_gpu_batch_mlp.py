@@ -16,17 +16,24 @@ def _levels():
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
-@pytest.mark.parametrize("kernel", ["dia", "dia_direct", "ell", "csr_vector", "csr_scalar", "mixed"])
+@pytest.mark.parametrize("kernel", ["dia", "dia_direct", "ell", "csr_vector", "csr_scalar",
+                                    "csr_adaptive", "mixed", "dia/wide", "dia_direct/wide",
+                                    "ell/wide", "mixed/wide"])
 def test_batch_equals_per_level_runs(kernel, dtype):
+    """Persistent launch and graph replay give each level's own result bit
+    for bit, for every level kind the persistent kernel takes in (adaptive
+    CSR included), with one-row and 16-byte-wide DIA / ELL tiles."""
     import torch
     from paper_1210_2536_amd.spmv import Batch, Plan
     levels = _levels()
+    kernel, _, wide = kernel.partition("/")
+    prm = {"wide_loads": 1 if wide else 2}
     kinds = (["dia", "ell", "csr_vector", "coo", "csr_adaptive"] if kernel == "mixed"
              else [kernel] * len(levels))
     plans, xs, ys_ref = [], [], []
     for l, (A, k) in enumerate(zip(levels, kinds)):
         rp, col, val = dev(A, dtype)
-        p = Plan(rp, col, val, n=A.n, selector=k)
+        p = Plan(rp, col, val, n=A.n, selector=k, params=prm)
         plans.append(p)
         x = S.uniform_vector(A.n, [4, l])
         xs.append(vec(x, dtype))
@@ -44,6 +51,18 @@ def test_batch_equals_per_level_runs(kernel, dtype):
             torch.cuda.synchronize()
             for y, r in zip(ys, ys_ref):
                 assert np.array_equal(y.cpu().numpy().view(np.uint8), r.view(np.uint8)), (mode, rep)
+        if mode == 0:
+            # the tuned shape (grid, leading levels on their own) changes
+            # nothing in the result
+            B.tune(xs, ys, reps=2)
+            grid, split = B.shape()
+            assert grid >= 1 and 0 <= split <= 2
+            for y in ys:
+                y.fill_(float("nan"))
+            B.run(xs, ys)
+            torch.cuda.synchronize()
+            for y, r in zip(ys, ys_ref):
+                assert np.array_equal(y.cpu().numpy().view(np.uint8), r.view(np.uint8)), "tuned"
 
 
 def test_mlp_forward_backward_adam_match_oracle():
