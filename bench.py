@@ -51,10 +51,11 @@ def kernel_sources_sha256():
     return h.hexdigest()
 
 
-def recorded_traffic(kernel, workload):
+def recorded_traffic(kernel, workload, algorithmic_bytes):
     """HBM bytes per launch of `kernel` on `workload` from the counter records
     committed under profiles/ (lines "traffic-record: {json}"), or None when no
-    record matches or the kernel sources changed since it was taken."""
+    record matches: another kernel or workload, other launches (their
+    algorithmic bytes per launch differ), or changed kernel sources."""
     pdir = os.path.join(ROOT, "profiles")
     if not os.path.isdir(pdir):
         return None
@@ -72,6 +73,7 @@ def recorded_traffic(kernel, workload):
                 except ValueError:
                     continue
                 if (r.get("kernel") == kernel and r.get("workload") == workload
+                        and r.get("algorithmic_bytes_per_launch") == algorithmic_bytes
                         and r.get("sources_sha256") == digest):
                     return int(r["bytes_per_launch"])
     return None
@@ -128,10 +130,12 @@ def main():
     items = workloads.build(a.workload)
     log(f"{len(items)} matrices generated in {time.time() - t_start:.1f}s")
 
-    replay = None
+    replay = replay_step = None
     if a.replay:
         with open(a.replay) as fh:
-            replay = json.load(fh)["records"]
+            rj = json.load(fh)
+        replay = rj["records"]
+        replay_step = rj.get("summary", {}).get("config", {}).get("step")
         assert len(replay) == len(items), "replay records do not match the workload"
 
     recs = []
@@ -239,6 +243,8 @@ def main():
         for name, b in batches.items():
             ml["trial_ms"][name] = trial(lambda b=b: b.run(xs, ys))
         ml["mode"] = min(ml["trial_ms"], key=ml["trial_ms"].get)
+        if replay_step:
+            ml["mode"] = replay_step  # profile the recorded run's step, not this trial's pick
         log(f"multilevel trial (ms/step): {ml['trial_ms']} -> {ml['mode']}")
         if ml["mode"] == "persistent":
             dt_name = "double" if recs[0]["rec"]["dtype"] == "float64" else "float"
@@ -455,7 +461,8 @@ def main():
         "roofline": {"bound": "hbm", "kernel": dominant, "launches_per_step": len(evs) // a.steps,
                      "achieved": round(dom_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(dom_achieved / HBM_PEAK_GBS, 4),
-                     "traffic": recorded_traffic(dominant, workload_name),
+                     "traffic": recorded_traffic(dominant, workload_name,
+                                                 int(np.mean(dom_bytes))),
                      "avg_launch_ms": round(dom_avg_ms, 5),
                      "bytes_per_launch": int(np.mean(dom_bytes))},
         "cpu_baseline": cpu,
