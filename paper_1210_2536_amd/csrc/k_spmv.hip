@@ -80,7 +80,25 @@ __global__ __launch_bounds__(kAdaptBlock) void k_csr_adaptive(AdaptiveLaunch a,
 // the next level.  Rows keep the length-binned order and lane widths of the
 // adaptive kernel, scaled down by the panel count (lane_shift); prow holds,
 // per panel and per binned position, the start of that row's segment.
-template <typename T, int L, bool NT, bool ACC>
+//
+// Where a row's panel sum goes (OUT): 0 stores y[row], 1 adds it to y[row]
+// (panels after the first, one launch per panel), 2 stores it at the row's
+// binned position of the panel's partial vector (all panels in one launch:
+// consecutive lanes write consecutive words; the reduction scatters to y).
+constexpr int kOutStore = 0, kOutAdd = 1, kOutPosition = 2;
+
+template <typename T, int OUT>
+__device__ __forceinline__ void panel_out(int64_t r, const int32_t *__restrict__ rows, double s,
+                                          T *__restrict__ y) {
+    if constexpr (OUT == kOutPosition) {
+        y[r] = (T)s;
+    } else {
+        const int64_t row = rows[r];
+        y[row] = OUT == kOutAdd ? (T)((double)y[row] + s) : (T)s;
+    }
+}
+
+template <typename T, int L, bool NT, int OUT>
 __device__ __forceinline__ void panel_lanes(unsigned local, unsigned rbeg, unsigned rend,
                                             const int32_t *__restrict__ rows,
                                             const int32_t *__restrict__ prow,
@@ -91,15 +109,12 @@ __device__ __forceinline__ void panel_lanes(unsigned local, unsigned rbeg, unsig
     int lane = threadIdx.x & (L - 1);
     if (r < rend) {
         double acc = lanes_sum<T, L, NT>(prow[r], prow[r + 1], lane, col, val, x);
-        if (lane == 0) {
-            int64_t row = rows[r];
-            y[row] = ACC ? (T)((double)y[row] + acc) : (T)acc;
-        }
+        if (lane == 0) panel_out<T, OUT>(r, rows, acc, y);
     }
 }
 
 // Work of workgroup `bid` of one panel's binned launch geometry.
-template <typename T, bool NT, bool ACC>
+template <typename T, bool NT, int OUT>
 __device__ __forceinline__ void panel_block(const AdaptiveLaunch &a, unsigned bid,
                                             const int32_t *__restrict__ rows,
                                             const int32_t *__restrict__ prow,
@@ -114,22 +129,19 @@ __device__ __forceinline__ void panel_block(const AdaptiveLaunch &a, unsigned bi
     if (b == 7) {
         const unsigned r = rb + local;
         double s = block_sum<T, kAdaptBlock, NT>(prow[r], prow[r + 1], col, val, x, part);
-        if (threadIdx.x == 0) {
-            int64_t row = rows[r];
-            y[row] = ACC ? (T)((double)y[row] + s) : (T)s;
-        }
+        if (threadIdx.x == 0) panel_out<T, OUT>(r, rows, s, y);
         return;
     }
     int lb = b - a.lane_shift;
     lb = lb < 0 ? 0 : lb;
     switch (lb) {
-    case 6: panel_lanes<T, 64, NT, ACC>(local, rb, re, rows, prow, col, val, x, y); break;
-    case 5: panel_lanes<T, 32, NT, ACC>(local, rb, re, rows, prow, col, val, x, y); break;
-    case 4: panel_lanes<T, 16, NT, ACC>(local, rb, re, rows, prow, col, val, x, y); break;
-    case 3: panel_lanes<T, 8, NT, ACC>(local, rb, re, rows, prow, col, val, x, y); break;
-    case 2: panel_lanes<T, 4, NT, ACC>(local, rb, re, rows, prow, col, val, x, y); break;
-    case 1: panel_lanes<T, 2, NT, ACC>(local, rb, re, rows, prow, col, val, x, y); break;
-    default: panel_lanes<T, 1, NT, ACC>(local, rb, re, rows, prow, col, val, x, y); break;
+    case 6: panel_lanes<T, 64, NT, OUT>(local, rb, re, rows, prow, col, val, x, y); break;
+    case 5: panel_lanes<T, 32, NT, OUT>(local, rb, re, rows, prow, col, val, x, y); break;
+    case 4: panel_lanes<T, 16, NT, OUT>(local, rb, re, rows, prow, col, val, x, y); break;
+    case 3: panel_lanes<T, 8, NT, OUT>(local, rb, re, rows, prow, col, val, x, y); break;
+    case 2: panel_lanes<T, 4, NT, OUT>(local, rb, re, rows, prow, col, val, x, y); break;
+    case 1: panel_lanes<T, 2, NT, OUT>(local, rb, re, rows, prow, col, val, x, y); break;
+    default: panel_lanes<T, 1, NT, OUT>(local, rb, re, rows, prow, col, val, x, y); break;
     }
 }
 
@@ -143,7 +155,7 @@ __global__ __launch_bounds__(kAdaptBlock) void k_csr_panel(AdaptiveLaunch a,
                                                            const T *__restrict__ x,
                                                            T *__restrict__ y) {
     __shared__ double part[kAdaptBlock / kWave];
-    panel_block<T, NT, ACC>(a, blockIdx.x, rows, prow, col, val, x, y, part);
+    panel_block<T, NT, ACC ? kOutAdd : kOutStore>(a, blockIdx.x, rows, prow, col, val, x, y, part);
 }
 
 // All P = 8 G panels in one launch.  Workgroups are dispatched to the eight
@@ -167,19 +179,21 @@ __global__ __launch_bounds__(kAdaptBlock) void k_csr_panel_xcd(AdaptiveLaunch a,
     const unsigned w = blockIdx.x;
     const int panel = (int)(w % 8u + 8u * (w / (8u * nblk)));
     const unsigned bid = (w / 8u) % nblk;
-    panel_block<T, NT, false>(a, bid, rows, prow + (int64_t)panel * (m + 1), col, val, x,
-                              partial + (int64_t)panel * m, part);
+    panel_block<T, NT, kOutPosition>(a, bid, rows, prow + (int64_t)panel * (m + 1), col, val, x,
+                                     partial + (int64_t)panel * m, part);
     (void)P;
 }
 
+// y[rows[i]] = sum over panels, in panel order, of the partials at binned
+// position i (every row has exactly one position).
 template <typename T>
-__global__ void k_panel_reduce(int P, int64_t m, const T *__restrict__ partial,
-                               T *__restrict__ y) {
+__global__ void k_panel_reduce(int P, int64_t m, const int32_t *__restrict__ rows,
+                               const T *__restrict__ partial, T *__restrict__ y) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= m) return;
     double s = 0.0;
     for (int p = 0; p < P; ++p) s += (double)partial[(int64_t)p * m + i];
-    y[i] = (T)s;
+    y[rows[i]] = (T)s;
 }
 
 // Rows longer than one workgroup may sum alone: segments of a row reduce to
@@ -534,7 +548,7 @@ spmv_status panel_dispatch(const AdaptiveLaunch &a, const int32_t *rows, int P, 
         k_csr_panel_xcd<T, NT><<<nblk * (unsigned)P, kAdaptBlock, 0, s>>>(a, P, m, rows, prow,
                                                                           pcol, pval, x, partial);
         SMAT_LAUNCHED("csr_panel_xcd");
-        k_panel_reduce<T><<<grid_for(m, 256), 256, 0, s>>>(P, m, partial, y);
+        k_panel_reduce<T><<<grid_for(m, 256), 256, 0, s>>>(P, m, rows, partial, y);
         SMAT_LAUNCHED("panel_reduce");
         return SPMV_OK;
     }
