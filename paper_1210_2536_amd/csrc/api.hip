@@ -599,6 +599,11 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
                 return SPMV_EUNSUPPORTED;
             }
             const int64_t L = (int64_t)V.P * (m + 1);
+            if (L >= (1ll << 31)) {
+                set_error("%d column panels x %lld rows exceed the int32 panel row pointers",
+                          V.P, (long long)m);
+                return SPMV_EUNSUPPORTED;
+            }
             Dev inv, cnt, scan;
             SMAT_TRY(inv.alloc(sizeof(int32_t) * std::max<int64_t>(1, m)));
             SMAT_TRY(cnt.alloc(sizeof(int32_t) * (size_t)L));
@@ -800,6 +805,7 @@ std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_
                 int P;
                 panel_geometry(F, dtype == SPMV_F64 ? 8 : 4, p, &w, &P);
                 if (P < 2 || (mode == 2 && dtype == SPMV_F32 && P > 16)) continue;
+                if ((int64_t)P * (F.m + 1) >= (1ll << 31)) continue;  // int32 panel row pointers
                 if (std::find(seen.begin(), seen.end(), std::make_pair(mode, P)) != seen.end())
                     continue;
                 seen.push_back({mode, P});
