@@ -14,6 +14,15 @@ DIA  one lane per occupied diagonal d = j - i (Section 4, Ndiags), offsets
      little-endian uint32 word s >> 5, s = d*m_pad + i) so explicit zeros
      survive the way back.
 
+BCSR b x b blocks (the blocked formats the paper names as its extension,
+     Section 2.1 and the conclusion; b = 4 here).  Block row R covers rows
+     [b*R, b*R + b); its blocks are the distinct column blocks col // b of
+     those rows, ascending (block row pointer brow_ptr, block column bcol).
+     Block k keeps its b*b values row-major at k*b*b + rr*b + cc for entry
+     (b*R + rr, b*bcol[k] + cc); a position with no stored entry holds +0.0,
+     and presence bit k*b*b + rr*b + cc (same packing as DIA) marks stored
+     ones.
+
 Values are moved bit for bit; nothing here does arithmetic on them.
 """
 from __future__ import annotations
@@ -106,3 +115,46 @@ def dia_to_csr(m, n, offsets, m_pad, data, words):
     pt = present.T
     cols = (np.arange(m, dtype=np.int64)[:, None] + offsets[None, :])[pt]
     return rp, cols.astype(np.int32), vals.T[pt]
+
+
+def csr_to_bcsr(m, n, row_ptr, col, val, b=4):
+    """CSR -> (brow_ptr, bcol, bval, words) with b x b blocks."""
+    rp = np.asarray(row_ptr, dtype=np.int64)
+    val = np.asarray(val)
+    rows = _rows_of_entries(rp)
+    cols = np.asarray(col, dtype=np.int64)
+    mb, nb = -(-m // b), -(-n // b)
+    key = (rows // b) * nb + cols // b
+    blocks = np.unique(key)                       # ascending: block row, then block column
+    brow_ptr = np.zeros(mb + 1, dtype=np.int64)
+    np.cumsum(np.bincount(blocks // nb, minlength=mb), out=brow_ptr[1:])
+    k = np.searchsorted(blocks, key)
+    flat = k * (b * b) + (rows % b) * b + cols % b
+    bval = np.zeros(blocks.size * b * b, dtype=val.dtype)
+    bval[flat] = val
+    nbits = blocks.size * b * b
+    present = np.zeros(nbits, dtype=bool)
+    present[flat] = True
+    words = np.packbits(np.concatenate([present, np.zeros((-nbits) % 32, bool)]),
+                        bitorder="little").view(np.uint32) if nbits else np.zeros(0, np.uint32)
+    return brow_ptr, (blocks % nb).astype(np.int32), bval, words
+
+
+def bcsr_to_csr(m, n, brow_ptr, bcol, bval, words, b=4):
+    """Inverse of csr_to_bcsr: the stored entries in CSR order."""
+    brow_ptr = np.asarray(brow_ptr, dtype=np.int64)
+    bcol = np.asarray(bcol, dtype=np.int64)
+    nblk = bcol.size
+    nbits = nblk * b * b
+    bits = np.unpackbits(np.asarray(words, dtype=np.uint32).view(np.uint8),
+                         bitorder="little")[:nbits].astype(bool).reshape(nblk, b, b)
+    brow = np.repeat(np.arange(brow_ptr.size - 1, dtype=np.int64), np.diff(brow_ptr))
+    kk, rr, cc = np.nonzero(bits)
+    rows = brow[kk] * b + rr
+    cols = bcol[kk] * b + cc
+    vals = np.asarray(bval).reshape(nblk, b, b)[kk, rr, cc]
+    order = np.lexsort((cols, rows))
+    rows, cols, vals = rows[order], cols[order], vals[order]
+    rp = np.zeros(m + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=m), out=rp[1:])
+    return rp, cols.astype(np.int32), vals

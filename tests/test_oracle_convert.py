@@ -1,6 +1,6 @@
 """Pins of the oracle's format layouts (CPU only).
 
-Round trips CSR -> {COO, ELL, DIA} -> CSR must be the identity bit for bit
+Round trips CSR -> {COO, ELL, DIA, BCSR} -> CSR must be the identity bit for bit
 (explicit +0.0 / -0.0 and NaN payloads included), and chosen slots of each
 layout are checked against the dense matrix by their definitions.
 """
@@ -70,6 +70,9 @@ def test_round_trips_bit_exact(A, dtype):
     offs, data, words = C.csr_to_dia(m, n, A.row_ptr, A.col, val, m_pad)
     rp2, c2, v2 = C.dia_to_csr(m, n, offs, m_pad, data, words)
     assert np.array_equal(rp2, A.row_ptr) and np.array_equal(c2, A.col) and _same_bits(v2, val)
+    brp, bc, bv, bw = C.csr_to_bcsr(m, n, A.row_ptr, A.col, val)
+    rp2, c2, v2 = C.bcsr_to_csr(m, n, brp, bc, bv, bw)
+    assert np.array_equal(rp2, A.row_ptr) and np.array_equal(c2, A.col) and _same_bits(v2, val)
 
 
 def test_layout_definitions_on_5pt():
@@ -115,3 +118,47 @@ def test_rectangular_dia_offsets_span():
     A = S.random_csr(rng, 7, 19, 0.5)
     offs = C.dia_offsets(A.m, A.n, A.row_ptr, A.col)
     assert offs.min() >= -(A.m - 1) and offs.max() <= A.n - 1
+
+
+def test_bcsr_hand_worked_example():
+    """5 x 6 matrix, 4 x 4 blocks, worked out by hand from the definition:
+    block row 0 (rows 0-3) holds column blocks 0 and 1, block row 1 (row 4)
+    column block 0; an explicit -0.0 keeps its presence bit."""
+    rp = np.array([0, 2, 3, 3, 4, 6])
+    col = np.array([0, 5, 1, 4, 0, 2], np.int32)
+    val = np.array([1.0, 2.0, 3.0, 4.0, 5.0, -0.0])
+    brp, bc, bv, bw = C.csr_to_bcsr(5, 6, rp, col, val)
+    assert brp.tolist() == [0, 2, 3] and bc.tolist() == [0, 1, 0]
+    expect = np.zeros(48)
+    expect[0], expect[5] = 1.0, 3.0            # block 0: (0,0), (1,1)
+    expect[16 + 1], expect[16 + 12] = 2.0, 4.0  # block 1: (0,5) -> rr 0 cc 1; (3,4) -> rr 3 cc 0
+    expect[32 + 0] = 5.0                        # block 2: (4,0); (4,2) is -0.0 at 34
+    assert np.array_equal(bv, expect) and np.signbit(bv[34])
+    assert bw.tolist() == [1 | (1 << 5) | (1 << 17) | (1 << 28), 1 | (1 << 2)]
+
+
+@pytest.mark.parametrize("A", _mats(), ids=lambda A: A.name)
+def test_bcsr_blocks_against_dense(A):
+    """Every block equals the dense matrix's 4 x 4 tile at (4 R, 4 bcol), the
+    tiles not listed are all zero, and the block count is the feature pass's
+    count of nonempty aligned 4 x 4 blocks."""
+    from oracle import features as OF
+    m, n = A.m, A.n
+    mp, np_ = -(-m // 4) * 4, -(-n // 4) * 4
+    dense = np.zeros((mp, np_))
+    rows = np.repeat(np.arange(m), np.diff(A.row_ptr))
+    dense[rows, A.col] = A.val
+    brp, bc, bv, bw = C.csr_to_bcsr(m, n, A.row_ptr, A.col, A.val)
+    listed = np.zeros((mp // 4, np_ // 4), bool)
+    for R in range(mp // 4):
+        for k in range(brp[R], brp[R + 1]):
+            tile = dense[4 * R:4 * R + 4, 4 * bc[k]:4 * bc[k] + 4]
+            assert np.array_equal(bv[16 * k:16 * k + 16].reshape(4, 4), tile)
+            listed[R, bc[k]] = True
+        assert np.all(np.diff(bc[brp[R]:brp[R + 1]]) > 0)
+    tiles = dense.reshape(mp // 4, 4, np_ // 4, 4).swapaxes(1, 2)
+    occupied = np.zeros_like(listed)
+    occupied[rows // 4, A.col // 4] = True
+    assert np.array_equal(listed, occupied)
+    assert np.all(tiles[~listed] == 0)
+    assert bc.size == OF.extract(m, n, A.row_ptr, A.col)["blocks4"]
