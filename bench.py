@@ -199,6 +199,8 @@ def main():
                     f"<{t}, {p['dia_rows_per_thread']}, {nt}, {v}>")
         if k == "coo":
             return f"k_coo<{t}, {nt}> + k_coo_fixup<{t}>"
+        if k == "bcsr":
+            return f"k_bcsr<{t}, {p['bcsr_lanes']}, {nt}>"
         if k == "csr_panel":
             if p["panel_xcd"] != 2:
                 return f"k_csr_panel_xcd<{t}, {nt}> + k_panel_reduce<{t}>"

@@ -50,8 +50,11 @@ typedef enum {
                                 cannot represent this matrix */
 } spmv_status;
 
-/* Storage formats (Section 2.1). */
-typedef enum { SPMV_FMT_CSR = 0, SPMV_FMT_COO = 1, SPMV_FMT_ELL = 2, SPMV_FMT_DIA = 3 } spmv_format;
+/* Storage formats (Section 2.1), plus 4x4 block CSR (the blocked formats the
+ * paper names as its extension, Section 2.1 and the conclusion). */
+typedef enum {
+    SPMV_FMT_CSR = 0, SPMV_FMT_COO = 1, SPMV_FMT_ELL = 2, SPMV_FMT_DIA = 3, SPMV_FMT_BCSR = 4
+} spmv_format;
 
 /* Kernel classes: a format plus an implementation (the paper's "best
  * implementation" per format, Section 3).  These are also the classes the
@@ -67,7 +70,11 @@ typedef enum {
     SPMV_K_COO = 6,           /* COO, wavefront segmented reduction             */
     SPMV_K_CSR_PANEL = 7,     /* CSR cut into column panels whose slice of x
                                  fits in L2, one binned launch per panel     */
-    SPMV_K_COUNT = 8
+    SPMV_K_BCSR = 8,          /* 4x4 block CSR: block row pointer, block
+                                 columns, 16 values per block (row-major,
+                                 absent entries +0.0); a lane group per block
+                                 row, one block per lane and trip          */
+    SPMV_K_COUNT = 9
 } spmv_kernel;
 
 /* How plan creation chooses the kernel (Section 6). */
@@ -121,6 +128,11 @@ typedef struct {
                                    slot of them with one 16-byte load; 2 =
                                    one row per lane; 0 = default (1 from
                                    2^20 rows on, 2 below)                  */
+    int32_t bcsr_lanes;         /* BCSR: lanes per block row, a power of two
+                                   in [1, 64] (0 = default: the mean blocks
+                                   per block row rounded up to a power of
+                                   two; float64 widens it as the 1e-12 bound
+                                   needs)                                   */
 } spmv_params;
 
 typedef struct spmv_selector_s *spmv_selector_t;
@@ -186,6 +198,7 @@ typedef struct {
                                            kernel was measured               */
     double t_tune_ms;                   /* parameter search (autotune), part
                                            of t_convert_ms and t_plan_ms      */
+    int64_t bcsr_blocks;                /* stored 4x4 blocks (BCSR plans)     */
 } spmv_plan_info;
 
 typedef struct spmv_plan_s *spmv_plan_t;
@@ -229,6 +242,11 @@ spmv_status spmv_convert_roundtrip(spmv_plan_t plan, int32_t *row_ptr_dev, int32
  *   2 ELL values (K*m_pad)             3 DIA offsets (int32, D)
  *   4 DIA values (D*m_pad)             5 DIA presence bits (uint32 words)
  *   6 CSR-adaptive row order (int32, m)
+ *   7 BCSR block row pointer (int32, ceil(m/4)+1)
+ *   8 BCSR block columns (int32, blocks)
+ *   9 BCSR values (16 per block, row-major within the block)
+ *  10 BCSR presence bits (uint32 words; bit 16 k + 4 r + c: entry (r, c) of
+ *     block k is stored, so explicit zeros survive the round trip)
  * EINVAL if the plan has no such array or `bytes` is too small.  On success
  * *bytes_out (if not NULL) receives the array size.  Synchronises. */
 spmv_status spmv_plan_export(spmv_plan_t plan, int32_t which, void *dst_dev, size_t bytes,

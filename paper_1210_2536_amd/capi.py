@@ -15,13 +15,13 @@ LIB_PATH = os.environ.get("SMAT_SPMV_LIB") or os.path.join(HERE, "libsmat_spmv.s
 SPMV_F32, SPMV_F64 = 0, 1
 SPMV_OK, SPMV_EINVAL, SPMV_ENOMEM, SPMV_EDEVICE, SPMV_EUNSUPPORTED = 0, -1, -2, -3, -4
 KERNELS = ("csr_scalar", "csr_vector", "csr_adaptive", "ell", "dia", "dia_direct", "coo",
-           "csr_panel")
-K_CSR_SCALAR, K_CSR_VECTOR, K_CSR_ADAPTIVE, K_ELL, K_DIA, K_DIA_DIRECT, K_COO, K_CSR_PANEL = \
-    range(8)
-K_COUNT = 8
-FORMATS = ("csr", "coo", "ell", "dia")
+           "csr_panel", "bcsr")
+(K_CSR_SCALAR, K_CSR_VECTOR, K_CSR_ADAPTIVE, K_ELL, K_DIA, K_DIA_DIRECT, K_COO, K_CSR_PANEL,
+ K_BCSR) = range(9)
+K_COUNT = 9
+FORMATS = ("csr", "coo", "ell", "dia", "bcsr")
 # storage format each kernel runs on (index into FORMATS); column panels are CSR
-FORMAT_OF = (0, 0, 0, 2, 3, 3, 1, 0)
+FORMAT_OF = (0, 0, 0, 2, 3, 3, 1, 0, 4)
 SELECT_RULES, SELECT_MLP, SELECT_EXHAUSTIVE, SELECT_FORCED = range(4)
 
 i32, i64, u32, u64, f32, f64 = (ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32,
@@ -38,7 +38,7 @@ class spmv_params(ctypes.Structure):
     _fields_ = [("block", i32), ("vector_lanes", i32), ("adaptive_rows_per_lane", i32),
                 ("adaptive_wg_min", i32), ("dia_rows_per_thread", i32), ("dia_span", i32),
                 ("coo_chunk", i32), ("ell_unroll", i32), ("stream_nt", i32),
-                ("panel_kib", i32), ("panel_xcd", i32), ("wide_loads", i32)]
+                ("panel_kib", i32), ("panel_xcd", i32), ("wide_loads", i32), ("bcsr_lanes", i32)]
 
 
 class spmv_plan_opts(ctypes.Structure):
@@ -66,7 +66,7 @@ class spmv_plan_info(ctypes.Structure):
                 ("device_bytes", u64), ("t_validate_ms", f64), ("t_features_ms", f64),
                 ("t_select_ms", f64), ("t_convert_ms", f64), ("t_plan_ms", f64),
                 ("mlp_input", f32 * 12), ("rules_kernel", i32),
-                ("out_of_domain", i32), ("t_tune_ms", f64)]
+                ("out_of_domain", i32), ("t_tune_ms", f64), ("bcsr_blocks", i64)]
 
 
 _SIGS = {

@@ -263,6 +263,13 @@ spmv_params resolve_params(int kernel, spmv_params p, const spmv_features &F) {
     // the chip many times over (measured: faster from about a million rows,
     // slower on smaller matrices)
     if (p.wide_loads == 0) p.wide_loads = F.m >= (1 << 20) ? 1 : 2;
+    if (p.bcsr_lanes == 0) {
+        // about one block per lane for a block row of mean length (measured
+        // best on dense 4x4 block matrices)
+        const int64_t mb = std::max<int64_t>(1, (F.m + 3) / 4);
+        const int64_t avg = (std::max<int64_t>(0, F.blocks4) + mb - 1) / mb;
+        p.bcsr_lanes = std::max(1, std::min(64, pow2_ceil(std::max<int64_t>(1, avg))));
+    }
     return p;
 }
 
@@ -279,6 +286,7 @@ void merge_params(spmv_params &p, const spmv_params &u) {
     if (u.panel_kib > 0) p.panel_kib = u.panel_kib;
     if (u.panel_xcd > 0) p.panel_xcd = u.panel_xcd;
     if (u.wide_loads > 0) p.wide_loads = u.wide_loads;
+    if (u.bcsr_lanes > 0) p.bcsr_lanes = u.bcsr_lanes;
 }
 
 spmv_status check_params(const spmv_params &p) {
@@ -322,6 +330,10 @@ spmv_status check_params(const spmv_params &p) {
         set_error("params.wide_loads must be 0 (default), 1 (on) or 2 (off)");
         return SPMV_EINVAL;
     }
+    if (p.bcsr_lanes != 0 && !(pow2(p.bcsr_lanes) && p.bcsr_lanes <= 64)) {
+        set_error("params.bcsr_lanes must be 0 (default) or a power of two <= 64");
+        return SPMV_EINVAL;
+    }
     return SPMV_OK;
 }
 
@@ -360,6 +372,19 @@ uint32_t feasible_mask(const spmv_features &F, int dtype, int64_t m_pad, uint64_
     {
         int64_t per = (int64_t)p.coo_chunk * kWave;
         if (!f64 || F.max_rd <= kCooMaxChunksPerRow * per) mask |= 1u << SPMV_K_COO;
+    }
+    {
+        // BCSR 4x4: the zero-fill rule (Section 2.3) applied to blocks --
+        // stored block slots at most 20x the entries (fill >= 5%) -- plus the
+        // storage cap; float64 chains: a lane adds at most
+        // 4 ceil(4 max_RD / L) products per row, L <= 64.
+        const uint64_t nb = (uint64_t)std::max<int64_t>(0, F.blocks4);
+        const uint64_t mb = (uint64_t)(F.m + 3) / 4;
+        const uint64_t bytes = nb * (uint64_t)(16 * elt + 6) + 4u * (mb + 1);
+        bool ok = nb > 0 && 16u * nb <= 20u * (uint64_t)F.nnz && bytes <= cap &&
+                  16u * nb < (1ull << 31);
+        if (f64 && 4 * ((4 * F.max_rd + 63) / 64) + 6 > kFp64MaxDepth) ok = false;
+        if (ok) mask |= 1u << SPMV_K_BCSR;
     }
     {
         // Column panels pay off only when x does not fit one panel.  In
@@ -427,6 +452,37 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
     case SPMV_K_CSR_SCALAR:
     case SPMV_K_CSR_VECTOR:
         return SPMV_OK;
+    case SPMV_K_BCSR: {
+        const int64_t mb = (m + 3) / 4;
+        Dev counts, scan;
+        SMAT_TRY(counts.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(1, mb)));
+        SMAT_TRY(scan.alloc(sizeof(unsigned) * (size_t)(mb / 4096 + 2)));
+        SMAT_TRY(V.brp.alloc(sizeof(int32_t) * (size_t)(mb + 1)));
+        SMAT_TRY(launch_bcsr_count(m, P.rp.as<int32_t>(), P.col.as<int32_t>(),
+                                   counts.as<int32_t>(), V.brp.as<int32_t>(), scan.as<unsigned>(),
+                                   s));
+        int32_t nb = 0;
+        SMAT_HIP(hipMemcpyAsync(&nb, V.brp.as<int32_t>() + mb, sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s));
+        SMAT_HIP(hipStreamSynchronize(s));
+        V.nblocks = nb;
+        SMAT_TRY(V.bcol.alloc(sizeof(int32_t) * (size_t)std::max<int64_t>(1, nb)));
+        SMAT_TRY(V.bval.alloc((size_t)elt * 16 * (size_t)std::max<int64_t>(1, nb)));
+        SMAT_TRY(V.bpres.alloc(sizeof(uint32_t) * (size_t)((nb + 1) / 2 + 1)));
+        SMAT_HIP(hipMemsetAsync(V.bval.p, 0, V.bval.bytes, s));
+        SMAT_HIP(hipMemsetAsync(V.bpres.p, 0, V.bpres.bytes, s));
+        SMAT_TRY(launch_csr_to_bcsr(m, P.rp.as<int32_t>(), P.col.as<int32_t>(), P.val.p, elt,
+                                    V.brp.as<int32_t>(), V.bcol.as<int32_t>(), V.bval.p,
+                                    V.bpres.as<uint16_t>(), s));
+        if (P.dtype == SPMV_F64) {
+            // keep every lane's chain within the float64 bound
+            int L = V.prm.bcsr_lanes;
+            while (L < 64 && 4 * ((4 * F.max_rd + L - 1) / L) + ilog2(L) > kFp64MaxDepth) L *= 2;
+            V.prm.bcsr_lanes = L;
+        }
+        SMAT_HIP(hipStreamSynchronize(s));
+        return SPMV_OK;
+    }
     case SPMV_K_COO: {
         SMAT_TRY(V.row_idx.alloc(sizeof(int32_t) * (size_t)nnz));
         SMAT_TRY(launch_csr_to_coo(m, nnz, P.rp.as<int32_t>(), V.row_idx.as<int32_t>(), s));
@@ -655,6 +711,9 @@ spmv_status run_variant(const spmv_plan_s &P, const Variant &V, const void *x, v
         return run_csr_panels(elt, nt, V.alaunch, V.bin_rows.as<int32_t>(), V.P, m,
                               V.prow.as<int32_t>(), V.pcol.as<int32_t>(), V.pval.p, x, y,
                               V.prm.panel_xcd != 2 ? V.ppart.p : nullptr, s);
+    case SPMV_K_BCSR:
+        return run_bcsr(elt, nt, m, P.n, V.brp.as<int32_t>(), V.bcol.as<int32_t>(), V.bval.p, x,
+                        y, V.prm.bcsr_lanes, std::min(V.prm.block, 256), s);
     case SPMV_K_ELL:
         return run_ell(elt, nt, m, P.m_pad, V.K, V.ecol.as<int32_t>(), V.eval.p, x, y,
                        V.prm.block, V.prm.ell_unroll, V.prm.wide_loads == 1, s);
@@ -794,6 +853,15 @@ std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_
                         add(p);
                     }
         break;
+    case SPMV_K_BCSR:
+        for (int f : {1, 2, 4})  // lanes at half, equal and twice the default
+            for (int nt : nts) {
+                spmv_params p = b;
+                p.bcsr_lanes = std::max(1, std::min(64, b.bcsr_lanes * f / 2));
+                p.stream_nt = nt;
+                add(p);
+            }
+        break;
     case SPMV_K_CSR_PANEL: {
         std::vector<std::pair<int, int>> seen;  // (mode, P): kib values giving equal panels
         for (int mode : {1, 2})  // 1: eight panels at a time, one launch; 2: sequential
@@ -895,7 +963,8 @@ extern "C" const char *spmv_last_error(void) { return g_err; }
 
 extern "C" const char *spmv_kernel_name(int32_t k) {
     static const char *names[] = {"csr_scalar", "csr_vector", "csr_adaptive", "ell",
-                                  "dia",        "dia_direct", "coo",          "csr_panel"};
+                                  "dia",        "dia_direct", "coo",          "csr_panel",
+                                  "bcsr"};
     return (k >= 0 && k < SPMV_K_COUNT) ? names[k] : "invalid";
 }
 
@@ -1033,7 +1102,7 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
         bool structural_ok = (all >> opts.force_kernel) & 1u;
         // DIA and ELL need their zero-fill feasibility; the others always run
         if (!structural_ok && (opts.force_kernel == SPMV_K_DIA || opts.force_kernel == SPMV_K_DIA_DIRECT ||
-                               opts.force_kernel == SPMV_K_ELL)) {
+                               opts.force_kernel == SPMV_K_ELL || opts.force_kernel == SPMV_K_BCSR)) {
             set_error("forced kernel %s is infeasible for this matrix (zero fill)",
                       spmv_kernel_name(opts.force_kernel));
             return SPMV_EINVAL;
@@ -1157,7 +1226,9 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
     I.format = (chosen <= SPMV_K_CSR_ADAPTIVE || chosen == SPMV_K_CSR_PANEL) ? SPMV_FMT_CSR
                : chosen == SPMV_K_ELL          ? SPMV_FMT_ELL
                : chosen == SPMV_K_COO          ? SPMV_FMT_COO
+               : chosen == SPMV_K_BCSR         ? SPMV_FMT_BCSR
                                                : SPMV_FMT_DIA;
+    I.bcsr_blocks = P->var->nblocks;
     I.params = P->var->prm;
     I.ell_width = P->var->K;
     I.dia_ndiags = P->var->D;
@@ -1255,6 +1326,11 @@ extern "C" spmv_status spmv_convert_roundtrip(spmv_plan_t P, int32_t *rp, int32_
         SMAT_TRY(launch_ell_to_csr(m, P->m_pad, V.K, V.ecol.as<int32_t>(), V.eval.p, elt, rp, col,
                                    val, counts.as<int32_t>(), scan.as<unsigned>(), s));
         break;
+    case SPMV_K_BCSR:
+        SMAT_TRY(launch_bcsr_to_csr(m, V.brp.as<int32_t>(), V.bcol.as<int32_t>(), V.bval.p,
+                                    V.bpres.as<uint16_t>(), elt, rp, col, val,
+                                    counts.as<int32_t>(), scan.as<unsigned>(), s));
+        break;
     case SPMV_K_CSR_PANEL:
         SMAT_TRY(launch_panels_to_csr(m, V.bin_rows.as<int32_t>(), V.P, V.prow.as<int32_t>(),
                                       V.pcol.as<int32_t>(), V.pval.p, elt, rp, col, val,
@@ -1305,10 +1381,22 @@ extern "C" spmv_status spmv_plan_export(spmv_plan_t P, int32_t which, void *dst,
     case 6:
         if (V.kernel == SPMV_K_CSR_ADAPTIVE || V.kernel == SPMV_K_CSR_PANEL) { src = V.bin_rows.p; n = sizeof(int32_t) * P->m; }
         break;
+    case 7:
+        if (V.kernel == SPMV_K_BCSR) { src = V.brp.p; n = sizeof(int32_t) * (size_t)((P->m + 3) / 4 + 1); }
+        break;
+    case 8:
+        if (V.kernel == SPMV_K_BCSR) { src = V.bcol.p; n = sizeof(int32_t) * (size_t)V.nblocks; }
+        break;
+    case 9:
+        if (V.kernel == SPMV_K_BCSR) { src = V.bval.p; n = (size_t)P->elt * 16 * (size_t)V.nblocks; }
+        break;
+    case 10:
+        if (V.kernel == SPMV_K_BCSR) { src = V.bpres.p; n = sizeof(uint32_t) * (size_t)((V.nblocks + 1) / 2); }
+        break;
     default:
         break;
     }
-    if (!src && n == 0 && which >= 0 && which <= 6 && bytes_out) {
+    if (!src && n == 0 && which >= 0 && which <= 10 && bytes_out) {
         // an empty array of a present format
     }
     if (!src) {

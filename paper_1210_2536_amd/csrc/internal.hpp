@@ -89,6 +89,23 @@ spmv_status launch_dia_to_csr(int64_t m, int64_t n, int64_t m_pad, int D, const 
                               const void *data, const uint32_t *present, int elt, int32_t *rp,
                               int32_t *col, void *val, int32_t *counts, unsigned int *scratch,
                               hipStream_t s);
+// 4x4 block CSR (block row R = rows 4R..4R+3): block counts per block row
+// and their exclusive scan (brp, ceil(m/4)+1 entries; scratch as below),
+// then block columns, zero-filled-beforehand values (16 per block,
+// row-major) and 16 presence bits per block; the inverse for round trips.
+spmv_status launch_bcsr_count(int64_t m, const int32_t *rp, const int32_t *col, int32_t *counts,
+                              int32_t *brp, unsigned int *scratch, hipStream_t s);
+spmv_status launch_csr_to_bcsr(int64_t m, const int32_t *rp, const int32_t *col, const void *val,
+                               int elt, const int32_t *brp, int32_t *bcol, void *bval,
+                               uint16_t *pres, hipStream_t s);
+spmv_status launch_bcsr_to_csr(int64_t m, const int32_t *brp, const int32_t *bcol,
+                               const void *bval, const uint16_t *pres, int elt, int32_t *rp,
+                               int32_t *col, void *val, int32_t *counts, unsigned int *scratch,
+                               hipStream_t s);
+// BCSR SpMV: `lanes` lanes per block row (power of two <= 64).
+spmv_status run_bcsr(int elt, bool nt, int64_t m, int64_t n, const int32_t *brp,
+                     const int32_t *bcol, const void *bval, const void *x, void *y, int lanes,
+                     int block, hipStream_t s);
 // scratch: at least ceil(m / 4096) unsigned ints
 spmv_status launch_exclusive_scan_rows(int64_t m, const int32_t *counts, int32_t *rp,
                                        unsigned int *scratch, hipStream_t s);

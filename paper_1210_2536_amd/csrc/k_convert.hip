@@ -339,7 +339,114 @@ __global__ void k_bin_scatter(int64_t m, const int32_t *__restrict__ rp, BinSpec
     }
 }
 
+// ---------------------------------------------------------------- BCSR 4x4
+// One thread per block row R (rows 4R..4R+3): the distinct column blocks
+// col >> 2 of those rows, ascending, by a 4-way merge of the sorted rows.
+__device__ __forceinline__ void bcsr_rows(int64_t R, int64_t m, const int32_t *__restrict__ rp,
+                                          int32_t (&p)[4], int32_t (&e)[4]) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        int64_t r = 4 * R + k;
+        p[k] = r < m ? rp[r] : 0;
+        e[k] = r < m ? rp[r + 1] : 0;
+    }
+}
+
+__device__ __forceinline__ int32_t bcsr_next_block(const int32_t (&p)[4], const int32_t (&e)[4],
+                                                   const int32_t *__restrict__ col) {
+    int32_t c = INT32_MAX;
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (p[k] < e[k]) c = min(c, col[p[k]] >> 2);
+    return c;
+}
+
+__global__ void k_bcsr_count(int64_t mb, int64_t m, const int32_t *__restrict__ rp,
+                             const int32_t *__restrict__ col, int32_t *__restrict__ counts) {
+    int64_t R = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (R >= mb) return;
+    int32_t p[4], e[4];
+    bcsr_rows(R, m, rp, p, e);
+    int32_t cnt = 0;
+    for (int32_t c = bcsr_next_block(p, e, col); c != INT32_MAX; c = bcsr_next_block(p, e, col)) {
+        ++cnt;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            while (p[k] < e[k] && (col[p[k]] >> 2) == c) ++p[k];
+    }
+    counts[R] = cnt;
+}
+
+// Values are moved as bit patterns (U = uint32 / uint64); bval must be
+// zero-filled beforehand.  pres holds 16 presence bits per block.
+template <typename U>
+__global__ void k_bcsr_fill(int64_t mb, int64_t m, const int32_t *__restrict__ rp,
+                            const int32_t *__restrict__ col, const U *__restrict__ val,
+                            const int32_t *__restrict__ brp, int32_t *__restrict__ bcol,
+                            U *__restrict__ bval, uint16_t *__restrict__ pres) {
+    int64_t R = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (R >= mb) return;
+    int32_t p[4], e[4];
+    bcsr_rows(R, m, rp, p, e);
+    int64_t kb = brp[R];
+    for (int32_t c = bcsr_next_block(p, e, col); c != INT32_MAX;
+         c = bcsr_next_block(p, e, col), ++kb) {
+        bcol[kb] = c;
+        unsigned bits = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k)
+            while (p[k] < e[k] && (col[p[k]] >> 2) == c) {
+                const int cc = col[p[k]] & 3;
+                bval[kb * 16 + k * 4 + cc] = val[p[k]];
+                bits |= 1u << (k * 4 + cc);
+                ++p[k];
+            }
+        pres[kb] = (uint16_t)bits;
+    }
+}
+
+// Inverse: per row, the count of stored entries, then the entries in block
+// order (ascending columns).
+__global__ void k_bcsr_rowcount(int64_t mb, int64_t m, const int32_t *__restrict__ brp,
+                                const uint16_t *__restrict__ pres, int32_t *__restrict__ counts) {
+    int64_t R = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (R >= mb) return;
+    int32_t c[4] = {0, 0, 0, 0};
+    for (int64_t kb = brp[R]; kb < brp[R + 1]; ++kb) {
+        const unsigned bits = pres[kb];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[k] += __popc((bits >> (4 * k)) & 15u);
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        if (4 * R + k < m) counts[4 * R + k] = c[k];
+}
+
+template <typename U>
+__global__ void k_bcsr_gather(int64_t mb, int64_t m, const int32_t *__restrict__ brp,
+                              const int32_t *__restrict__ bcol, const U *__restrict__ bval,
+                              const uint16_t *__restrict__ pres, const int32_t *__restrict__ rp,
+                              int32_t *__restrict__ col, U *__restrict__ val) {
+    int64_t R = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (R >= mb) return;
+    for (int k = 0; k < 4; ++k) {
+        const int64_t r = 4 * R + k;
+        if (r >= m) break;
+        int64_t q = rp[r];
+        for (int64_t kb = brp[R]; kb < brp[R + 1]; ++kb) {
+            const unsigned bits = pres[kb];
+            for (int cc = 0; cc < 4; ++cc)
+                if ((bits >> (4 * k + cc)) & 1u) {
+                    col[q] = bcol[kb] * 4 + cc;
+                    val[q] = bval[kb * 16 + k * 4 + cc];
+                    ++q;
+                }
+        }
+    }
+}
+
 }  // namespace
+
 
 spmv_status launch_csr_to_coo(int64_t m, int64_t nnz, const int32_t *rp, int32_t *row_idx,
                               hipStream_t s) {
@@ -489,6 +596,52 @@ spmv_status launch_bin_rows(int64_t m, const int32_t *rp, const BinSpec &spec,
     SMAT_LAUNCHED("bin_scan");
     k_bin_scatter<<<nblk, kBlock, 0, s>>>(m, rp, spec, block_counts, rows_out);
     SMAT_LAUNCHED("bin_scatter");
+    return SPMV_OK;
+}
+
+spmv_status launch_bcsr_count(int64_t m, const int32_t *rp, const int32_t *col, int32_t *counts,
+                              int32_t *brp, unsigned int *scratch, hipStream_t s) {
+    const int64_t mb = (m + 3) / 4;
+    if (mb > 0) {
+        k_bcsr_count<<<grid_for(mb, kBlock), kBlock, 0, s>>>(mb, m, rp, col, counts);
+        SMAT_LAUNCHED("bcsr_count");
+    }
+    return launch_exclusive_scan_rows(mb, counts, brp, scratch, s);
+}
+
+spmv_status launch_csr_to_bcsr(int64_t m, const int32_t *rp, const int32_t *col, const void *val,
+                               int elt, const int32_t *brp, int32_t *bcol, void *bval,
+                               uint16_t *pres, hipStream_t s) {
+    const int64_t mb = (m + 3) / 4;
+    if (mb == 0) return SPMV_OK;
+    if (elt == 8)
+        k_bcsr_fill<uint64_t><<<grid_for(mb, kBlock), kBlock, 0, s>>>(
+            mb, m, rp, col, (const uint64_t *)val, brp, bcol, (uint64_t *)bval, pres);
+    else
+        k_bcsr_fill<uint32_t><<<grid_for(mb, kBlock), kBlock, 0, s>>>(
+            mb, m, rp, col, (const uint32_t *)val, brp, bcol, (uint32_t *)bval, pres);
+    SMAT_LAUNCHED("bcsr_fill");
+    return SPMV_OK;
+}
+
+spmv_status launch_bcsr_to_csr(int64_t m, const int32_t *brp, const int32_t *bcol,
+                               const void *bval, const uint16_t *pres, int elt, int32_t *rp,
+                               int32_t *col, void *val, int32_t *counts, unsigned int *scratch,
+                               hipStream_t s) {
+    const int64_t mb = (m + 3) / 4;
+    if (mb > 0) {
+        k_bcsr_rowcount<<<grid_for(mb, kBlock), kBlock, 0, s>>>(mb, m, brp, pres, counts);
+        SMAT_LAUNCHED("bcsr_rowcount");
+    }
+    spmv_status st = launch_exclusive_scan_rows(m, counts, rp, scratch, s);
+    if (st != SPMV_OK || mb == 0) return st;
+    if (elt == 8)
+        k_bcsr_gather<uint64_t><<<grid_for(mb, kBlock), kBlock, 0, s>>>(
+            mb, m, brp, bcol, (const uint64_t *)bval, pres, rp, col, (uint64_t *)val);
+    else
+        k_bcsr_gather<uint32_t><<<grid_for(mb, kBlock), kBlock, 0, s>>>(
+            mb, m, brp, bcol, (const uint32_t *)bval, pres, rp, col, (uint32_t *)val);
+    SMAT_LAUNCHED("bcsr_gather");
     return SPMV_OK;
 }
 

@@ -287,6 +287,65 @@ __global__ __launch_bounds__(256) void k_dia_direct(int64_t m, int64_t n, int64_
     dia_tile_direct<T, RPT, NT, V>(r0, m, n, m_pad, D, offs, data, x, y);
 }
 
+// ---------------------------------------------------------------- BCSR 4x4
+// A group of L lanes per block row (4 rows); lane l takes blocks l, l+L, ...
+// of its block row.  A block's 16 values (row-major) arrive in 16-byte
+// loads, its 4 x values in one (element-aligned) load away from the last
+// column block; each lane keeps one running sum per row (products of a
+// block in column order), and the L lanes' sums are added by xor shuffles.
+// Zero-filled positions add exact zeros.
+template <typename T, int L, bool NT>
+__global__ __launch_bounds__(256) void k_bcsr(int64_t mb, int64_t m, int64_t n,
+                                              const int32_t *__restrict__ brp,
+                                              const int32_t *__restrict__ bcol,
+                                              const T *__restrict__ bval,
+                                              const T *__restrict__ x, T *__restrict__ y) {
+    constexpr int V = 16 / (int)sizeof(T);   // values per 16-byte load
+    typedef T vec __attribute__((ext_vector_type(V)));
+    typedef T vec4 __attribute__((ext_vector_type(4)));
+    const int64_t R = (int64_t)blockIdx.x * (blockDim.x / L) + threadIdx.x / L;
+    const int lane = threadIdx.x & (L - 1);
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (R < mb) {
+        const int32_t kb = brp[R], ke = brp[R + 1];
+        for (int32_t k = kb + lane; k < ke; k += L) {
+            T v[16];
+            const vec *src = reinterpret_cast<const vec *>(bval + (int64_t)k * 16);
+#pragma unroll
+            for (int q = 0; q < 16 / V; ++q) {
+                vec w = ld<NT>(src + q);
+#pragma unroll
+                for (int e = 0; e < V; ++e) v[q * V + e] = w[e];
+            }
+            const int64_t c0 = (int64_t)ld<NT>(bcol + k) * 4;
+            T xv[4];
+            if (c0 + 4 <= n) {
+                vec4 t;
+                __builtin_memcpy(&t, x + c0, sizeof(t));
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) xv[cc] = t[cc];
+            } else {
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) xv[cc] = c0 + cc < n ? x[c0 + cc] : T(0);
+            }
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc)
+                    acc[rr] = fma((double)v[rr * 4 + cc], (double)xv[cc], acc[rr]);
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) acc[rr] += __shfl_xor(acc[rr], off, L);
+    if (R < mb && lane == 0) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+            if (4 * R + rr < m) y[4 * R + rr] = (T)acc[rr];
+    }
+}
+
 // ---------------------------------------------------------------- COO
 // Each wavefront owns a chunk of E*64 consecutive entries (rows ascending).
 // Per trip the 64 lanes form their products and run a segmented inclusive
@@ -563,7 +622,38 @@ spmv_status panel_dispatch(const AdaptiveLaunch &a, const int32_t *rows, int P, 
     return SPMV_OK;
 }
 
+template <typename T, bool NT>
+spmv_status bcsr_dispatch(int64_t m, int64_t n, const int32_t *brp, const int32_t *bcol,
+                          const T *bval, const T *x, T *y, int lanes, int block, hipStream_t s) {
+    const int64_t mb = (m + 3) / 4;
+    if (mb == 0) return SPMV_OK;
+    if (block <= 0 || block > 256) block = 256;
+    if (lanes < 1 || lanes > 64 || (lanes & (lanes - 1)) || lanes > block) {
+        set_error("bcsr: lanes must be a power of two in [1, min(64, block)], got %d", lanes);
+        return SPMV_EINVAL;
+    }
+    const unsigned g = grid_for(mb, block / lanes);
+#define L_CASE(L)                                                                            \
+    case L: k_bcsr<T, L, NT><<<g, block, 0, s>>>(mb, m, n, brp, bcol, bval, x, y); break;
+    switch (lanes) {
+        L_CASE(1) L_CASE(2) L_CASE(4) L_CASE(8) L_CASE(16) L_CASE(32) L_CASE(64)
+    }
+#undef L_CASE
+    SMAT_LAUNCHED("bcsr");
+    return SPMV_OK;
+}
+
 }  // namespace
+
+spmv_status run_bcsr(int elt, bool nt, int64_t m, int64_t n, const int32_t *brp,
+                     const int32_t *bcol, const void *bval, const void *x, void *y, int lanes,
+                     int block, hipStream_t s) {
+#define CALL(T, NT)                                                                         \
+    bcsr_dispatch<T, NT>(m, n, brp, bcol, (const T *)bval, (const T *)x, (T *)y, lanes, block, s)
+    return elt == 8 ? (nt ? CALL(double, true) : CALL(double, false))
+                    : (nt ? CALL(float, true) : CALL(float, false));
+#undef CALL
+}
 
 spmv_status run_csr_panels(int elt, bool nt, const AdaptiveLaunch &a, const int32_t *rows, int P,
                            int64_t m, const int32_t *prow, const int32_t *pcol, const void *pval,

@@ -59,12 +59,15 @@ struct Variant {
     int P = 0;
     int64_t panel_w = 0;
     int64_t nsplit_rows = 0, nsplit_segs = 0;
+    // BCSR 4x4
+    Dev brp, bcol, bval, bpres;
+    int64_t nblocks = 0;
     uint64_t bytes() const {
         return row_idx.bytes + coo_head.bytes + coo_tail.bytes + coo_flags.bytes + ecol.bytes +
                eval.bytes + dia_off.bytes + dia_data.bytes + dia_present.bytes + dia_win.bytes +
                bin_rows.bytes + bin_scratch.bytes + split_segs.bytes + split_partials.bytes +
                split_begin.bytes + split_rows.bytes + prow.bytes + pcol.bytes + pval.bytes +
-               ppart.bytes;
+               ppart.bytes + brp.bytes + bcol.bytes + bval.bytes + bpres.bytes;
     }
 };
 

@@ -28,7 +28,9 @@ KERNEL_FORMAT = {"csr_scalar": "csr", "csr_vector": "csr", "csr_adaptive": "csr"
                  "ell": "ell", "dia": "dia", "dia_direct": "dia", "coo": "coo"}
 
 
-def algorithmic_bytes(fmt, m, n, nnz, s, K=0, D=0):
+def algorithmic_bytes(fmt, m, n, nnz, s, K=0, D=0, blocks=0):
+    if fmt == "bcsr":   # 4x4 blocks: 16 values + a block column each, block row pointers
+        return blocks * (16 * s + 4) + 4 * ((m + 3) // 4 + 1) + s * (n + m)
     if fmt == "csr":
         return nnz * (s + 4) + 4 * (m + 1) + s * (n + m)
     if fmt == "coo":
@@ -45,7 +47,8 @@ def plan_bytes(info):
     s = 8 if info["dtype"] == 1 else 4
     fmt = info["format_name"]
     return algorithmic_bytes(fmt, info["m"], info["n"], info["nnz"], s,
-                             K=info.get("ell_width", 0), D=info.get("dia_ndiags", 0))
+                             K=info.get("ell_width", 0), D=info.get("dia_ndiags", 0),
+                             blocks=info.get("bcsr_blocks", 0))
 
 
 def sweep(threads=8, count=S.SWEEP_SIZE):

@@ -45,8 +45,11 @@ def test_roundtrip_bit_exact_and_layouts(dtype):
         val = _poisoned(A.val, dtype)
         B = S.CSR(A.m, A.n, A.row_ptr, A.col, val, A.name)
         f = OF.extract(A.m, A.n, A.row_ptr, A.col)
-        for k in ("csr_vector", "csr_adaptive", "coo", "ell", "dia", "dia_direct", "csr_panel"):
+        for k in ("csr_vector", "csr_adaptive", "coo", "ell", "dia", "dia_direct", "csr_panel",
+                  "bcsr"):
             if k == "ell" and not f["ell_feasible"]:
+                continue
+            if k == "bcsr" and not (f["blocks4"] > 0 and 16 * f["blocks4"] <= 20 * f["NNZ"]):
                 continue
             if k.startswith("dia") and not f["dia_feasible"]:
                 continue
@@ -76,6 +79,13 @@ def test_roundtrip_bit_exact_and_layouts(dtype):
             if k in ("csr_adaptive", "csr_panel"):
                 order = p.export(6).cpu().numpy().view(np.int32)
                 assert np.array_equal(np.sort(order), np.arange(A.m))
+            if k == "bcsr":
+                brp, bc, bv, bw = OC.csr_to_bcsr(A.m, A.n, A.row_ptr, A.col, val)
+                assert info["bcsr_blocks"] == bc.size
+                assert np.array_equal(p.export(7).cpu().numpy().view(np.int32), brp)
+                assert np.array_equal(p.export(8).cpu().numpy().view(np.int32), bc)
+                assert np.array_equal(p.export(9).cpu().numpy(), bv.view(np.uint8))
+                assert np.array_equal(p.export(10).cpu().numpy().view(np.uint32), bw)
 
 
 def test_features_match_oracle():

@@ -16,7 +16,7 @@ from gpu_util import assert_parity, dev, note, vec
 pytestmark = pytest.mark.gpu
 
 KERNELS = ("csr_scalar", "csr_vector", "csr_adaptive", "ell", "dia", "dia_direct", "coo",
-           "csr_panel")
+           "csr_panel", "bcsr")
 DTYPES = (np.float64, np.float32)
 
 
@@ -36,6 +36,9 @@ def _feasible(A, kernel):
         return f["ell_feasible"]
     if kernel in ("dia", "dia_direct"):
         return f["dia_feasible"]
+    if kernel == "bcsr":
+        # zero-fill rule on 4x4 blocks: stored slots at most 20x the entries
+        return f["blocks4"] > 0 and 16 * f["blocks4"] <= 20 * f["NNZ"]
     return True
 
 
@@ -162,6 +165,16 @@ def test_tiny_tiles_force_every_boundary(dtype):
         for prm in ({}, {"panel_kib": 4}, {"panel_kib": 8, "panel_xcd": 2}):
             for k, y in _run_all(G, dtype, xg, kernels=("csr_panel",), params=prm).items():
                 assert_parity(y, G, xg, dtype)
+    # BCSR with every lane width, on shapes that are not multiples of 4
+    # (49 x 49 stencil, 37 x 53 rectangular) and on 4x4 dense blocks
+    rng = np.random.default_rng(48)
+    for M in (S.stencil_5pt(7), S.random_csr(rng, 37, 53, 0.25),
+              S.blocks_g3(np.random.default_rng([48, 1]), 3000)):
+        xm = S.uniform_vector(M.n, [48, M.m])
+        for prm in ({}, {"bcsr_lanes": 1}, {"bcsr_lanes": 4, "block": 64}, {"bcsr_lanes": 64},
+                    {"bcsr_lanes": 16, "stream_nt": 1}):
+            for k, y in _run_all(M, dtype, xm, kernels=("bcsr",), params=prm).items():
+                assert_parity(y, M, xm, dtype)
     B = S.stencil_27pt(12)
     xb = S.uniform_vector(B.n, 44)
     for prm in ({"dia_span": 0}, {"dia_span": 1, "dia_rows_per_thread": 1},
@@ -195,7 +208,7 @@ def test_empty_matrices():
         rp = torch.zeros(1, dtype=torch.int32, device="cuda")
         col = torch.zeros(0, dtype=torch.int32, device="cuda")
         val = torch.zeros(0, dtype=torch.float64, device="cuda")
-        if k in ("ell", "dia", "dia_direct"):
+        if k in ("ell", "dia", "dia_direct", "bcsr"):
             continue
         p = Plan(rp, col, val, n=5, selector=k)
         p.run(torch.ones(5, dtype=torch.float64, device="cuda"))
@@ -207,7 +220,7 @@ def test_empty_matrices():
         try:
             p = Plan(rp, col, val, n=7, selector=k)
         except RuntimeError:
-            assert k in ("ell", "dia", "dia_direct")
+            assert k in ("ell", "dia", "dia_direct", "bcsr")
             continue
         y = p.run(torch.ones(7, dtype=torch.float32, device="cuda"),
                   torch.full((32,), 9.0, dtype=torch.float32, device="cuda"))
