@@ -248,28 +248,16 @@ def main():
         if replay_step:
             ml["mode"] = replay_step  # profile the recorded run's step, not this trial's pick
         log(f"multilevel trial (ms/step): {ml['trial_ms']} -> {ml['mode']}")
-        if ml["mode"] == "persistent":
-            dt_name = "double" if recs[0]["rec"]["dtype"] == "float64" else "float"
-            dominant = f"k_batch_persistent<{dt_name}>"
-            sym_time = {dominant: sum(r["rec"]["tuned_ms"] for r in recs)}
     step_mode = ml["mode"] if ml else "separate"
-    level_bytes = sum(r["rec"]["bytes"] for r in recs)
 
     # ---- timed region: K steps of every tuned SpMV
     def steps(which, K, events=False):
         evs = []
         if which == "tuned" and step_mode != "separate":
+            # a batch launch hides the levels' kernels from stream events
             b = batches[step_mode]
-            pairs = event_pairs(K) if events and step_mode == "persistent" else None
             for _ in range(K):
-                if pairs is not None:
-                    e0, e1 = next(pairs)
-                    e0.record()
-                    b.run(xs, ys)
-                    e1.record()
-                    evs.append((e0, e1, level_bytes))
-                else:
-                    b.run(xs, ys)
+                b.run(xs, ys)
             return evs
         return per_plan(which, K, events)
 
@@ -317,12 +305,12 @@ def main():
     evs = steps("tuned", a.steps, events=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    stream_copy(mark_dst, mark_src)
     if not evs:
-        # graph replays hide the level kernels from stream events: time the
-        # dominant kernel's launches one by one, outside the timed region
+        # batch steps: the dominant level kernel is timed launch by launch
+        # right after the timed steps, still inside the marked trace region
         evs = per_plan("tuned", a.steps, events=True)
         torch.cuda.synchronize()
+    stream_copy(mark_dst, mark_src)
     # achievable-bandwidth probe: copy 1 GiB (2 GiB of traffic), median of 5
     cp_src = torch.zeros(1 << 28, dtype=torch.float32, device=dev)
     cp_dst = torch.empty_like(cp_src)
