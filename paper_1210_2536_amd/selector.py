@@ -227,6 +227,38 @@ def pick_tau(params, mean, std, ds, topk=3):
     return 1e9, evaluate(sc, ds, tau=1e9, topk=topk)
 
 
+FEATURE_NAMES = ("log_m", "log_nnz", "log_aver_rd", "log_max_rd", "log_std_rd", "log_ndiags",
+                 "dia_fill", "ell_pad", "zipf_R", "log_bandwidth", "block_fill", "is_f64")
+
+
+def tree_baseline(ds, ho, depth=8, min_leaf=5, seed=7):
+    """Fit the classification-tree baseline on `ds`, choose its confidence
+    threshold (leaf-frequency margin between the two best feasible kernels)
+    on a 10% validation split as for the network, and score `ho`."""
+    from .tree import Tree
+    X = transform(ds["raw"])
+    y = np.argmin(np.where(np.isfinite(ds["times"]), ds["times"], np.inf), axis=1)
+    rng = np.random.default_rng(seed)
+    mats = np.unique(ds["idx"])
+    vm = set(rng.choice(mats, size=max(1, len(mats) // 10), replace=False).tolist())
+    val = np.array([i in vm for i in ds["idx"]])
+    t = Tree(C.K_COUNT, max_depth=depth, min_leaf=min_leaf).fit(X[~val], y[~val])
+    va = {k: v[val] for k, v in ds.items()}
+    sv = t.scores(X[val])
+    always = evaluate(sv, va, tau=1e9)["hit_rate"]
+    tau = 1e9
+    for cand in (0.0, 0.05, 0.1, 0.2, 0.3, 0.5, 1.0):
+        if evaluate(sv, va, tau=cand)["hit_rate"] >= always - 0.01:
+            tau = cand
+            break
+    sh = t.scores(transform(ho["raw"]))
+    strip = lambda r: {k: v for k, v in r.items() if k != "choice"}  # noqa: E731
+    return {"depth": depth, "leaves": t.n_leaves(), "tau": tau,
+            "heldout_tree": strip(evaluate(sh, ho)),
+            "heldout_tree_tau": strip(evaluate(sh, ho, tau=tau)),
+            "rules": t.rules(FEATURE_NAMES, C.KERNELS)}
+
+
 def domain(raw):
     """Per-input range [lo, hi] of the raw features the model was fitted on."""
     r = np.asarray(raw, dtype=np.float32)
@@ -260,6 +292,11 @@ def main(argv=None):
     t.add_argument("--heldout", nargs="*", default=[])
     t.add_argument("--out", required=True)
     t.add_argument("--epochs", type=int, default=300)
+    tr = sub.add_parser("tree", help="fit the re-fitted rule baseline (classification tree)")
+    tr.add_argument("--data", nargs="+", required=True)
+    tr.add_argument("--heldout", nargs="+", required=True)
+    tr.add_argument("--depth", type=int, default=8)
+    tr.add_argument("--out", default="")
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)
     e.add_argument("--data", nargs="+", required=True)
@@ -291,6 +328,12 @@ def main(argv=None):
             meta["heldout_rules"] = {k: v for k, v in evaluate_rules(ho).items() if k != "choice"}
         save(a.out, params, mean, std, meta, dom=domain(tr["raw"]))
         log(json.dumps({k: v for k, v in meta.items() if k != "loss_curve"}))
+    elif a.cmd == "tree":
+        meta = tree_baseline(load(a.data), load(a.heldout), depth=a.depth)
+        log(json.dumps({k: v for k, v in meta.items() if k != "rules"}))
+        if a.out:
+            with open(a.out, "w") as fh:
+                json.dump(meta, fh, indent=1)
     else:
         with open(a.weights) as fh:
             w = json.load(fh)
