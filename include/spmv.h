@@ -2,8 +2,9 @@
  * Adaptive sparse matrix-vector multiply for AMD Instinct MI355X (gfx950).
  *
  * The caller hands over one matrix in CSR form; the library measures its
- * structure on the GPU, picks a storage format (CSR, COO, ELL or DIA) and a
- * kernel for it, converts the matrix into plan-owned device memory and then
+ * structure on the GPU, picks a storage format (CSR, COO, ELL, DIA, or 4x4
+ * block CSR) and a kernel for it, converts the matrix into plan-owned device
+ * memory and then
  * computes y = A x as often as asked.  This is the input-adaptive auto-tuner
  * of Li, Zhang, Tan and Chen, "SMAT: An Input Adaptive Sparse Matrix-Vector
  * Multiplication Auto-Tuner" (arXiv 1210.2536): a CSR-based interface
@@ -68,8 +69,9 @@ typedef enum {
     SPMV_K_DIA = 4,           /* DIA, x windows staged in LDS                   */
     SPMV_K_DIA_DIRECT = 5,    /* DIA, x read through the caches                 */
     SPMV_K_COO = 6,           /* COO, wavefront segmented reduction             */
-    SPMV_K_CSR_PANEL = 7,     /* CSR cut into column panels whose slice of x
-                                 fits in L2, one binned launch per panel     */
+    SPMV_K_CSR_PANEL = 7,     /* CSR re-sorted into column panels whose slice
+                                 of x fits one XCD's L2 (spmv_params
+                                 panel_xcd / panel_kib)                      */
     SPMV_K_BCSR = 8,          /* 4x4 block CSR: block row pointer, block
                                  columns, 16 values per block (row-major,
                                  absent entries +0.0); a lane group per block
@@ -153,8 +155,9 @@ typedef struct {
                                    point) replaces the predicted one only
                                    when more than 3% faster               */
     uint32_t disable_mask;      /* bit k set: never pick kernel k             */
-    uint64_t mem_cap_bytes;     /* cap on padded ELL / DIA storage; 0 = 1/4 of
-                                   free device memory                        */
+    uint64_t mem_cap_bytes;     /* cap on the storage of the padded formats
+                                   (ELL, DIA, BCSR) and column panels; 0 =
+                                   1/4 of free device memory                */
     spmv_selector_t model;      /* learned model (NULL: rules)                */
     int32_t autotune;           /* 1: time a few parameter points for the
                                    chosen kernel and keep the fastest        */
