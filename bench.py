@@ -85,7 +85,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="sweep",
-                    choices=["sweep", "large", "multilevel", "multilevel32", "c1"])
+                    choices=["sweep", "large", "mixed", "multilevel", "multilevel32", "c1"])
     ap.add_argument("--selector", default="auto", help="auto|mlp|rules|exhaustive|<kernel>")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep default kernel parameters for the chosen kernels")
@@ -94,6 +94,9 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--detail", default="", help="write per-matrix records (JSON) here")
+    ap.add_argument("--segments", type=int, default=0,
+                    help="plan every matrix as this many row segments, each with its own "
+                         "format and kernel (records and the step are per segment)")
     ap.add_argument("--replay", default="",
                     help="per-matrix records of an earlier run (--detail): build every plan "
                          "with the kernel and parameters recorded there instead of selecting "
@@ -151,16 +154,24 @@ def main():
             tuned = Plan(rp, col, val, n=A.n, selector=rr["kernel"], params=rr["params"])
         else:
             tuned = Plan(rp, col, val, n=A.n, selector=selector, model=model,
-                         autotune=not a.no_autotune)
+                         autotune=not a.no_autotune, segments=a.segments)
         plain = None if a.no_plain else Plan(rp, col, val, n=A.n, selector="csr_scalar")
         info = tuned.info()
-        rec = dict(name=A.name, dtype=np.dtype(dt).name, m=A.m, n=A.n, nnz=A.nnz,
-                   kernel=info["kernel_name"], format=info["format_name"],
-                   plan_ms=info["t_plan_ms"], tune_ms=info["t_tune_ms"],
-                   bytes=workloads.plan_bytes(info),
-                   confidence=info["confidence"], n_measured=info["n_measured"],
-                   params=info["params"], rules_kernel=capi.KERNELS[info["rules_kernel"]])
-        recs.append(dict(rec=rec, tuned=tuned, plain=plain, x=x, y=y))
+        # a segmented plan is timed segment by segment (same launches as its
+        # own run); the plain plan and the plan cost belong to the first one
+        parts = tuned.segments() if info["n_segments"] else [(0, tuned)]
+        for k, (r0, part) in enumerate(parts):
+            pi = part.info()
+            rec = dict(name=A.name if len(parts) == 1 else f"{A.name}#seg{k}",
+                       dtype=np.dtype(dt).name, m=part.m, n=A.n, nnz=part.nnz,
+                       kernel=pi["kernel_name"], format=pi["format_name"],
+                       plan_ms=info["t_plan_ms"] if k == 0 else 0.0,
+                       tune_ms=info["t_tune_ms"] if k == 0 else 0.0,
+                       bytes=workloads.plan_bytes(pi), confidence=pi["confidence"],
+                       n_measured=pi["n_measured"], params=pi["params"],
+                       rules_kernel=capi.KERNELS[pi["rules_kernel"]])
+            recs.append(dict(rec=rec, tuned=part, plain=plain if k == 0 else None, x=x,
+                             y=y[r0:r0 + part.m], py=y, owner=tuned))
         del rp, col, val
     torch.cuda.synchronize()
     log(f"plans built ({time.time() - t_start:.1f}s)")
@@ -180,7 +191,7 @@ def main():
     for r in recs:
         r["rec"]["tuned_ms"] = time_run(r["tuned"], r["x"], r["y"])
         if r["plain"] is not None:
-            r["rec"]["plain_ms"] = time_run(r["plain"], r["x"], r["y"])
+            r["rec"]["plain_ms"] = time_run(r["plain"], r["x"], r["py"])
     # Kernel symbol of each plan: the compiled kernel it launches (format
     # kernel, value type and the template parameters of its launch).
     def symbol(rec):
@@ -283,14 +294,17 @@ def main():
         for _ in range(K):
             for r in recs:
                 p = r[which]
+                if p is None:
+                    continue
+                y = r["py"] if which == "plain" else r["y"]
                 if events and r["rec"]["symbol"] == dominant:
                     e0, e1 = next(pairs)
                     e0.record()
-                    p.run(r["x"], r["y"])
+                    p.run(r["x"], y)
                     e1.record()
                     evs.append((e0, e1, r["rec"]["bytes"]))
                 else:
-                    p.run(r["x"], r["y"])
+                    p.run(r["x"], y)
         return evs
 
     # 16-byte copies bracket the timed region in kernel traces (profilers see
@@ -350,7 +364,9 @@ def main():
 
     # ---- selector hit rate against exhaustive timing (same session)
     hit_rate = rules_hit_rate = None
-    if not a.no_hitrate:
+    if a.segments >= 2:
+        log("hit rate not measured for segmented plans (per segment, no whole-matrix best)")
+    if not a.no_hitrate and a.segments < 2:
         hits = 0
         slow = []
         for i, r in enumerate(recs):
@@ -412,6 +428,7 @@ def main():
         log(f"cpu oracle: {cpu['value']} GFLOP/s on {threads} threads")
 
     workload_name = {"sweep": "sweep200_f32_f64", "large": "zipf8M_f32+lap7_256^3_f64",
+                     "mixed": "mixed_lap7_128^3+zipf_f64_f32",
                      "multilevel": "galerkin27_160^3_6levels_f64",
                      "multilevel32": "galerkin27_160^3_6levels_f32",
                      "c1": "lap5_64x64_f64"}[a.workload]
@@ -436,7 +453,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload_name,
                    "matrices": len(items), "nnz_per_step": int(flops / 2), "selector": selector,
-                   "step": step_mode},
+                   "step": step_mode, "segments": a.segments},
         "multilevel": ml,
         "hbm_gbs": round(hbm_gbs, 1),
         "hbm_frac_peak": round(hbm_gbs / HBM_PEAK_GBS, 4),

@@ -163,6 +163,13 @@ typedef struct {
                                    chosen kernel and keep the fastest        */
     int32_t use_params;         /* 1: take `params` as given                  */
     spmv_params params;
+    int32_t segments;           /* >= 2: cut the rows into this many segments
+                                   of about nnz/segments entries each (at most
+                                   64, at most m) and plan each segment on its
+                                   own -- its own features, format and kernel
+                                   (the per-thread sub-matrices of Section 6)
+                                   -- with these same options; 0 or 1: one
+                                   plan for the whole matrix (default)      */
 } spmv_plan_opts;
 
 /* Feature parameters of Table 3 (Section 4) plus the selector's extras.
@@ -202,6 +209,10 @@ typedef struct {
     double t_tune_ms;                   /* parameter search (autotune), part
                                            of t_convert_ms and t_plan_ms      */
     int64_t bcsr_blocks;                /* stored 4x4 blocks (BCSR plans)     */
+    int32_t n_segments;                 /* segmented plans: the number of row
+                                           segments (kernel and format are
+                                           then -1; spmv_plan_segment gives
+                                           each segment's plan); else 0     */
 } spmv_plan_info;
 
 typedef struct spmv_plan_s *spmv_plan_t;
@@ -226,6 +237,13 @@ spmv_status spmv_run(spmv_plan_t plan, const void *x_dev, void *y_dev, void *str
 
 /* Copy the plan's report into *out (host). */
 spmv_status spmv_plan_info_get(spmv_plan_t plan, spmv_plan_info *out);
+
+/* Segment k of a segmented plan (opts.segments >= 2): its own plan, which
+ * covers rows row0 .. row0 + m_k - 1 and all columns (report through
+ * spmv_plan_info_get; spmv_run on it with y + row0 computes those rows).
+ * The segment plan belongs to `plan` and lives as long as it; do not
+ * destroy it.  EINVAL if `plan` is not segmented or k is out of range. */
+spmv_status spmv_plan_segment(spmv_plan_t plan, int32_t k, spmv_plan_t *segment, int64_t *row0);
 
 /* Release the plan and its device memory.  NULL is accepted (OK). */
 spmv_status spmv_plan_destroy(spmv_plan_t plan);

@@ -45,7 +45,7 @@ class spmv_plan_opts(ctypes.Structure):
     _fields_ = [("selector", i32), ("force_kernel", i32), ("confidence_tau", f32),
                 ("measure_topk", i32), ("timing_reps", i32), ("disable_mask", u32),
                 ("mem_cap_bytes", u64), ("model", vp), ("autotune", i32), ("use_params", i32),
-                ("params", spmv_params)]
+                ("params", spmv_params), ("segments", i32)]
 
 
 class spmv_features(ctypes.Structure):
@@ -66,7 +66,8 @@ class spmv_plan_info(ctypes.Structure):
                 ("device_bytes", u64), ("t_validate_ms", f64), ("t_features_ms", f64),
                 ("t_select_ms", f64), ("t_convert_ms", f64), ("t_plan_ms", f64),
                 ("mlp_input", f32 * 12), ("rules_kernel", i32),
-                ("out_of_domain", i32), ("t_tune_ms", f64), ("bcsr_blocks", i64)]
+                ("out_of_domain", i32), ("t_tune_ms", f64), ("bcsr_blocks", i64),
+                ("n_segments", i32)]
 
 
 _SIGS = {
@@ -74,6 +75,7 @@ _SIGS = {
     "spmv_plan_create": (i32, [vp, vp, vp, vp]),
     "spmv_run": (i32, [vp, vp, vp, vp]),
     "spmv_plan_info_get": (i32, [vp, vp]),
+    "spmv_plan_segment": (i32, [vp, i32, vp, vp]),
     "spmv_plan_destroy": (i32, [vp]),
     "spmv_features_compute": (i32, [vp, vp, vp]),
     "spmv_convert_roundtrip": (i32, [vp, vp, vp, vp, vp]),

@@ -1017,6 +1017,96 @@ extern "C" spmv_status spmv_features_compute(const spmv_csr *A, spmv_features *o
     return validate_and_extract(*A, (hipStream_t)stream, *out, W, false, nullptr, nullptr);
 }
 
+namespace {
+__global__ void k_rebase_rows(int64_t m, const int32_t *__restrict__ rp, int32_t base,
+                              int32_t *__restrict__ out) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i <= m) out[i] = rp[i] - base;
+}
+__global__ void k_offset_rows(int64_t m, int32_t *__restrict__ rp, int32_t base) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i <= m) rp[i] += base;
+}
+}  // namespace
+
+extern "C" spmv_status spmv_plan_create(const spmv_csr *A, const spmv_plan_opts *opts,
+                                        void *stream, spmv_plan_t *out);
+
+// Segmented plan (Section 6: the matrix divided by rows into sub-matrices of
+// equal nonzero counts, each tuned on its own): rows cut where the running
+// nonzero count crosses k nnz / S, each segment planned through the public
+// entry point with the caller's options.
+static spmv_status plan_create_segments(const spmv_csr *A, const spmv_plan_opts &opts, int mode,
+                                        hipStream_t s, spmv_plan_t *out,
+                                        std::chrono::steady_clock::time_point t_start) {
+    auto P = std::make_unique<spmv_plan_s>();
+    P->m = A->m;
+    P->n = A->n;
+    P->nnz = A->nnz;
+    P->dtype = A->dtype;
+    P->elt = elt_of(A->dtype);
+    P->m_pad = round_up(A->m, kRowPad);
+    P->var = std::make_unique<Variant>();  // kernel -1: the segments hold the work
+    spmv_plan_info &I = P->info;
+    I.m = A->m;
+    I.n = A->n;
+    I.nnz = A->nnz;
+    I.dtype = A->dtype;
+    I.confidence = -1.0f;
+    I.m_pad = P->m_pad;
+    I.kernel = -1;
+    I.format = -1;
+    I.selector_used = mode;
+    FeatureWork W;
+    spmv_features F;
+    SMAT_TRY(validate_and_extract(*A, s, F, W, false, &I.t_validate_ms, &I.t_features_ms));
+    I.features = F;
+    std::vector<int32_t> rp(A->m + 1);
+    SMAT_HIP(hipMemcpyAsync(rp.data(), A->row_ptr_dev, sizeof(int32_t) * (A->m + 1),
+                            hipMemcpyDeviceToHost, s));
+    SMAT_HIP(hipStreamSynchronize(s));
+    const int64_t S = std::min<int64_t>({(int64_t)opts.segments, A->m, 64});
+    std::vector<int64_t> cut(1, 0);
+    for (int64_t k = 1, r = 0; k < S; ++k) {
+        const int64_t target = (int64_t)A->nnz * k / S;
+        while (r < A->m && rp[r] < target) ++r;
+        if (r > cut.back() && r < A->m) cut.push_back(r);
+    }
+    cut.push_back(A->m);
+    spmv_plan_opts co = opts;
+    co.segments = 0;
+    Dev rb;
+    SMAT_TRY(rb.alloc(sizeof(int32_t) * (size_t)(A->m + 1)));
+    for (size_t k = 0; k + 1 < cut.size(); ++k) {
+        const int64_t r0 = cut[k], mk = cut[k + 1] - r0;
+        const int32_t base = rp[r0];
+        k_rebase_rows<<<(unsigned)((mk + 256) / 256), 256, 0, s>>>(
+            mk, (const int32_t *)A->row_ptr_dev + r0, base, rb.as<int32_t>());
+        SMAT_LAUNCHED("rebase_rows");
+        spmv_csr c{};
+        c.m = mk;
+        c.n = A->n;
+        c.nnz = rp[cut[k + 1]] - base;
+        c.row_ptr_dev = rb.as<int32_t>();
+        c.col_dev = (const int32_t *)A->col_dev + base;
+        c.val_dev = (const char *)A->val_dev + (size_t)P->elt * base;
+        c.dtype = A->dtype;
+        spmv_plan_t child = nullptr;
+        SMAT_TRY(spmv_plan_create(&c, &co, s, &child));
+        P->seg.push_back(child);
+        P->seg_row0.push_back(r0);
+        I.device_bytes += child->info.device_bytes;
+        I.t_select_ms += child->info.t_plan_ms;
+        I.t_tune_ms += child->info.t_tune_ms;
+        I.n_measured += child->info.n_measured;
+    }
+    I.n_segments = (int32_t)P->seg.size();
+    I.t_plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
+                                                            t_start).count();
+    *out = P.release();
+    return SPMV_OK;
+}
+
 static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opts_in,
                                     hipStream_t s, spmv_plan_t *out) {
     auto t_start = std::chrono::steady_clock::now();
@@ -1042,6 +1132,12 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
         set_error("force_kernel %d out of range", opts.force_kernel);
         return SPMV_EINVAL;
     }
+    if (opts.segments < 0) {
+        set_error("segments must be >= 0");
+        return SPMV_EINVAL;
+    }
+    if (opts.segments >= 2 && A->m >= 2 && A->nnz > 0)
+        return plan_create_segments(A, opts, mode, s, out, t_start);
     auto P = std::make_unique<spmv_plan_s>();
     P->m = A->m;
     P->n = A->n;
@@ -1275,7 +1371,23 @@ extern "C" spmv_status spmv_run(spmv_plan_t P, const void *x, void *y, void *str
         set_error("x and y overlap");
         return SPMV_EINVAL;
     }
+    if (!P->seg.empty()) {
+        for (size_t k = 0; k < P->seg.size(); ++k)
+            SMAT_TRY(spmv_run(P->seg[k], x, (char *)y + (size_t)P->elt * P->seg_row0[k], stream));
+        return SPMV_OK;
+    }
     return run_variant(*P, *P->var, x, y, (hipStream_t)stream);
+}
+
+extern "C" spmv_status spmv_plan_segment(spmv_plan_t P, int32_t k, spmv_plan_t *segment,
+                                         int64_t *row0) {
+    if (!P || P->seg.empty() || k < 0 || k >= (int32_t)P->seg.size()) {
+        set_error("plan is not segmented or segment %d does not exist", k);
+        return SPMV_EINVAL;
+    }
+    if (segment) *segment = P->seg[k];
+    if (row0) *row0 = P->seg_row0[k];
+    return SPMV_OK;
 }
 
 extern "C" spmv_status spmv_plan_info_get(spmv_plan_t P, spmv_plan_info *out) {
@@ -1299,6 +1411,23 @@ extern "C" spmv_status spmv_convert_roundtrip(spmv_plan_t P, int32_t *rp, int32_
         return SPMV_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
+    if (!P->seg.empty()) {
+        // each segment rebuilds its rows; their row pointers are shifted by
+        // the entries before the segment (its last entry is the next start)
+        int64_t base = 0;
+        for (size_t k = 0; k < P->seg.size(); ++k) {
+            const spmv_plan_s &C = *P->seg[k];
+            const int64_t r0 = P->seg_row0[k];
+            SMAT_TRY(spmv_convert_roundtrip(P->seg[k], rp + r0, col + base,
+                                            (char *)val + (size_t)P->elt * base, stream));
+            k_offset_rows<<<(unsigned)((C.m + 256) / 256), 256, 0, s>>>(C.m, rp + r0,
+                                                                        (int32_t)base);
+            SMAT_LAUNCHED("offset_rows");
+            base += C.nnz;
+        }
+        SMAT_HIP(hipStreamSynchronize(s));
+        return SPMV_OK;
+    }
     const Variant &V = *P->var;
     const int64_t m = P->m, nnz = P->nnz;
     const int elt = P->elt;

@@ -91,5 +91,11 @@ struct spmv_plan_s {
     spmv_plan_info info{};
     smat::Dev diag_map;                 // diagonal -> slot map (kept only while converting)
     std::vector<int32_t> dia_offsets;
+    // segmented plans: one plan per row segment, in row order
+    std::vector<spmv_plan_s *> seg;
+    std::vector<int64_t> seg_row0;
+    ~spmv_plan_s() {
+        for (auto *c : seg) delete c;
+    }
 };
 

@@ -153,7 +153,7 @@ class Plan:
 
     def __init__(self, row_ptr, col, val, n=None, selector="rules", model=None,
                  tau=None, topk=None, reps=None, disable=(), mem_cap=0, params=None,
-                 autotune=False, stream=None):
+                 autotune=False, segments=0, stream=None):
         torch = _torch()
         m = row_ptr.numel() - 1
         n = m if n is None else int(n)
@@ -184,6 +184,7 @@ class Plan:
         o.disable_mask = mask
         o.mem_cap_bytes = int(mem_cap)
         o.autotune = 1 if autotune else 0
+        o.segments = int(segments)
         if selector == "mlp" and tau is None and model is not None and \
                 getattr(model, "tau", None) is not None:
             o.confidence_tau = model.tau
@@ -218,9 +219,25 @@ class Plan:
         I = C.spmv_plan_info()
         C.check(C.lib().spmv_plan_info_get(self.handle, ctypes.byref(I)), "spmv_plan_info_get")
         d = _struct_to_dict(I)
-        d["kernel_name"] = C.KERNELS[d["kernel"]]
-        d["format_name"] = C.FORMATS[d["format"]]
+        if d["n_segments"] > 0:
+            d["kernel_name"] = d["format_name"] = "segmented"
+        else:
+            d["kernel_name"] = C.KERNELS[d["kernel"]]
+            d["format_name"] = C.FORMATS[d["format"]]
         return d
+
+    def segments(self):
+        """[(row0, plan of that row segment)] of a segmented plan; the segment
+        plans belong to this one (they are never destroyed on their own)."""
+        out = []
+        for k in range(self.info()["n_segments"]):
+            h = ctypes.c_void_p()
+            r0 = ctypes.c_int64(0)
+            C.check(C.lib().spmv_plan_segment(self.handle, k, ctypes.byref(h), ctypes.byref(r0)),
+                    "spmv_plan_segment")
+            seg = _SegmentPlan(h, self)
+            out.append((r0.value, seg))
+        return out
 
     def roundtrip(self, stream=None):
         torch = _torch()
@@ -252,6 +269,21 @@ class Plan:
 
     def __del__(self):
         self.close()
+
+
+class _SegmentPlan(Plan):
+    """A row segment's plan inside a segmented plan (not owned)."""
+
+    def __init__(self, handle, parent):  # noqa: D107 -- no plan creation here
+        self.handle = handle
+        self._parent = parent
+        I = C.spmv_plan_info()
+        C.check(C.lib().spmv_plan_info_get(handle, ctypes.byref(I)), "spmv_plan_info_get")
+        self.m, self.n, self.nnz = int(I.m), int(I.n), int(I.nnz)
+        self.dtype, self.device = parent.dtype, parent.device
+
+    def close(self):
+        self.handle = None
 
 
 class Batch:

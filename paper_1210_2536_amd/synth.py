@@ -322,6 +322,27 @@ def zipf_large(n: int = 8_000_000, kmax: int = 800_000, seed=(5, 0)) -> CSR:
     return _finish(n, n, row_len, col, val, f"zipf2_n{n}")
 
 
+def mixed_stencil_zipf(g: int = 128, kmax: int = 20_000, seed=(6, 0)) -> CSR:
+    """Two halves of one square matrix, n = 2 g^3: rows [0, g^3) are the
+    7-point Laplacian on g^3 (6 / -1, columns in the first half), rows
+    [g^3, 2 g^3) have degrees floor(k), p(k) ~ k^-2 on [2, kmax], with
+    distinct uniform columns over all n.  No single format suits both
+    halves (the random half makes DIA and ELL infeasible)."""
+    rng = np.random.default_rng(list(seed))
+    S1 = stencil_7pt(g)
+    h = S1.m
+    n = 2 * h
+    u = rng.random(h)
+    a, b = 0.5, 1.0 / kmax
+    row_len2 = np.minimum(np.floor(1.0 / (a - u * (a - b))).astype(np.int64), kmax)
+    col2 = _sorted_distinct_cols(rng, row_len2, n)
+    val2 = _uniform_vals(rng, col2.size)
+    row_len = np.concatenate([np.diff(S1.row_ptr), row_len2])
+    col = np.concatenate([S1.col, col2]).astype(np.int32)
+    val = np.concatenate([S1.val.astype(np.float64), val2])
+    return _finish(n, n, row_len, col, val, f"mixed_lap7_{g}^3+zipf2")
+
+
 def laplace_7pt_large(g: int = 256) -> CSR:
     return stencil_7pt(g)
 

@@ -5,6 +5,7 @@ Workloads (all seeded, see ``synth``):
   sweep       200 matrices, n = 10^U(3,6), four generators, float32 and float64
   large       Zipf rows (n = 8M, p(k) ~ k^-2 on [2, 800000], float32) and the
               7-point Laplacian on 256^3 (float64)
+  mixed       half 7-point Laplacian on 128^3, half Zipf rows (float64, float32)
   multilevel  27-point stencil on 160^3 plus five 2x2x2-aggregation Galerkin
               levels, float64 (and float32)
 
@@ -72,6 +73,9 @@ def build(name, threads=8):
             fz = ex.submit(S.zipf_large)
             fl = ex.submit(S.laplace_7pt_large)
             return [(fz.result(), np.float32, (5, 1)), (fl.result(), np.float64, (5, 2))]
+    if name == "mixed":
+        A = S.mixed_stencil_zipf()
+        return [(A, np.float64, (6, 1)), (A, np.float32, (6, 1))]
     if name in ("multilevel", "multilevel32"):
         levels = S.multilevel(160, 6)
         dt = np.float64 if name == "multilevel" else np.float32

@@ -251,3 +251,52 @@ def test_run_argument_errors():
     assert st == C.SPMV_EINVAL and b"overlap" in C.lib().spmv_last_error()
     assert C.lib().spmv_run(None, None, None, None) == C.SPMV_EINVAL
     assert C.lib().spmv_plan_destroy(None) == C.SPMV_OK
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_segmented_plans(dtype):
+    """Row segments of about nnz/S entries, each planned on its own: parity,
+    segment boundaries, the kernels chosen per segment, the round trip and a
+    batch holding a segmented plan."""
+    import torch
+    from paper_1210_2536_amd.spmv import Batch, Plan
+    rng = np.random.default_rng(49)
+    mats = [S.mixed_stencil_zipf(g=16, kmax=500, seed=(49, 0)),
+            S.random_csr(rng, 301, 170, 0.05, explicit_zeros=True), _edge_matrices()[0]]
+    for A in mats:
+        x = S.uniform_vector(A.n, [49, A.m])
+        rp, col, val = dev(A, dtype)
+        for seg in (2, 3, 7, 64):
+            for sel in ("rules", "exhaustive"):
+                note(f"[segments] {A.name} {np.dtype(dtype).name} S={seg} {sel}")
+                p = Plan(rp, col, val, n=A.n, selector=sel, segments=seg)
+                info = p.info()
+                parts = p.segments()
+                assert info["n_segments"] == len(parts) >= 1
+                r0s = [r0 for r0, _ in parts]
+                assert r0s[0] == 0 and all(b > a for a, b in zip(r0s, r0s[1:]))
+                assert sum(q.m for _, q in parts) == A.m and sum(q.nnz for _, q in parts) == A.nnz
+                y = p.run(vec(x, dtype)).cpu().numpy()
+                assert_parity(y, A, x, dtype)
+                rp2, col2, v2 = p.roundtrip()
+                assert np.array_equal(rp2.cpu().numpy(), A.row_ptr.astype(np.int32))
+                assert np.array_equal(col2.cpu().numpy(), A.col)
+                assert np.array_equal(v2.cpu().numpy().view(np.uint8),
+                                      A.val.astype(dtype).view(np.uint8))
+    # planned as three nnz-balanced segments, the first lies inside the
+    # stencil half and the last inside the random half: the rules give them
+    # different formats
+    A = mats[0]
+    rp, col, val = dev(A, dtype)
+    p = Plan(rp, col, val, n=A.n, selector="rules", segments=3)
+    kinds = [q.info()["kernel_name"] for _, q in p.segments()]
+    assert kinds[0] in ("dia", "dia_direct") and kinds[-1] not in ("dia", "dia_direct"), kinds
+    x = vec(S.uniform_vector(A.n, 50), dtype)
+    ref = p.run(x).cpu().numpy()
+    for mode in (0, 1):
+        B = Batch([p], mode=mode)
+        y = torch.full((A.m,), float("nan"), dtype=x.dtype, device="cuda")
+        B.run([x], [y])
+        torch.cuda.synchronize()
+        assert np.array_equal(y.cpu().numpy().view(np.uint8), ref.view(np.uint8)), mode
+        B.close()
