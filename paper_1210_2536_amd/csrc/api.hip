@@ -123,8 +123,12 @@ spmv_status validate_and_extract(const spmv_csr &A, hipStream_t s, spmv_features
                   (h.flags & kBadRowPtrOrder) ? "row_ptr decreasing or out of range" : "");
         return SPMV_EINVAL;
     }
+    // column checks and the row pass (which reads only row_ptr, valid by
+    // now) share one synchronisation
     SMAT_TRY(launch_validate_entries(m, n, nnz, A.row_ptr_dev, A.col_dev, &d->flags, s));
+    SMAT_TRY(launch_row_stats(m, A.row_ptr_dev, &d->rs, s));
     SMAT_HIP(hipMemcpyAsync(&h.flags, &d->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SMAT_HIP(hipMemcpyAsync(&h.rs, &d->rs, sizeof(RowStats), hipMemcpyDeviceToHost, s));
     SMAT_HIP(hipStreamSynchronize(s));
     if (h.flags) {
         set_error("invalid CSR columns (flags 0x%x: %s%s)", h.flags,
@@ -133,10 +137,6 @@ spmv_status validate_and_extract(const spmv_csr &A, hipStream_t s, spmv_features
         return SPMV_EINVAL;
     }
     auto t1 = std::chrono::steady_clock::now();
-    // ---- row pass
-    SMAT_TRY(launch_row_stats(m, A.row_ptr_dev, &d->rs, s));
-    SMAT_HIP(hipMemcpyAsync(&h.rs, &d->rs, sizeof(RowStats), hipMemcpyDeviceToHost, s));
-    SMAT_HIP(hipStreamSynchronize(s));
     F = spmv_features{};
     F.m = m;
     F.n = n;
