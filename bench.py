@@ -97,6 +97,9 @@ def parse():
     ap.add_argument("--segments", type=int, default=0,
                     help="plan every matrix as this many row segments, each with its own "
                          "format and kernel (records and the step are per segment)")
+    ap.add_argument("--no-staged", action="store_true",
+                    help="extract every feature before selecting (no staged early exit) "
+                         "for the timed plans")
     ap.add_argument("--replay", default="",
                     help="per-matrix records of an earlier run (--detail): build every plan "
                          "with the kernel and parameters recorded there instead of selecting "
@@ -154,7 +157,7 @@ def main():
             tuned = Plan(rp, col, val, n=A.n, selector=rr["kernel"], params=rr["params"])
         else:
             tuned = Plan(rp, col, val, n=A.n, selector=selector, model=model,
-                         autotune=not a.no_autotune, segments=a.segments)
+                         autotune=not a.no_autotune, segments=a.segments, staged=not a.no_staged)
         plain = None if a.no_plain else Plan(rp, col, val, n=A.n, selector="csr_scalar")
         info = tuned.info()
         # a segmented plan is timed segment by segment (same launches as its
@@ -169,7 +172,7 @@ def main():
                        tune_ms=info["t_tune_ms"] if k == 0 else 0.0,
                        bytes=workloads.plan_bytes(pi), confidence=pi["confidence"],
                        n_measured=pi["n_measured"], params=pi["params"],
-                       rules_kernel=capi.KERNELS[pi["rules_kernel"]])
+                       feature_stage=pi["feature_stage"])
             recs.append(dict(rec=rec, tuned=part, plain=plain if k == 0 else None, x=x,
                              y=y[r0:r0 + part.m], py=y, owner=tuned))
         del rp, col, val
@@ -362,8 +365,11 @@ def main():
     for b in batches.values():
         b.close()
 
-    # ---- selector hit rate against exhaustive timing (same session)
+    # ---- selector hit rate against exhaustive timing (same session), and
+    # the plan cost of untuned plans with all features up front vs staged
+    # extraction (Table 6 analog, in plain-CSR SpMV times)
     hit_rate = rules_hit_rate = None
+    study = [] if selector in ("mlp", "rules") else None
     if a.segments >= 2:
         log("hit rate not measured for segmented plans (per segment, no whole-matrix best)")
     if not a.no_hitrate and a.segments < 2:
@@ -382,9 +388,22 @@ def main():
             best = min(table.values())
             got = table.get(r["rec"]["kernel"], float("inf"))
             r["rec"]["exhaustive_ms"] = table
+            r["rec"]["rules_kernel"] = capi.KERNELS[ei["rules_kernel"]]
             r["rec"]["hit"] = bool(got <= 1.05 * best)
             r["rec"]["rules_hit"] = bool(table.get(r["rec"]["rules_kernel"], float("inf"))
                                          <= 1.05 * best)
+            if study is not None and r["rec"].get("plain_ms"):
+                row = {}
+                order = (("all", False), ("staged", True))
+                for tag, stg in (order if i % 2 == 0 else order[::-1]):  # alternate who goes first
+                    pi = Plan(rp, col, val, n=A.n, selector=selector, model=model,
+                              staged=stg).info()
+                    row[tag] = {"plan_units": pi["t_plan_ms"] / r["rec"]["plain_ms"],
+                                "feature_units": (pi["t_validate_ms"] + pi["t_features_ms"])
+                                / r["rec"]["plain_ms"],
+                                "stopped": pi["feature_stage"] == 1,
+                                "hit": table.get(pi["kernel_name"], float("inf")) <= 1.05 * best}
+                study.append(row)
             hits += r["rec"]["hit"]
             slow.append(got / best)
             ex.close()
@@ -437,6 +456,19 @@ def main():
     select_units = [(r["rec"]["plan_ms"] - r["rec"]["tune_ms"]) / r["rec"]["plain_ms"]
                     for r in recs if r["rec"].get("plain_ms")]
     speedup = (plain_ms_step / ms_step) if plain_ms_step else None
+    plan_study = None
+    if study:
+        med = lambda tag, k: round(float(np.median([r[tag][k] for r in study])), 2)  # noqa: E731
+        share = lambda tag, k: round(float(np.mean([r[tag][k] for r in study])), 4)  # noqa: E731
+        plan_study = {"matrices": len(study), "selector": selector,
+                      "plan_units_median": {"all_features": med("all", "plan_units"),
+                                            "staged": med("staged", "plan_units")},
+                      "feature_units_median": {"all_features": med("all", "feature_units"),
+                                               "staged": med("staged", "feature_units")},
+                      "hit_rate": {"all_features": share("all", "hit"),
+                                   "staged": share("staged", "hit")},
+                      "staged_stop_share": share("staged", "stopped")}
+        log(f"plan study: {json.dumps(plan_study)}")
     out = {
         "metric": METRIC,
         "value": round(gflops, 3),
@@ -453,7 +485,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": workload_name,
                    "matrices": len(items), "nnz_per_step": int(flops / 2), "selector": selector,
-                   "step": step_mode, "segments": a.segments},
+                   "step": step_mode, "segments": a.segments, "staged": not a.no_staged},
         "multilevel": ml,
         "hbm_gbs": round(hbm_gbs, 1),
         "hbm_frac_peak": round(hbm_gbs / HBM_PEAK_GBS, 4),
@@ -465,6 +497,7 @@ def main():
         "plan_cost_plain_csr_units_median": round(float(np.median(plan_units)), 2) if plan_units else None,
         "plan_cost_untuned_plain_csr_units_median":
             round(float(np.median(select_units)), 2) if select_units else None,
+        "plan_study": plan_study,
         "roofline": {"bound": "hbm", "kernel": dominant, "launches_per_step": len(evs) // a.steps,
                      "achieved": round(dom_achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(dom_achieved / HBM_PEAK_GBS, 4),

@@ -170,6 +170,24 @@ typedef struct {
                                    (the per-thread sub-matrices of Section 6)
                                    -- with these same options; 0 or 1: one
                                    plan for the whole matrix (default)      */
+    int32_t staged;             /* 1: staged feature extraction (Section 6,
+                                   the time-saving format search): rows
+                                   statistics, then the diagonal census; if
+                                   these already settle the format -- RULES:
+                                   the DIA or ELL test passes; MLP: the
+                                   model's stage rule (spmv_selector_set_stage)
+                                   names a DIA, ELL or CSR kernel, feasible,
+                                   with confidence >= stage_conf, inputs inside
+                                   the model's domain -- the power-law fit,
+                                   the 4x4 block count, the network and any
+                                   measurement are skipped.  RULES picks the
+                                   same kernel staged or not.  Default 1
+                                   (spmv_plan_opts_default); 0: all features
+                                   first.  EXHAUSTIVE and FORCED ignore it. */
+    float stage_conf;           /* stage rule confidence needed to stop early
+                                   (the share of training matrices of the
+                                   rule's leaf on which its kernel ran within
+                                   5% of the fastest); <= 0: default 0.98  */
 } spmv_plan_opts;
 
 /* Feature parameters of Table 3 (Section 4) plus the selector's extras.
@@ -177,7 +195,8 @@ typedef struct {
  * the population variance; a diagonal is "true" when 5 count > 3 length;
  * R is the least-squares power-law exponent of the row degrees.  The
  * diagonal census is only taken while DIA can still be feasible
- * (max_RD M <= 20 NNZ); otherwise ndiags = -1. */
+ * (max_RD M <= 20 NNZ); otherwise ndiags = -1.  A staged plan that stopped
+ * early leaves R = NaN and blocks4 = block_fill = -1 (not extracted). */
 typedef struct {
     int64_t m, n, nnz;
     int64_t sum_rd, sum_rd2, max_rd, min_rd;
@@ -213,6 +232,14 @@ typedef struct {
                                            segments (kernel and format are
                                            then -1; spmv_plan_segment gives
                                            each segment's plan); else 0     */
+    int32_t feature_stage;              /* 0: not staged; 1: staged, settled
+                                           after the census (rest stage
+                                           skipped; rules_kernel is then -1
+                                           unless the rules' DIA / ELL tests
+                                           decide); 2: staged, every stage
+                                           ran                               */
+    float stage_confidence;             /* MLP stage rule: confidence of the
+                                           leaf reached, -1 if not consulted */
 } spmv_plan_info;
 
 typedef struct spmv_plan_s *spmv_plan_t;
@@ -295,6 +322,23 @@ spmv_status spmv_selector_destroy(spmv_selector_t sel);
  * predictions), and reports out_of_domain = 1.  EINVAL if only one pointer
  * is NULL or lo[i] > hi[i]. */
 spmv_status spmv_selector_set_domain(spmv_selector_t sel, const float *lo, const float *hi);
+
+/* Stage rule of a selector (Section 6: the format search runs format by
+ * format, DIA first, and stops once a format's rules are confident): a
+ * binary decision tree over the raw inputs known after the diagonal census,
+ * inputs 0-7, 9 and 11 (spmv_plan_info.mlp_input order).  Node i < n_nodes
+ * with feat[i] >= 0 sends raw[feat[i]] <= thr[i] to node left[i], else to
+ * right[i]; a leaf (feat[i] = -1) names kernel[i] with confidence conf[i] in
+ * [0, 1] (the share of its training matrices on which that kernel ran within
+ * 5% of the fastest).  Node 0 is the root; child indices must exceed their
+ * parent's.  Host arrays of n_nodes entries, copied (thr, left and right of
+ * leaves are ignored).  n_nodes = 0 removes the rule.  Used by plans created
+ * with opts.staged = 1.  EINVAL on NULL arrays with n_nodes > 0, n_nodes
+ * outside [0, 4096], an input other than those listed, a child out of
+ * order or range, a kernel out of range or a confidence outside [0, 1]. */
+spmv_status spmv_selector_set_stage(spmv_selector_t sel, const int32_t *feat, const float *thr,
+                                    const int32_t *left, const int32_t *right,
+                                    const int32_t *kernel, const float *conf, int32_t n_nodes);
 
 /* Score raw feature rows with the selector on the GPU (inference kernel):
  * raw_dev is float32 [rows x 12], scores_dev float32 [rows x SPMV_K_COUNT]. */

@@ -45,7 +45,8 @@ class spmv_plan_opts(ctypes.Structure):
     _fields_ = [("selector", i32), ("force_kernel", i32), ("confidence_tau", f32),
                 ("measure_topk", i32), ("timing_reps", i32), ("disable_mask", u32),
                 ("mem_cap_bytes", u64), ("model", vp), ("autotune", i32), ("use_params", i32),
-                ("params", spmv_params), ("segments", i32)]
+                ("params", spmv_params), ("segments", i32), ("staged", i32),
+                ("stage_conf", f32)]
 
 
 class spmv_features(ctypes.Structure):
@@ -67,7 +68,7 @@ class spmv_plan_info(ctypes.Structure):
                 ("t_select_ms", f64), ("t_convert_ms", f64), ("t_plan_ms", f64),
                 ("mlp_input", f32 * 12), ("rules_kernel", i32),
                 ("out_of_domain", i32), ("t_tune_ms", f64), ("bcsr_blocks", i64),
-                ("n_segments", i32)]
+                ("n_segments", i32), ("feature_stage", i32), ("stage_confidence", f32)]
 
 
 _SIGS = {
@@ -83,6 +84,7 @@ _SIGS = {
     "spmv_selector_create": (i32, [vp, i64, vp, vp, vp]),
     "spmv_selector_destroy": (i32, [vp]),
     "spmv_selector_set_domain": (i32, [vp, vp, vp]),
+    "spmv_selector_set_stage": (i32, [vp, vp, vp, vp, vp, vp, vp, i32]),
     "spmv_selector_score": (i32, [vp, vp, i64, vp, vp]),
     "spmv_mlp_param_count": (i64, [i32]),
     "spmv_mlp_workspace_floats": (i64, [i64]),

@@ -15,6 +15,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <limits>
 #include <memory>
 
 namespace smat {
@@ -103,10 +104,19 @@ struct Scratch {
     double fit[5];
 };
 
-spmv_status validate_and_extract(const spmv_csr &A, hipStream_t s, spmv_features &F,
-                                 FeatureWork &W, bool keep_census, double *t_val,
-                                 double *t_feat) {
-    auto t0 = std::chrono::steady_clock::now();
+// Feature extraction in stages, in the order the format search consumes them
+// (Section 6: DIA first, then ELL and CSR, COO last):
+//   rows    validation, row statistics and bandwidth -- everything the ELL
+//           and CSR tests need;
+//   census  the diagonal histogram (Ndiags, NTdiags, ER_DIA), taken only
+//           while DIA can still be feasible;
+//   rest    the row-degree histogram with the power-law fit (R, the COO
+//           trigger) and the 4x4 block count.
+// Without staging, census and rest share one entry pass and one
+// synchronisation.
+enum : unsigned { kStageCensus = 1, kStageRest = 2 };
+
+spmv_status extract_rows(const spmv_csr &A, hipStream_t s, spmv_features &F, FeatureWork &W) {
     const int64_t m = A.m, n = A.n, nnz = A.nnz;
     SMAT_TRY(W.scratch.alloc(sizeof(Scratch)));
     Scratch *d = W.scratch.as<Scratch>();
@@ -123,12 +133,12 @@ spmv_status validate_and_extract(const spmv_csr &A, hipStream_t s, spmv_features
                   (h.flags & kBadRowPtrOrder) ? "row_ptr decreasing or out of range" : "");
         return SPMV_EINVAL;
     }
-    // column checks and the row pass (which reads only row_ptr, valid by
-    // now) share one synchronisation
-    SMAT_TRY(launch_validate_entries(m, n, nnz, A.row_ptr_dev, A.col_dev, &d->flags, s));
+    // column checks (with the bandwidth) and the row pass (which reads only
+    // row_ptr, valid by now) share one synchronisation
+    SMAT_TRY(launch_validate_entries(m, n, nnz, A.row_ptr_dev, A.col_dev, &d->flags,
+                                     &d->es.bandwidth, s));
     SMAT_TRY(launch_row_stats(m, A.row_ptr_dev, &d->rs, s));
-    SMAT_HIP(hipMemcpyAsync(&h.flags, &d->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    SMAT_HIP(hipMemcpyAsync(&h.rs, &d->rs, sizeof(RowStats), hipMemcpyDeviceToHost, s));
+    SMAT_HIP(hipMemcpyAsync(&h, d, sizeof(Scratch), hipMemcpyDeviceToHost, s));
     SMAT_HIP(hipStreamSynchronize(s));
     if (h.flags) {
         set_error("invalid CSR columns (flags 0x%x: %s%s)", h.flags,
@@ -136,7 +146,6 @@ spmv_status validate_and_extract(const spmv_csr &A, hipStream_t s, spmv_features
                   (h.flags & kBadColOrder) ? "columns not strictly increasing in a row" : "");
         return SPMV_EINVAL;
     }
-    auto t1 = std::chrono::steady_clock::now();
     F = spmv_features{};
     F.m = m;
     F.n = n;
@@ -153,35 +162,55 @@ spmv_status validate_and_extract(const spmv_csr &A, hipStream_t s, spmv_features
     F.std_rd = std::sqrt(F.var_rd);
     F.er_ell = F.max_rd ? (double)nnz / ((double)F.max_rd * (double)m) : 0.0;
     F.ell_feasible = m && (__int128)F.max_rd * m <= (__int128)20 * nnz;
+    F.bandwidth = h.es.bandwidth;
+    // not extracted yet
+    F.ndiags = -1;
+    F.blocks4 = -1;
+    F.block_fill = -1.0;
+    F.R = std::numeric_limits<double>::quiet_NaN();
+    return SPMV_OK;
+}
+
+spmv_status extract_entries(const spmv_csr &A, hipStream_t s, spmv_features &F, FeatureWork &W,
+                            unsigned what, bool keep_census) {
+    const int64_t m = A.m, n = A.n, nnz = A.nnz;
+    Scratch *d = W.scratch.as<Scratch>();
+    const bool rest = what & kStageRest;
     // ---- power-law fit over the row-degree histogram
-    if (m && F.max_rd >= 1) {
+    if (rest && m && F.max_rd >= 1) {
         SMAT_TRY(W.row_hist.alloc(sizeof(unsigned) * (size_t)(F.max_rd + 1)));
         SMAT_HIP(hipMemsetAsync(W.row_hist.p, 0, W.row_hist.bytes, s));
         SMAT_TRY(launch_row_hist(m, A.row_ptr_dev, (int)F.max_rd, W.row_hist.as<unsigned>(), s));
         SMAT_TRY(launch_powerlaw_fit(W.row_hist.as<unsigned>(), (int)F.max_rd, m, d->fit, s));
     }
-    // ---- entry pass (+ diagonal census while DIA may still be feasible)
-    W.census = F.ell_feasible && nnz > 0;
-    if (W.census) {
+    // ---- entry pass: diagonal census (while DIA may still be feasible,
+    // since Ndiags >= max_RD) and / or the 4x4 block count
+    const bool census = (what & kStageCensus) && F.ell_feasible && nnz > 0;
+    if (census) {
         SMAT_TRY(W.diag_hist.alloc(sizeof(unsigned) * (size_t)(m + n - 1)));
         SMAT_HIP(hipMemsetAsync(W.diag_hist.p, 0, W.diag_hist.bytes, s));
     }
-    SMAT_TRY(launch_entry_stats(m, n, nnz, A.row_ptr_dev, A.col_dev, &d->es,
-                                W.census ? W.diag_hist.as<unsigned>() : nullptr, s));
-    if (W.census) SMAT_TRY(launch_diag_stats(m, n, W.diag_hist.as<unsigned>(), &d->ds, s));
+    if (census || rest)
+        SMAT_TRY(launch_entry_stats(m, n, nnz, A.row_ptr_dev, A.col_dev, &d->es,
+                                    census ? W.diag_hist.as<unsigned>() : nullptr, rest, s));
+    if (census) SMAT_TRY(launch_diag_stats(m, n, W.diag_hist.as<unsigned>(), &d->ds, s));
+    Scratch h{};
     SMAT_HIP(hipMemcpyAsync(&h, d, sizeof(Scratch), hipMemcpyDeviceToHost, s));
     SMAT_HIP(hipStreamSynchronize(s));
-    F.bandwidth = h.es.bandwidth;
-    F.blocks4 = (int64_t)h.es.blocks4;
-    F.block_fill = F.blocks4 ? (double)nnz / (16.0 * (double)F.blocks4) : 0.0;
-    F.R = (m && F.max_rd >= 1 && h.fit[0] >= 2.0 && h.fit[4] > 0) ? -h.fit[3] / h.fit[4] : 0.0;
-    if (W.census) {
+    if (rest) {
+        F.blocks4 = (int64_t)h.es.blocks4;
+        F.block_fill = F.blocks4 ? (double)nnz / (16.0 * (double)F.blocks4) : 0.0;
+        F.R = (m && F.max_rd >= 1 && h.fit[0] >= 2.0 && h.fit[4] > 0) ? -h.fit[3] / h.fit[4]
+                                                                     : 0.0;
+    }
+    if (census) {
+        W.census = true;
         F.ndiags = (int64_t)h.ds.ndiags;
         F.ntdiags = (int64_t)h.ds.ntrue;
         F.ntdiags_ratio = F.ndiags ? (double)F.ntdiags / (double)F.ndiags : 0.0;
         F.er_dia = F.ndiags ? (double)nnz / ((double)F.ndiags * (double)m) : 0.0;
         F.dia_feasible = (__int128)F.ndiags * m <= (__int128)20 * nnz;
-    } else {
+    } else if (what & kStageCensus) {
         F.ndiags = -1;
         F.ntdiags = 0;
         F.ntdiags_ratio = 0.0;
@@ -190,6 +219,17 @@ spmv_status validate_and_extract(const spmv_csr &A, hipStream_t s, spmv_features
     }
     if (!keep_census || !F.dia_feasible) W.diag_hist.release();
     W.row_hist.release();
+    return SPMV_OK;
+}
+
+// All features up front (no staging).
+spmv_status validate_and_extract(const spmv_csr &A, hipStream_t s, spmv_features &F,
+                                 FeatureWork &W, bool keep_census, double *t_val,
+                                 double *t_feat) {
+    auto t0 = std::chrono::steady_clock::now();
+    SMAT_TRY(extract_rows(A, s, F, W));
+    auto t1 = std::chrono::steady_clock::now();
+    SMAT_TRY(extract_entries(A, s, F, W, kStageCensus | kStageRest, keep_census));
     auto t2 = std::chrono::steady_clock::now();
     if (t_val) *t_val = std::chrono::duration<double, std::milli>(t1 - t0).count();
     if (t_feat) *t_feat = std::chrono::duration<double, std::milli>(t2 - t1).count();
@@ -410,7 +450,9 @@ uint32_t feasible_mask(const spmv_features &F, int dtype, int64_t m_pad, uint64_
 // The method without the learned part: Section 4 observations as IF-THEN
 // rules, tried in the Section 6 order (DIA, ELL, then COO on its only
 // trigger R, CSR by default).  Integer forms of every threshold.
-int rules_choose(const spmv_features &F, uint32_t feas) {
+// The DIA and ELL tests: the part of the rule order that needs no feature of
+// the rest stage.  -1 when neither applies.
+int rules_dia_ell(const spmv_features &F, uint32_t feas) {
     const __int128 M = F.m, NNZ = F.nnz;
     const int64_t nd = F.ndiags;
     if ((feas & (1u << SPMV_K_DIA)) && nd >= 0 && nd <= 500) {
@@ -423,11 +465,34 @@ int rules_choose(const spmv_features &F, uint32_t feas) {
         bool var_ok = 2 * (M * (__int128)F.sum_rd2 - (__int128)F.sum_rd * F.sum_rd) < M * M;
         if (er_ok && (var_ok || F.max_rd < 5)) return SPMV_K_ELL;
     }
+    return -1;
+}
+
+int rules_choose(const spmv_features &F, uint32_t feas) {
+    const int k = rules_dia_ell(F, feas);
+    if (k >= 0) return k;
     if (F.R >= 1.0 && F.R < 4.0 && (feas & (1u << SPMV_K_COO))) return SPMV_K_COO;
     // CSR: a fixed lane width suits rows of similar length, binning otherwise
     if ((double)F.max_rd <= 8.0 * std::max(1.0, F.aver_rd) && (feas & (1u << SPMV_K_CSR_VECTOR)))
         return SPMV_K_CSR_VECTOR;
     return SPMV_K_CSR_ADAPTIVE;
+}
+
+// Kernels a staged search may settle on before the rest stage (DIA, ELL and
+// CSR come before COO in the search order; BCSR's feasibility needs the
+// block count) and the selector inputs known by then (all but R, 8, and the
+// block fill, 10).
+constexpr uint32_t kStageKernels =
+    (1u << SPMV_K_CSR_SCALAR) | (1u << SPMV_K_CSR_VECTOR) | (1u << SPMV_K_CSR_ADAPTIVE) |
+    (1u << SPMV_K_CSR_PANEL) | (1u << SPMV_K_ELL) | (1u << SPMV_K_DIA) | (1u << SPMV_K_DIA_DIRECT);
+constexpr uint32_t kStageInputs = 0xFFFu & ~((1u << 8) | (1u << 10));
+
+// Leaf of the selector's stage rule reached by these inputs (node 0 is the
+// root; every child index exceeds its parent's, so the walk ends).
+int stage_leaf(const spmv_selector_s &S, const float raw[12]) {
+    int i = 0;
+    while (S.st_feat[i] >= 0) i = raw[S.st_feat[i]] <= S.st_thr[i] ? S.st_left[i] : S.st_right[i];
+    return i;
 }
 
 void raw_features(const spmv_features &F, int dtype, float out[12]) {
@@ -976,6 +1041,8 @@ extern "C" spmv_status spmv_plan_opts_default(spmv_plan_opts *o) {
     o->confidence_tau = 0.1f;
     o->measure_topk = 3;
     o->timing_reps = 5;
+    o->staged = 1;
+    o->stage_conf = 0.98f;
     return SPMV_OK;
 }
 
@@ -1057,6 +1124,7 @@ static spmv_status plan_create_segments(const spmv_csr *A, const spmv_plan_opts 
     I.kernel = -1;
     I.format = -1;
     I.selector_used = mode;
+    I.stage_confidence = -1.0f;
     FeatureWork W;
     spmv_features F;
     SMAT_TRY(validate_and_extract(*A, s, F, W, false, &I.t_validate_ms, &I.t_features_ms));
@@ -1118,6 +1186,11 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
         spmv_plan_opts_default(&opts);
     if (opts.timing_reps <= 0) opts.timing_reps = 5;
     if (opts.measure_topk <= 0) opts.measure_topk = 3;
+    if (!(opts.stage_conf > 0.0f)) opts.stage_conf = 0.98f;
+    if (opts.staged != 0 && opts.staged != 1) {
+        set_error("staged must be 0 or 1");
+        return SPMV_EINVAL;
+    }
     int mode = opts.selector;
     if (mode < 0) mode = opts.model ? SPMV_SELECT_MLP : SPMV_SELECT_RULES;
     if (mode > SPMV_SELECT_FORCED) {
@@ -1155,9 +1228,70 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
 
     FeatureWork W;
     spmv_features F;
-    SMAT_TRY(validate_and_extract(*A, s, F, W, true, &I.t_validate_ms, &I.t_features_ms));
-    I.features = F;
+    const bool staged = opts.staged == 1 &&
+                        (mode == SPMV_SELECT_RULES || mode == SPMV_SELECT_MLP);
+    if (!staged) {
+        SMAT_TRY(validate_and_extract(*A, s, F, W, true, &I.t_validate_ms, &I.t_features_ms));
+    } else {
+        auto t0 = std::chrono::steady_clock::now();
+        SMAT_TRY(extract_rows(*A, s, F, W));
+        auto t1 = std::chrono::steady_clock::now();
+        SMAT_TRY(extract_entries(*A, s, F, W, kStageCensus, true));
+        auto t2 = std::chrono::steady_clock::now();
+        I.t_validate_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        I.t_features_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    }
     auto t_sel0 = std::chrono::steady_clock::now();
+
+    uint64_t cap = opts.mem_cap_bytes;
+    if (cap == 0) {
+        size_t fr = 0, tot = 0;
+        SMAT_HIP(hipMemGetInfo(&fr, &tot));
+        cap = fr / 4;
+    }
+    spmv_params prm_base = default_params(0, F);
+    if (opts.use_params) {
+        merge_params(prm_base, opts.params);
+        SMAT_TRY(check_params(prm_base));
+    }
+    uint32_t feas = feasible_mask(F, A->dtype, P->m_pad, cap, prm_base) & ~opts.disable_mask;
+
+    // ---- staged search (Section 6): settle on DIA, ELL or CSR from the
+    // features known so far when the format test is confident, else
+    // extract the rest
+    int chosen = -1;
+    I.stage_confidence = -1.0f;
+    if (staged) {
+        if (mode == SPMV_SELECT_RULES) {
+            chosen = rules_dia_ell(F, feas);  // the rules' own DIA / ELL tests
+        } else if (!opts.model->st_feat.empty()) {
+            const spmv_selector_s &S = *opts.model;
+            float raw[12];
+            raw_features(F, A->dtype, raw);
+            bool inside = true;
+            if (S.has_domain)
+                for (int j = 0; j < 12; ++j)
+                    if ((kStageInputs >> j) & 1u)
+                        inside = inside && raw[j] >= S.lo[j] && raw[j] <= S.hi[j];
+            const int leaf = stage_leaf(S, raw);
+            const int k = S.st_kernel[leaf];
+            I.stage_confidence = S.st_conf[leaf];
+            if (inside && ((kStageKernels & feas) >> k & 1u) &&
+                S.st_conf[leaf] >= opts.stage_conf)
+                chosen = k;
+        }
+        if (chosen >= 0) {
+            I.feature_stage = 1;
+        } else {
+            auto t0 = std::chrono::steady_clock::now();
+            SMAT_TRY(extract_entries(*A, s, F, W, kStageRest, true));
+            I.t_features_ms += std::chrono::duration<double, std::milli>(
+                                   std::chrono::steady_clock::now() - t0).count();
+            feas = feasible_mask(F, A->dtype, P->m_pad, cap, prm_base) & ~opts.disable_mask;
+            I.feature_stage = 2;
+        }
+    }
+    I.features = F;
 
     // plan-owned CSR copy (every conversion starts from it)
     SMAT_TRY(P->rp.alloc(sizeof(int32_t) * (size_t)(A->m + 1)));
@@ -1173,27 +1307,18 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
     }
     P->has_csr = true;
 
-    uint64_t cap = opts.mem_cap_bytes;
-    if (cap == 0) {
-        size_t fr = 0, tot = 0;
-        SMAT_HIP(hipMemGetInfo(&fr, &tot));
-        cap = fr / 4;
-    }
-    spmv_params prm_base = default_params(0, F);
-    if (opts.use_params) {
-        merge_params(prm_base, opts.params);
-        SMAT_TRY(check_params(prm_base));
-    }
-    uint32_t feas = feasible_mask(F, A->dtype, P->m_pad, cap, prm_base) & ~opts.disable_mask;
     I.feasible_mask = feas;
     raw_features(F, A->dtype, I.mlp_input);
-    I.rules_kernel = rules_choose(F, feas);
+    // an early stop leaves R unknown: the rules' pick is known only when
+    // their DIA / ELL tests decide
+    I.rules_kernel = I.feature_stage == 1 ? rules_dia_ell(F, feas) : rules_choose(F, feas);
 
     // ---- selection
     std::vector<int> cands;
-    int chosen = -1;
     I.selector_used = mode;
-    if (mode == SPMV_SELECT_FORCED) {
+    if (chosen >= 0) {
+        // settled by the staged search
+    } else if (mode == SPMV_SELECT_FORCED) {
         uint32_t all = feasible_mask(F, A->dtype, P->m_pad, ~0ull, prm_base, false);
         bool structural_ok = (all >> opts.force_kernel) & 1u;
         // DIA and ELL need their zero-fill feasibility; the others always run
@@ -1592,6 +1717,40 @@ extern "C" spmv_status spmv_selector_set_domain(spmv_selector_t S, const float *
     std::copy(lo, lo + 12, S->lo);
     std::copy(hi, hi + 12, S->hi);
     S->has_domain = true;
+    return SPMV_OK;
+}
+
+extern "C" spmv_status spmv_selector_set_stage(spmv_selector_t S, const int32_t *feat,
+                                               const float *thr, const int32_t *left,
+                                               const int32_t *right, const int32_t *kernel,
+                                               const float *conf, int32_t n_nodes) {
+    if (!S || n_nodes < 0 || n_nodes > 4096 ||
+        (n_nodes > 0 && (!feat || !thr || !left || !right || !kernel || !conf))) {
+        set_error("selector handle, 0 <= n_nodes <= 4096 and all six arrays required");
+        return SPMV_EINVAL;
+    }
+    for (int i = 0; i < n_nodes; ++i) {
+        if (feat[i] == -1) {
+            if (kernel[i] < 0 || kernel[i] >= SPMV_K_COUNT || !(conf[i] >= 0.0f && conf[i] <= 1.0f)) {
+                set_error("stage leaf %d: kernel %d or confidence out of range", i, kernel[i]);
+                return SPMV_EINVAL;
+            }
+        } else if (feat[i] < 0 || feat[i] >= 12 || !((kStageInputs >> feat[i]) & 1u)) {
+            set_error("stage node %d tests input %d, not known after the census", i, feat[i]);
+            return SPMV_EINVAL;
+        } else if (left[i] <= i || right[i] <= i || left[i] >= n_nodes || right[i] >= n_nodes ||
+                   !std::isfinite(thr[i])) {
+            set_error("stage node %d: children must lie in (%d, %d), threshold finite", i, i,
+                      n_nodes);
+            return SPMV_EINVAL;
+        }
+    }
+    S->st_feat.assign(feat, feat + n_nodes);
+    S->st_thr.assign(thr, thr + n_nodes);
+    S->st_left.assign(left, left + n_nodes);
+    S->st_right.assign(right, right + n_nodes);
+    S->st_kernel.assign(kernel, kernel + n_nodes);
+    S->st_conf.assign(conf, conf + n_nodes);
     return SPMV_OK;
 }
 

@@ -43,9 +43,9 @@ struct RowStats {       // device-side reduction target for the row pass
     int max_rd, min_rd;
 };
 
-struct EntryStats {     // device-side reduction target for the entry pass
-    unsigned long long blocks4;
-    int bandwidth;
+struct EntryStats {     // device-side reduction targets of the entry passes
+    unsigned long long blocks4;  // block pass
+    int bandwidth;               // column validation
     int pad;
 };
 
@@ -56,7 +56,8 @@ struct DiagStats {
 spmv_status launch_validate_rows(int64_t m, int64_t nnz, const int32_t *rp, uint32_t *flags,
                                  hipStream_t s);
 spmv_status launch_validate_entries(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
-                                    const int32_t *col, uint32_t *flags, hipStream_t s);
+                                    const int32_t *col, uint32_t *flags, int *bandwidth,
+                                    hipStream_t s);
 spmv_status launch_row_stats(int64_t m, const int32_t *rp, RowStats *out, hipStream_t s);
 spmv_status launch_row_hist(int64_t m, const int32_t *rp, int max_rd, unsigned int *hist,
                             hipStream_t s);
@@ -64,7 +65,7 @@ spmv_status launch_powerlaw_fit(const unsigned int *hist, int max_rd, int64_t m,
                                 hipStream_t s);
 spmv_status launch_entry_stats(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
                                const int32_t *col, EntryStats *out, unsigned int *diag_hist,
-                               hipStream_t s);
+                               bool blocks, hipStream_t s);
 spmv_status launch_diag_stats(int64_t m, int64_t n, const unsigned int *diag_hist, DiagStats *out,
                               hipStream_t s);
 spmv_status launch_diag_compact(int64_t m, int64_t n, unsigned int *diag_hist, int32_t *offsets,

@@ -46,23 +46,37 @@ __global__ void k_validate_rows(int64_t m, int64_t nnz, const int32_t *__restric
     if (bad) atomicOr(flags, bad);
 }
 
+// Column checks, and the bandwidth max |j - i| on the way (meaningful once
+// the checks pass).
 __global__ void k_validate_entries(int64_t m, int64_t n, int64_t nnz,
                                    const int32_t *__restrict__ rp,
-                                   const int32_t *__restrict__ col, uint32_t *flags) {
+                                   const int32_t *__restrict__ col, uint32_t *flags,
+                                   int *bandwidth) {
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int64_t p0 = t * kEntryRun;
-    if (p0 >= nnz) return;
-    int64_t p1 = p0 + kEntryRun < nnz ? p0 + kEntryRun : nnz;
-    int64_t row = row_of_entry(rp, m, p0);
-    int64_t rend = rp[row + 1];
     uint32_t bad = 0;
-    for (int64_t p = p0; p < p1; ++p) {
-        while (p >= rend) rend = rp[++row + 1];
-        int32_t c = col[p];
-        if (c < 0 || (int64_t)c >= n) bad |= kBadColRange;
-        if (p + 1 < rend && col[p + 1] <= c) bad |= kBadColOrder;
+    int bw = 0;
+    if (p0 < nnz) {
+        int64_t p1 = p0 + kEntryRun < nnz ? p0 + kEntryRun : nnz;
+        int64_t row = row_of_entry(rp, m, p0);
+        int64_t rend = rp[row + 1];
+        for (int64_t p = p0; p < p1; ++p) {
+            while (p >= rend) rend = rp[++row + 1];
+            int32_t c = col[p];
+            if (c < 0 || (int64_t)c >= n) bad |= kBadColRange;
+            if (p + 1 < rend && col[p + 1] <= c) bad |= kBadColOrder;
+            int64_t d = (int64_t)c - row;
+            int ad = (int)(d < 0 ? -d : d);
+            bw = ad > bw ? ad : bw;
+        }
     }
     if (bad) atomicOr(flags, bad);
+    // every lane of the wave is here: reduce across it, one atomic per wave
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        int o = __shfl_xor(bw, off, kWave);
+        bw = o > bw ? o : bw;
+    }
+    if (threadIdx.x % kWave == 0 && bw > 0) atomicMax(bandwidth, bw);
 }
 
 template <typename T, typename Op>
@@ -192,13 +206,15 @@ __device__ __forceinline__ bool row_has_block(const int32_t *__restrict__ rp,
     return a < rp[r + 1] && col[a] <= lo + 3;
 }
 
+// BLOCKS: count the nonempty aligned 4x4 blocks (a few binary searches per
+// block start); with a histogram, take the diagonal census.  Either or both.
+template <bool BLOCKS>
 __global__ void k_entry_stats(int64_t m, int64_t n, int64_t nnz, const int32_t *__restrict__ rp,
                               const int32_t *__restrict__ col, EntryStats *out,
                               unsigned int *diag_hist) {
     __shared__ int hkey[kHash];
     __shared__ unsigned int hcnt[kHash];
     __shared__ unsigned long long lds_u[kBlock / kWave];
-    __shared__ int lds_i[kBlock / kWave];
     const bool census = diag_hist != nullptr;
     if (census) {
         for (int b = threadIdx.x; b < kHash; b += blockDim.x) {
@@ -207,7 +223,6 @@ __global__ void k_entry_stats(int64_t m, int64_t n, int64_t nnz, const int32_t *
         }
         __syncthreads();
     }
-    int bw = 0;
     unsigned long long nb = 0;
     int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     int64_t p0 = t * kEntryRun;
@@ -223,14 +238,13 @@ __global__ void k_entry_stats(int64_t m, int64_t n, int64_t nnz, const int32_t *
             }
             int32_t c = col[p];
             int64_t d = (int64_t)c - row;
-            int ad = (int)(d < 0 ? -d : d);
-            bw = ad > bw ? ad : bw;
-            // first entry of its aligned 4x4 block, in row-major order?
-            int32_t lo = c & ~3;
-            bool fresh = !(p > rbeg && (col[p - 1] & ~3) == lo);
-            for (int64_t r2 = row & ~(int64_t)3; fresh && r2 < row; ++r2)
-                if (row_has_block(rp, col, r2, lo)) fresh = false;
-            nb += fresh;
+            if (BLOCKS) {  // first entry of its aligned 4x4 block, in row-major order?
+                int32_t lo = c & ~3;
+                bool fresh = !(p > rbeg && (col[p - 1] & ~3) == lo);
+                for (int64_t r2 = row & ~(int64_t)3; fresh && r2 < row; ++r2)
+                    if (row_has_block(rp, col, r2, lo)) fresh = false;
+                nb += fresh;
+            }
             if (census) {
                 int key = (int)d;
                 unsigned int hsh = ((unsigned int)key * 2654435761u) >> 22;  // 10 bits
@@ -247,11 +261,9 @@ __global__ void k_entry_stats(int64_t m, int64_t n, int64_t nnz, const int32_t *
             }
         }
     }
-    nb = block_reduce(nb, OpAdd(), lds_u, 0ull);
-    bw = block_reduce(bw, OpMax(), lds_i, 0);
-    if (threadIdx.x == 0) {
-        atomicAdd(&out->blocks4, nb);
-        atomicMax(&out->bandwidth, bw);
+    if (BLOCKS) {
+        nb = block_reduce(nb, OpAdd(), lds_u, 0ull);
+        if (threadIdx.x == 0) atomicAdd(&out->blocks4, nb);
     }
     if (census) {
         __syncthreads();
@@ -366,11 +378,12 @@ spmv_status launch_validate_rows(int64_t m, int64_t nnz, const int32_t *rp, uint
 }
 
 spmv_status launch_validate_entries(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
-                                    const int32_t *col, uint32_t *flags, hipStream_t s) {
+                                    const int32_t *col, uint32_t *flags, int *bandwidth,
+                                    hipStream_t s) {
     if (nnz == 0) return SPMV_OK;
     int64_t threads = (nnz + kEntryRun - 1) / kEntryRun;
     k_validate_entries<<<grid_for(threads, kBlock, INT_MAX), kBlock, 0, s>>>(m, n, nnz, rp, col,
-                                                                            flags);
+                                                                            flags, bandwidth);
     SMAT_LAUNCHED("validate_entries");
     return SPMV_OK;
 }
@@ -399,11 +412,14 @@ spmv_status launch_powerlaw_fit(const unsigned int *hist, int max_rd, int64_t m,
 
 spmv_status launch_entry_stats(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
                                const int32_t *col, EntryStats *out, unsigned int *diag_hist,
-                               hipStream_t s) {
+                               bool blocks, hipStream_t s) {
     if (nnz == 0) return SPMV_OK;
     int64_t threads = (nnz + kEntryRun - 1) / kEntryRun;
-    k_entry_stats<<<grid_for(threads, kBlock, INT_MAX), kBlock, 0, s>>>(m, n, nnz, rp, col, out,
-                                                                       diag_hist);
+    const unsigned g = grid_for(threads, kBlock, INT_MAX);
+    if (blocks)
+        k_entry_stats<true><<<g, kBlock, 0, s>>>(m, n, nnz, rp, col, out, diag_hist);
+    else
+        k_entry_stats<false><<<g, kBlock, 0, s>>>(m, n, nnz, rp, col, out, diag_hist);
     SMAT_LAUNCHED("entry_stats");
     return SPMV_OK;
 }

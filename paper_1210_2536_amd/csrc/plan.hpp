@@ -79,6 +79,9 @@ struct spmv_selector_s {
     int n_out = 0;
     bool has_domain = false;
     float lo[12] = {}, hi[12] = {};   // training range of the raw inputs
+    // stage rule: a decision tree over the inputs known after the census
+    std::vector<int32_t> st_feat, st_left, st_right, st_kernel;
+    std::vector<float> st_thr, st_conf;
 };
 
 struct spmv_plan_s {

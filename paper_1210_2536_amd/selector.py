@@ -259,6 +259,64 @@ def tree_baseline(ds, ho, depth=8, min_leaf=5, seed=7):
             "rules": t.rules(FEATURE_NAMES, C.KERNELS)}
 
 
+# Inputs known after the diagonal census (all but R and the block fill) and
+# the kernels a staged search may settle on there (DIA, ELL, CSR).
+STAGE_INPUTS = (0, 1, 2, 3, 4, 5, 6, 7, 9, 11)
+STAGE_KERNELS = tuple(C.KERNELS.index(k) for k in
+                      ("csr_scalar", "csr_vector", "csr_adaptive", "csr_panel", "ell", "dia",
+                       "dia_direct"))
+STAGE_CONF = 0.98
+
+
+def stage_exits(rule, raw, times, conf=STAGE_CONF, dom=None):
+    """Where a staged plan stops early under `rule`: (mask, kernel per row),
+    by the library's test (feasible kernel, confidence >= conf, stage inputs
+    inside the training domain)."""
+    raw = np.asarray(raw, dtype=np.float32)
+    feat, thr = rule["feat"], np.asarray(rule["thr"], dtype=np.float32)
+    kern = np.empty(len(raw), dtype=np.int64)
+    cf_ = np.empty(len(raw))
+    for i, x in enumerate(raw):
+        node = 0
+        while feat[node] >= 0:
+            node = rule["left"][node] if x[feat[node]] <= thr[node] else rule["right"][node]
+        kern[i], cf_[i] = rule["kernel"][node], rule["conf"][node]
+    ok = np.isfinite(times[np.arange(len(raw)), kern]) & (cf_ >= conf)
+    if dom is not None:
+        lo, hi = (np.asarray(v, dtype=np.float32) for v in dom)
+        j = list(STAGE_INPUTS)
+        ok &= np.all((raw[:, j] >= lo[j]) & (raw[:, j] <= hi[j]), axis=1)
+    return ok, kern
+
+
+def fit_stage(ds, depth=8, min_leaf=20):
+    """Stage rule: a classification tree over the stage inputs, fitted on the
+    best-kernel labels, whose leaves name their most reliable DIA / ELL / CSR
+    kernel (see tree.stage_rule)."""
+    from .tree import Tree, stage_rule
+    times = ds["times"]
+    feas = np.isfinite(times)
+    best = np.where(feas, times, np.inf).min(axis=1)
+    hit = feas & (times <= 1.05 * best[:, None])
+    X = np.full(ds["raw"].shape, 0.0)
+    X[:, list(STAGE_INPUTS)] = ds["raw"][:, list(STAGE_INPUTS)]  # others stay constant
+    y = np.argmin(np.where(feas, times, np.inf), axis=1)
+    t = Tree(C.K_COUNT, max_depth=depth, min_leaf=min_leaf, quantile_method="lower").fit(X, y)
+    return stage_rule(t, X, hit, STAGE_KERNELS), t.n_leaves()
+
+
+def evaluate_stage(rule, ds, conf=STAGE_CONF, dom=None):
+    times = ds["times"]
+    best = np.where(np.isfinite(times), times, np.inf).min(axis=1)
+    ex, kern = stage_exits(rule, ds["raw"], times, conf=conf, dom=dom)
+    t = times[np.arange(len(times)), kern]
+    return {"rows": int(len(times)), "exits": int(ex.sum()),
+            "exit_share": float(ex.mean()),
+            "exit_hit_rate": float(np.mean(t[ex] <= 1.05 * best[ex])) if ex.any() else None,
+            "exit_kernels": {C.KERNELS[k]: int(c) for k, c in
+                             zip(*np.unique(kern[ex], return_counts=True))}}
+
+
 def domain(raw):
     """Per-input range [lo, hi] of the raw features the model was fitted on."""
     r = np.asarray(raw, dtype=np.float32)
@@ -297,6 +355,12 @@ def main(argv=None):
     tr.add_argument("--heldout", nargs="+", required=True)
     tr.add_argument("--depth", type=int, default=8)
     tr.add_argument("--out", default="")
+    sg = sub.add_parser("stage", help="fit the stage rule of the staged format search "
+                                     "and store it in a weights file")
+    sg.add_argument("--data", nargs="+", required=True)
+    sg.add_argument("--heldout", nargs="*", default=[])
+    sg.add_argument("--weights", required=True)
+    sg.add_argument("--depth", type=int, default=8)
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)
     e.add_argument("--data", nargs="+", required=True)
@@ -334,6 +398,21 @@ def main(argv=None):
         if a.out:
             with open(a.out, "w") as fh:
                 json.dump(meta, fh, indent=1)
+    elif a.cmd == "stage":
+        with open(a.weights) as fh:
+            w = json.load(fh)
+        dom = (w["lo"], w["hi"]) if "lo" in w else None
+        tr = load(a.data)
+        rule, leaves = fit_stage(tr, depth=a.depth)
+        meta = {"depth": a.depth, "leaves": leaves, "conf": STAGE_CONF,
+                "train": evaluate_stage(rule, tr, dom=dom)}
+        if a.heldout:
+            meta["heldout"] = evaluate_stage(rule, load(a.heldout), dom=dom)
+        w["stage"] = rule
+        w["meta"]["stage"] = meta
+        with open(a.weights, "w") as fh:
+            json.dump(w, fh)
+        log(json.dumps(meta))
     else:
         with open(a.weights) as fh:
             w = json.load(fh)

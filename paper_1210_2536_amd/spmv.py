@@ -88,6 +88,7 @@ class Selector:
         self.handle = h
         self.params, self.mean, self.std = p, mu, sd
         self.lo = self.hi = None
+        self.stage = None
 
     @classmethod
     def load(cls, path):
@@ -97,7 +98,30 @@ class Selector:
         sel.tau = d.get("meta", {}).get("tau")
         if "lo" in d and "hi" in d:
             sel.set_domain(d["lo"], d["hi"])
+        if "stage" in d:
+            sel.set_stage(d["stage"])
         return sel
+
+    def set_stage(self, rule):
+        """Stage rule for staged plans: a dict of equal-length node lists
+        feat, thr, left, right, kernel, conf (see spmv_selector_set_stage);
+        None removes it."""
+        if rule is None:
+            C.check(C.lib().spmv_selector_set_stage(self.handle, None, None, None, None, None,
+                                                    None, 0), "spmv_selector_set_stage")
+            self.stage = None
+            return
+        arr = {k: np.ascontiguousarray(rule[k], dtype=np.float32 if k in ("thr", "conf")
+                                       else np.int32)
+               for k in ("feat", "thr", "left", "right", "kernel", "conf")}
+        n = len(arr["feat"])
+        assert all(len(v) == n for v in arr.values())
+        ptr = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+        C.check(C.lib().spmv_selector_set_stage(self.handle, ptr(arr["feat"]), ptr(arr["thr"]),
+                                                ptr(arr["left"]), ptr(arr["right"]),
+                                                ptr(arr["kernel"]), ptr(arr["conf"]), n),
+                "spmv_selector_set_stage")
+        self.stage = arr
 
     def set_domain(self, lo, hi):
         """Training range of the 12 raw inputs (None, None clears it)."""
@@ -153,7 +177,7 @@ class Plan:
 
     def __init__(self, row_ptr, col, val, n=None, selector="rules", model=None,
                  tau=None, topk=None, reps=None, disable=(), mem_cap=0, params=None,
-                 autotune=False, segments=0, stream=None):
+                 autotune=False, segments=0, staged=True, stage_conf=None, stream=None):
         torch = _torch()
         m = row_ptr.numel() - 1
         n = m if n is None else int(n)
@@ -185,6 +209,9 @@ class Plan:
         o.mem_cap_bytes = int(mem_cap)
         o.autotune = 1 if autotune else 0
         o.segments = int(segments)
+        o.staged = 1 if staged else 0
+        if stage_conf is not None:
+            o.stage_conf = float(stage_conf)
         if selector == "mlp" and tau is None and model is not None and \
                 getattr(model, "tau", None) is not None:
             o.confidence_tau = model.tau
@@ -224,6 +251,7 @@ class Plan:
         else:
             d["kernel_name"] = C.KERNELS[d["kernel"]]
             d["format_name"] = C.FORMATS[d["format"]]
+        d["rules_kernel_name"] = C.KERNELS[d["rules_kernel"]] if d["rules_kernel"] >= 0 else None
         return d
 
     def segments(self):

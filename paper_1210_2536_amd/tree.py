@@ -23,11 +23,15 @@ def _gini(counts):
 
 
 class Tree:
-    def __init__(self, n_classes, max_depth=8, min_leaf=10, n_thresholds=64):
+    def __init__(self, n_classes, max_depth=8, min_leaf=10, n_thresholds=64,
+                 quantile_method="linear"):
         self.C = n_classes
         self.max_depth = max_depth
         self.min_leaf = min_leaf
         self.n_thr = n_thresholds
+        # "lower" keeps every threshold a data value, so float32 inputs compare
+        # the same way against it in float32 and in float64
+        self.qmethod = quantile_method
         # nodes: feature, threshold, left, right (-1 for leaves), class counts
         self.feat, self.thr, self.left, self.right, self.counts = [], [], [], [], []
 
@@ -53,7 +57,8 @@ class Tree:
             best = (0.0, -1, 0.0, None)
             for f in range(X.shape[1]):
                 xs = X[idx, f]
-                cand = np.unique(np.quantile(xs, np.linspace(0, 1, self.n_thr + 2)[1:-1]))
+                cand = np.unique(np.quantile(xs, np.linspace(0, 1, self.n_thr + 2)[1:-1],
+                                             method=self.qmethod))
                 if cand.size == 0:
                     continue
                 # class counts left of every candidate threshold
@@ -123,3 +128,32 @@ class Tree:
     def to_json(self):
         return json.dumps({"C": self.C, "feat": self.feat, "thr": self.thr, "left": self.left,
                            "right": self.right, "counts": [c.tolist() for c in self.counts]})
+
+
+def stage_rule(tree, X, hit, allowed):
+    """Leaf rules of a tree for the staged format search: every leaf names
+    the allowed kernel that ran within 5% of the fastest (`hit`, boolean
+    [rows, C]) on the largest share of the leaf's training rows, with that
+    share as its confidence.  Returns the node lists of the library's stage
+    rule (feat, thr, left, right, kernel, conf); inner nodes carry kernel -1
+    and confidence 0, leaves feature -1."""
+    X = np.asarray(X, dtype=np.float64)
+    leaves = np.array([tree.leaf(x) for x in X], dtype=np.int64)
+    mask = np.zeros(tree.C, bool)
+    mask[list(allowed)] = True
+    n = len(tree.feat)
+    kernel = [-1] * n
+    conf = [0.0] * n
+    for node in range(n):
+        if tree.feat[node] >= 0:
+            continue
+        rows = leaves == node
+        if not rows.any():          # no training row reached it: never trusted
+            kernel[node] = int(np.flatnonzero(mask)[0])
+            continue
+        share = np.where(mask, hit[rows].mean(axis=0), -1.0)
+        kernel[node] = int(np.argmax(share))
+        conf[node] = float(share[kernel[node]])
+    return {"feat": [int(f) for f in tree.feat], "thr": [float(t) for t in tree.thr],
+            "left": [int(v) for v in tree.left], "right": [int(v) for v in tree.right],
+            "kernel": kernel, "conf": conf}

@@ -15,6 +15,7 @@ matrix arrays once, x read once, y written once (s = value bytes):
   COO  nnz (s + 8) + s (n + m)
   ELL  m K (s + 4) + s (n + m)
   DIA  m D s + 4 D + s (n + m)
+  BCSR B (16 s + 4) + 4 (ceil(m/4) + 1) + s (n + m), B stored 4x4 blocks
 Flops: 2 nnz (padding not counted).
 """
 from __future__ import annotations
@@ -24,10 +25,6 @@ import concurrent.futures as cf
 import numpy as np
 
 from . import synth as S
-
-KERNEL_FORMAT = {"csr_scalar": "csr", "csr_vector": "csr", "csr_adaptive": "csr",
-                 "ell": "ell", "dia": "dia", "dia_direct": "dia", "coo": "coo"}
-
 
 def algorithmic_bytes(fmt, m, n, nnz, s, K=0, D=0, blocks=0):
     if fmt == "bcsr":   # 4x4 blocks: 16 values + a block column each, block row pointers

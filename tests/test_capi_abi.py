@@ -47,9 +47,11 @@ def test_status_strings_without_gpu():
     assert L.spmv_plan_destroy(None) == capi.SPMV_OK
     assert L.spmv_selector_set_domain(None, None, None) == capi.SPMV_EINVAL
     assert L.spmv_plan_segment(None, 0, None, None) == capi.SPMV_EINVAL
+    assert L.spmv_selector_set_stage(None, None, None, None, None, None, None, 0) == capi.SPMV_EINVAL
     o = capi.spmv_plan_opts()
     assert L.spmv_plan_opts_default(ctypes.byref(o)) == capi.SPMV_OK
     assert o.measure_topk == 3 and o.timing_reps == 5 and abs(o.confidence_tau - 0.1) < 1e-7
+    assert o.staged == 1 and abs(o.stage_conf - 0.98) < 1e-7
 
 
 PROBE = r"""
@@ -64,6 +66,7 @@ int main(void) {
   O(spmv_plan_info, measured_ms) O(spmv_plan_info, features) O(spmv_plan_info, params)
   O(spmv_plan_info, m_pad) O(spmv_plan_info, t_plan_ms) O(spmv_features, aver_rd)
   O(spmv_plan_info, mlp_input) O(spmv_plan_info, rules_kernel) O(spmv_plan_info, out_of_domain) O(spmv_plan_info, t_tune_ms) O(spmv_plan_info, bcsr_blocks) O(spmv_plan_info, n_segments) O(spmv_plan_opts, segments)
+  O(spmv_plan_opts, staged) O(spmv_plan_opts, stage_conf) O(spmv_plan_info, feature_stage) O(spmv_plan_info, stage_confidence)
   O(spmv_features, dia_feasible)
   return 0;
 }

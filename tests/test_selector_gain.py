@@ -69,7 +69,8 @@ def test_live_selection_network_vs_rules():
             nm = ex["n_measured"]
             table = dict(zip(ex["measured_kernel"][:nm], ex["measured_ms"][:nm]))
             best = min(table.values())
-            pm = Plan(rp, col, val, n=A.n, selector="mlp", model=sel, tau=0.0).info()
+            pm = Plan(rp, col, val, n=A.n, selector="mlp", model=sel, tau=0.0,
+                      staged=False).info()
             hits_mlp += table[pm["kernel"]] <= 1.05 * best
             hits_rules += table[ex["rules_kernel"]] <= 1.05 * best
             total += 1
@@ -92,14 +93,14 @@ def test_out_of_domain_inputs_are_measured_not_trusted():
     rp = torch.from_numpy(A.row_ptr.astype(np.int32)).cuda()
     col = torch.from_numpy(A.col).cuda()
     val = torch.from_numpy(A.val.astype(np.float64)).cuda()
-    inside = Plan(rp, col, val, n=A.n, selector="mlp", model=sel, tau=0.0).info()
+    inside = Plan(rp, col, val, n=A.n, selector="mlp", model=sel, tau=0.0, staged=False).info()
     assert inside["out_of_domain"] == 0 and inside["n_measured"] == 0
     raw = np.array(inside["mlp_input"], dtype=np.float32)
     # a domain that excludes this matrix's nnz only
     lo, hi = sel.lo.copy(), sel.hi.copy()
     hi[1] = raw[1] - 1
     sel.set_domain(lo, hi)
-    out = Plan(rp, col, val, n=A.n, selector="mlp", model=sel, tau=0.0).info()
+    out = Plan(rp, col, val, n=A.n, selector="mlp", model=sel, tau=0.0, staged=False).info()
     nfeas = bin(out["feasible_mask"]).count("1")
     assert out["out_of_domain"] == 1 and out["n_measured"] == nfeas
     nm = out["n_measured"]
@@ -108,7 +109,7 @@ def test_out_of_domain_inputs_are_measured_not_trusted():
     # than 3% faster, so the kept time is within 1/0.97 of the fastest
     assert times[out["kernel"]] <= min(times.values()) / 0.97 * (1 + 1e-12)
     sel.set_domain(None, None)
-    again = Plan(rp, col, val, n=A.n, selector="mlp", model=sel, tau=0.0).info()
+    again = Plan(rp, col, val, n=A.n, selector="mlp", model=sel, tau=0.0, staged=False).info()
     assert again["out_of_domain"] == 0 and again["n_measured"] == 0
 
 
@@ -130,3 +131,48 @@ def test_refitted_tree_baseline_on_heldout_tables():
         saved = json.load(fh)
     assert saved["heldout_tree"] == meta["heldout_tree"] and saved["leaves"] == meta["leaves"]
     assert all(0.0 < r["confidence"] <= 1.0 and r["support"] >= 5 for r in meta["rules"])
+
+
+def test_stage_rule_on_heldout_tables():
+    """The stage rule of the staged format search: the committed rule is
+    reproduced exactly from the training tables; on the held-out tables it
+    stops early on a large share of matrices, and the staged pipeline (the
+    rule's kernel where it stops, the network with its measurement
+    elsewhere) stays within 1% of the network's own hit rate."""
+    from paper_1210_2536_amd import capi as C
+    from paper_1210_2536_amd import selector as SL
+    data = os.path.join(ROOT, "paper_1210_2536_amd", "data")
+    ds = SL.load([os.path.join(data, "train_0000_2500.npz"),
+                  os.path.join(data, "train_2500_5000.npz")])
+    ho = SL.load([HELD])
+    with open(WEIGHTS) as fh:
+        w = json.load(fh)
+    rule, leaves = SL.fit_stage(ds, depth=w["meta"]["stage"]["depth"])
+    assert rule == w["stage"] and leaves == w["meta"]["stage"]["leaves"]
+    # every test is on an input known after the census; every leaf names a
+    # DIA, ELL or CSR kernel; children follow their parents
+    for i, f in enumerate(rule["feat"]):
+        if f >= 0:
+            assert f in SL.STAGE_INPUTS and rule["left"][i] > i and rule["right"][i] > i
+        else:
+            assert rule["kernel"][i] in SL.STAGE_KERNELS and 0.0 <= rule["conf"][i] <= 1.0
+    dom = (w["lo"], w["hi"])
+    r = SL.evaluate_stage(rule, ho, dom=dom)
+    assert r["exit_share"] >= 0.4 and r["exit_hit_rate"] >= 0.97, r
+    # the staged pipeline, with the network scored by the float64 oracle
+    times = ho["times"]
+    params = OM.unflatten(np.array(w["params"], dtype=np.float64), w["n_out"])
+    z = OM.preprocess(ho["raw"].astype(np.float64), np.array(w["mean"]), np.array(w["std"]))
+    s, _ = OM.forward(params, z)
+    tau = w["meta"]["tau"]
+    unstaged = SL.evaluate(s, ho, tau=tau)
+    ex, kern = SL.stage_exits(rule, ho["raw"], times, conf=SL.STAGE_CONF, dom=dom)
+    choice = unstaged["choice"].copy()
+    choice[ex] = kern[ex]
+    staged_hits = _hit(choice, np.where(np.isfinite(times), times, np.inf)).mean()
+    print(f"held-out: stage rule stops on {ex.mean():.3f} of matrices "
+          f"(hit {r['exit_hit_rate']:.3f}); pipeline hit rate staged {staged_hits:.3f}, "
+          f"unstaged {unstaged['hit_rate']:.3f}")
+    assert staged_hits >= unstaged["hit_rate"] - 0.01
+    assert set(np.unique(kern[ex])) <= set(SL.STAGE_KERNELS)
+    assert C.KERNELS.index("coo") not in kern[ex]
