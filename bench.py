@@ -117,7 +117,7 @@ def main():
 
     from paper_1210_2536_amd import capi, workloads
     from paper_1210_2536_amd import synth as S
-    from paper_1210_2536_amd.spmv import Plan, default_selector, stream_copy
+    from paper_1210_2536_amd.spmv import Plan, default_selector, gather_probe, stream_copy
 
     capi.lib()  # fails loudly if the HIP library is missing
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -305,7 +305,7 @@ def main():
                     e0.record()
                     p.run(r["x"], y)
                     e1.record()
-                    evs.append((e0, e1, r["rec"]["bytes"]))
+                    evs.append((e0, e1, r["rec"]["bytes"], r["rec"]["nnz"]))
                 else:
                     p.run(r["x"], y)
         return evs
@@ -341,13 +341,38 @@ def main():
         cps.append(e0.elapsed_time(e1))
     copy_gbs = 2.0 * cp_src.numel() * 4 / (float(np.median(cps[1:])) * 1e-3) / 1e9
     del cp_src, cp_dst
+    # uniform random gathers: the CSR row loop's memory pattern (value and
+    # index streams, one gather per entry) from a 1 MiB table, which every
+    # XCD's L2 holds, with no two lanes sharing a cache line on purpose --
+    # the rate of short random rows (long rows with nearby columns share
+    # lines and can run faster)
+    gather = {"table_bytes": 1 << 20, "entries": 1 << 26}
+    g = torch.Generator(device="cpu").manual_seed(7)
+    for tdt, name in ((torch.float32, "float32"), (torch.float64, "float64")):
+        tlen = (1 << 20) // (4 if tdt == torch.float32 else 8)
+        table = torch.rand(tlen, generator=g, dtype=torch.float64).to(tdt).to(dev)
+        idx = torch.randint(0, tlen, (1 << 26,), generator=g, dtype=torch.int32).to(dev)
+        vals = torch.rand(1 << 26, generator=g, dtype=torch.float64).to(tdt).to(dev)
+        outp = None
+        ts = []
+        for _ in range(6):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            outp = gather_probe(table, idx, vals, out=outp)
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        gather[f"{name}_entries_per_s"] = float(idx.numel() / (np.median(ts[1:]) * 1e-3))
+        del table, idx, vals, outp
+    log(f"gather probe: {gather}")
     ms_step = (t1 - t0) * 1e3 / a.steps
     flops = sum(2.0 * r["rec"]["nnz"] for r in recs)
     nbytes = sum(float(r["rec"]["bytes"]) for r in recs)
     gflops = flops / (ms_step * 1e-3) / 1e9
     hbm_gbs = nbytes / (ms_step * 1e-3) / 1e9
-    dom_ms = [e0.elapsed_time(e1) for e0, e1, _ in evs]
-    dom_bytes = [b for _, _, b in evs]
+    dom_ms = [e0.elapsed_time(e1) for e0, e1, _, _ in evs]
+    dom_bytes = [b for _, _, b, _ in evs]
+    dom_entries_per_s = sum(q for _, _, _, q in evs) / (sum(dom_ms) * 1e-3)
     dom_avg_ms = float(np.mean(dom_ms))
     dom_achieved = sum(dom_bytes) / (sum(dom_ms) * 1e-3) / 1e9
     log(f"tuned: {ms_step:.3f} ms/step, {gflops:.1f} GFLOP/s, {hbm_gbs:.0f} GB/s algorithmic")
@@ -504,7 +529,11 @@ def main():
                      "traffic": recorded_traffic(dominant, workload_name,
                                                  int(np.mean(dom_bytes))),
                      "avg_launch_ms": round(dom_avg_ms, 5),
-                     "bytes_per_launch": int(np.mean(dom_bytes))},
+                     "bytes_per_launch": int(np.mean(dom_bytes)),
+                     "entry_rate_G_per_s": round(dom_entries_per_s / 1e9, 2)},
+        "gather_probe": {(k.replace("entries_per_s", "G_entries_per_s")):
+                         (round(v / 1e9, 2) if k.endswith("per_s") else v)
+                         for k, v in gather.items()},
         "cpu_baseline": cpu,
     }
     if a.detail:

@@ -397,6 +397,21 @@ spmv_status spmv_batch_destroy(spmv_batch_t batch);
  * (multiple of 16, 16-byte aligned).  Asynchronous. */
 spmv_status spmv_stream_copy(void *dst_dev, const void *src_dev, size_t bytes, void *stream);
 
+/* Random-gather ceiling probe, the memory pattern of a CSR row loop (a
+ * coalesced value stream, a coalesced index stream and one gather per
+ * entry) without row pointers or y: thread t of a fixed grid of
+ * spmv_gather_probe_threads() threads writes out_dev[t] = the sum, in
+ * order, of val_dev[i] * table_dev[idx_dev[i]] over i = t, t + G, t + 2G, ...
+ * < count (G the thread count), products and sum in float64, rounded once
+ * to the element type.  elt = 4 (float32 table, val and out) or 8
+ * (float64).  idx values must lie in [0, table_len).  Device buffers,
+ * caller-owned; asynchronous.  EINVAL on NULL buffers with count > 0, a bad
+ * elt, count < 0 or table_len < 1. */
+spmv_status spmv_gather_probe(const void *table_dev, int64_t table_len, const int32_t *idx_dev,
+                              const void *val_dev, int64_t count, int32_t elt, void *out_dev,
+                              void *stream);
+int64_t spmv_gather_probe_threads(void);
+
 /* Readable name of a status, and the calling thread's last error text. */
 const char *spmv_status_string(spmv_status s);
 const char *spmv_last_error(void);

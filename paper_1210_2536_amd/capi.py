@@ -97,6 +97,8 @@ _SIGS = {
     "spmv_batch_tune": (i32, [vp, vp, vp, i32, vp, vp]),
     "spmv_batch_shape": (i32, [vp, vp, vp]),
     "spmv_stream_copy": (i32, [vp, vp, ctypes.c_size_t, vp]),
+    "spmv_gather_probe": (i32, [vp, i64, vp, vp, i64, i32, vp, vp]),
+    "spmv_gather_probe_threads": (i64, []),
     "spmv_status_string": (ctypes.c_char_p, [i32]),
     "spmv_last_error": (ctypes.c_char_p, []),
     "spmv_kernel_name": (ctypes.c_char_p, [i32]),

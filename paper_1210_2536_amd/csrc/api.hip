@@ -486,6 +486,8 @@ constexpr uint32_t kStageKernels =
     (1u << SPMV_K_CSR_SCALAR) | (1u << SPMV_K_CSR_VECTOR) | (1u << SPMV_K_CSR_ADAPTIVE) |
     (1u << SPMV_K_CSR_PANEL) | (1u << SPMV_K_ELL) | (1u << SPMV_K_DIA) | (1u << SPMV_K_DIA_DIRECT);
 constexpr uint32_t kStageInputs = 0xFFFu & ~((1u << 8) | (1u << 10));
+// ... and those known before the census (all but Ndiags, 5, and the DIA fill, 6)
+constexpr uint32_t kRowInputs = kStageInputs & ~((1u << 5) | (1u << 6));
 
 // Leaf of the selector's stage rule reached by these inputs (node 0 is the
 // root; every child index exceeds its parent's, so the walk ends).
@@ -1230,13 +1232,31 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
     spmv_features F;
     const bool staged = opts.staged == 1 &&
                         (mode == SPMV_SELECT_RULES || mode == SPMV_SELECT_MLP);
+    bool may_stop = false;  // can the staged search still stop after the census?
     if (!staged) {
         SMAT_TRY(validate_and_extract(*A, s, F, W, true, &I.t_validate_ms, &I.t_features_ms));
     } else {
         auto t0 = std::chrono::steady_clock::now();
         SMAT_TRY(extract_rows(*A, s, F, W));
         auto t1 = std::chrono::steady_clock::now();
-        SMAT_TRY(extract_entries(*A, s, F, W, kStageCensus, true));
+        if (mode == SPMV_SELECT_RULES) {
+            may_stop = F.ell_feasible;  // DIA and ELL both need ELL's zero-fill bound
+        } else {
+            const spmv_selector_s &S = *opts.model;
+            may_stop = !S.st_feat.empty();
+            if (may_stop && S.has_domain) {  // the inputs known now must be in range
+                float raw[12];
+                raw_features(F, A->dtype, raw);
+                for (int j = 0; j < 12; ++j)
+                    if ((kRowInputs >> j) & 1u)
+                        may_stop = may_stop && raw[j] >= S.lo[j] && raw[j] <= S.hi[j];
+            }
+        }
+        // without a possible stop, census and rest share one pass
+        if (!may_stop)
+            SMAT_TRY(extract_entries(*A, s, F, W, kStageCensus | kStageRest, true));
+        else if (F.ell_feasible && A->nnz > 0)
+            SMAT_TRY(extract_entries(*A, s, F, W, kStageCensus, true));
         auto t2 = std::chrono::steady_clock::now();
         I.t_validate_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
         I.t_features_ms = std::chrono::duration<double, std::milli>(t2 - t1).count();
@@ -1261,7 +1281,14 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
     // extract the rest
     int chosen = -1;
     I.stage_confidence = -1.0f;
-    if (staged) {
+    if (staged && !may_stop) {
+        I.feature_stage = 2;
+        if (mode == SPMV_SELECT_MLP && !opts.model->st_feat.empty()) {
+            float raw[12];
+            raw_features(F, A->dtype, raw);
+            I.stage_confidence = opts.model->st_conf[stage_leaf(*opts.model, raw)];
+        }
+    } else if (staged) {
         if (mode == SPMV_SELECT_RULES) {
             chosen = rules_dia_ell(F, feas);  // the rules' own DIA / ELL tests
         } else if (!opts.model->st_feat.empty()) {
@@ -1767,6 +1794,19 @@ extern "C" spmv_status spmv_selector_score(spmv_selector_t S, const float *raw, 
     }
     return run_mlp_infer(S->params.as<float>(), S->n_out, S->mean.as<float>(), S->stdv.as<float>(),
                          raw, rows, scores, (hipStream_t)stream);
+}
+
+extern "C" int64_t spmv_gather_probe_threads(void) { return gather_probe_threads(); }
+
+extern "C" spmv_status spmv_gather_probe(const void *table, int64_t table_len, const int32_t *idx,
+                                         const void *val, int64_t count, int32_t elt, void *out,
+                                         void *stream) {
+    if ((elt != 4 && elt != 8) || count < 0 || table_len < 1 || !out ||
+        (count > 0 && (!table || !idx || !val))) {
+        set_error("gather_probe: elt 4 or 8, count >= 0, table_len >= 1, buffers required");
+        return SPMV_EINVAL;
+    }
+    return run_gather_probe(table, idx, val, count, elt, out, (hipStream_t)stream);
 }
 
 extern "C" spmv_status spmv_stream_copy(void *dst, const void *src, size_t bytes, void *stream) {

@@ -159,7 +159,47 @@ __global__ __launch_bounds__(256) void k_stream_copy(const v4u *__restrict__ src
     for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// Random-gather probe: thread t adds val[i] * table[idx[i]] over i = t,
+// t + G, t + 2 G, ... (G threads in the grid) in that order, four entries per
+// trip -- the memory pattern of a CSR row loop (two coalesced streams and
+// one gather per entry) without row pointers or y.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gather_probe(const T *__restrict__ table,
+                                                      const int32_t *__restrict__ idx,
+                                                      const T *__restrict__ val, int64_t count,
+                                                      T *__restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int64_t i = t; i < count; i += stride)
+        acc = fma((double)val[i], (double)table[idx[i]], acc);
+    out[t] = (T)acc;
+}
+
 }  // namespace
+
+int64_t gather_probe_threads() {
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    return (int64_t)cus * 8 * 256;
+}
+
+spmv_status run_gather_probe(const void *table, const int32_t *idx, const void *val,
+                             int64_t count, int elt, void *out, hipStream_t s) {
+    const int64_t threads = gather_probe_threads();
+    const unsigned g = (unsigned)(threads / 256);
+    if (elt == 8)
+        k_gather_probe<double><<<g, 256, 0, s>>>((const double *)table, idx, (const double *)val,
+                                                 count, (double *)out);
+    else
+        k_gather_probe<float><<<g, 256, 0, s>>>((const float *)table, idx, (const float *)val,
+                                                count, (float *)out);
+    SMAT_LAUNCHED("gather_probe");
+    return SPMV_OK;
+}
 
 spmv_status run_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s) {
     int64_t n = (int64_t)(bytes / 16);

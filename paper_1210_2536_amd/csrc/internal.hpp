@@ -181,5 +181,8 @@ spmv_status run_mlp_infer(const float *params, int n_out, const float *mean, con
 
 // ----------------------------------------------------------------- misc
 spmv_status run_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+int64_t gather_probe_threads();
+spmv_status run_gather_probe(const void *table, const int32_t *idx, const void *val,
+                             int64_t count, int elt, void *out, hipStream_t s);
 
 }  // namespace smat

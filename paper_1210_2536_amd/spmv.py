@@ -368,6 +368,23 @@ def stream_copy(dst, src, stream=None):
     return dst
 
 
+def gather_probe(table, idx, val, out=None, stream=None):
+    """spmv_gather_probe over device tensors (table and val of one float
+    dtype, idx int32); returns the per-thread sums."""
+    torch = _torch()
+    if table.dtype != val.dtype or table.dtype not in (torch.float32, torch.float64) or \
+            idx.dtype != torch.int32 or idx.numel() != val.numel():
+        raise TypeError("table / val float32 or float64 alike, idx int32 of val's length")
+    n = int(C.lib().spmv_gather_probe_threads())
+    if out is None:
+        out = torch.empty(n, dtype=table.dtype, device=table.device)
+    assert out.numel() == n and out.dtype == table.dtype
+    C.check(C.lib().spmv_gather_probe(_ptr(table), table.numel(), _ptr(idx), _ptr(val),
+                                      idx.numel(), table.element_size(), _ptr(out),
+                                      _stream_handle(stream)), "spmv_gather_probe")
+    return out
+
+
 # ---- selector training kernels -------------------------------------------------
 
 def mlp_param_count(n_out=C.K_COUNT):

@@ -116,3 +116,28 @@ def test_selector_inference_matches_training_forward_and_oracle():
                       std.astype(np.float64))
     s_ref, _ = OM.forward(OM.unflatten(flat.astype(np.float64), C), z)
     np.testing.assert_allclose(sc, s_ref, rtol=1e-4, atol=1e-5)
+
+
+def test_gather_probe_sums():
+    """The random-gather probe computes what it states: per thread, the
+    ordered float64 sum of val[i] * table[idx[i]] over its grid-stride
+    indices (checked against numpy on a small input with a ragged tail)."""
+    import torch
+    from paper_1210_2536_amd import capi as C
+    from paper_1210_2536_amd.spmv import gather_probe
+    G = int(C.lib().spmv_gather_probe_threads())
+    rng = np.random.default_rng(71)
+    count = 3 * G + 12345
+    for dt in (np.float64, np.float32):
+        table = rng.uniform(-1, 1, 1000).astype(dt)
+        idx = rng.integers(0, 1000, count).astype(np.int32)
+        val = rng.uniform(-1, 1, count).astype(dt)
+        out = gather_probe(torch.from_numpy(table).cuda(), torch.from_numpy(idx).cuda(),
+                           torch.from_numpy(val).cuda()).cpu().numpy()
+        prod = val.astype(np.float64) * table[idx].astype(np.float64)
+        pad = np.zeros(4 * G)
+        pad[:count] = prod
+        ref = pad.reshape(4, G).sum(axis=0)
+        absref = np.abs(pad).reshape(4, G).sum(axis=0)
+        tol = 1e-15 if dt == np.float64 else 2 ** -24
+        assert np.all(np.abs(out.astype(np.float64) - ref) <= tol * absref + 1e-300)
