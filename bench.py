@@ -97,6 +97,8 @@ def parse():
     ap.add_argument("--segments", type=int, default=0,
                     help="plan every matrix as this many row segments, each with its own "
                          "format and kernel (records and the step are per segment)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="time plain back-to-back runs only (no graph / persistent trial)")
     ap.add_argument("--no-staged", action="store_true",
                     help="extract every feature before selecting (no staged early exit) "
                          "for the timed plans")
@@ -229,15 +231,22 @@ def main():
     log(f"dominant kernel {dominant}: {sym_time[dominant]:.3f} ms of "
         f"{sum(sym_time.values()):.3f} ms per step")
 
-    # ---- multilevel workloads: all levels in one persistent launch, one
-    # graph replay, or one launch per level; a short trial picks the mode
+    # ---- the step as one captured graph of every plan's launches (and, for
+    # the multilevel workloads, as one persistent launch); a short trial
+    # against plain back-to-back runs picks the mode
     batches, ml = {}, None
-    if a.workload in ("multilevel", "multilevel32"):
+    owners = []
+    for r in recs:   # whole-matrix plans with their full output vectors
+        if not owners or owners[-1][0] is not r["owner"]:
+            owners.append((r["owner"], r["x"], r["py"]))
+    if not a.no_batch:
         from paper_1210_2536_amd.spmv import Batch
-        xs, ys = [r["x"] for r in recs], [r["y"] for r in recs]
+        xs, ys = [o[1] for o in owners], [o[2] for o in owners]
         ml = {}
-        for mode, name in ((0, "persistent"), (1, "graph")):
-            b = Batch([r["tuned"] for r in recs], mode=mode)
+        modes = ((0, "persistent"), (1, "graph")) if a.workload.startswith("multilevel") \
+            else ((1, "graph"),)
+        for mode, name in modes:
+            b = Batch([o[0] for o in owners], mode=mode)
             if mode == 0:
                 b.tune(xs, ys)
                 ml["persistent_grid"], ml["persistent_split"] = b.shape()
@@ -261,7 +270,7 @@ def main():
         ml["mode"] = min(ml["trial_ms"], key=ml["trial_ms"].get)
         if replay_step:
             ml["mode"] = replay_step  # profile the recorded run's step, not this trial's pick
-        log(f"multilevel trial (ms/step): {ml['trial_ms']} -> {ml['mode']}")
+        log(f"step trial (ms/step): {ml['trial_ms']} -> {ml['mode']}")
     step_mode = ml["mode"] if ml else "separate"
 
     # ---- timed region: K steps of every tuned SpMV
@@ -511,7 +520,7 @@ def main():
         "config": {"workload": workload_name,
                    "matrices": len(items), "nnz_per_step": int(flops / 2), "selector": selector,
                    "step": step_mode, "segments": a.segments, "staged": not a.no_staged},
-        "multilevel": ml,
+        "step_trial": ml,
         "hbm_gbs": round(hbm_gbs, 1),
         "hbm_frac_peak": round(hbm_gbs / HBM_PEAK_GBS, 4),
         "stream_copy_gbs": round(copy_gbs, 1),

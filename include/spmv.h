@@ -373,7 +373,10 @@ spmv_status spmv_mlp_adam(float *params_dev, const float *grad_dev, float *adam_
  * CSR_ADAPTIVE (unless rows were split into segments), ELL, DIA and
  * DIA_DIRECT levels, each with its plan's tile shape; levels with other
  * kernels are launched separately on the same stream, after the persistent
- * kernel. */
+ * kernel.  Mode 0 takes 1..16 plans of one dtype; mode 1 takes 1..4096
+ * plans of any dtypes and kernels (every spmv_run of the batch, in order,
+ * captured on the first run and again whenever the vectors change).
+ * EINVAL otherwise. */
 spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplans, int32_t mode,
                               spmv_batch_t *out);
 spmv_status spmv_batch_run(spmv_batch_t batch, const void *const *xs_dev, void *const *ys_dev,

@@ -18,7 +18,8 @@
 namespace smat {
 namespace {
 
-constexpr int kMaxLevels = 16;
+constexpr int kMaxLevels = 16;        // persistent mode
+constexpr int kMaxGraphPlans = 4096;  // graph mode
 constexpr int kPBlock = 256;   // persistent workgroup size
 constexpr int kPDiaRpt = 4;    // rows per thread of a DIA tile
 
@@ -245,8 +246,10 @@ struct spmv_batch_s {
 
 extern "C" spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplans, int32_t mode,
                                          spmv_batch_t *out) {
-    if (!out || !plans || nplans <= 0 || nplans > kMaxLevels || (mode != 0 && mode != 1)) {
-        set_error("spmv_batch_create: need 1..%d plans and mode 0 or 1", kMaxLevels);
+    const int most = mode == 1 ? kMaxGraphPlans : kMaxLevels;
+    if (!out || !plans || (mode != 0 && mode != 1) || nplans <= 0 || nplans > most) {
+        set_error("spmv_batch_create: mode 0 with 1..%d plans or mode 1 with 1..%d", kMaxLevels,
+                  kMaxGraphPlans);
         return SPMV_EINVAL;
     }
     *out = nullptr;
@@ -259,8 +262,8 @@ extern "C" spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplan
             set_error("plan %d is NULL", l);
             return SPMV_EINVAL;
         }
-        if (plans[l]->elt != B->elt) {
-            set_error("all plans of a batch must share one dtype");
+        if (mode == 0 && plans[l]->elt != B->elt) {
+            set_error("all plans of a persistent batch must share one dtype");
             return SPMV_EINVAL;
         }
         B->plans.push_back(plans[l]);

@@ -141,3 +141,54 @@ def test_gather_probe_sums():
         absref = np.abs(pad).reshape(4, G).sum(axis=0)
         tol = 1e-15 if dt == np.float64 else 2 ** -24
         assert np.all(np.abs(out.astype(np.float64) - ref) <= tol * absref + 1e-300)
+
+
+def test_graph_batch_of_many_mixed_plans():
+    """Graph mode takes many plans of both dtypes and every kernel class
+    (column panels, COO, BCSR, segmented plans included): each replay gives
+    every plan's own result bit for bit, also after the vectors change;
+    persistent mode keeps its limits (16 plans, one dtype)."""
+    import torch
+    from paper_1210_2536_amd.spmv import Batch, Plan
+    mats = [S.stencil_7pt(12), S.blocks_g3(np.random.default_rng([72, 0]), 4000),
+            S.zipf_g2(np.random.default_rng([72, 1]), 30_000),
+            S.uniform_g1(np.random.default_rng([72, 2]), 5000)]
+    choices = [("dia_direct", {}), ("bcsr", {}), ("coo", {}), ("csr_panel", {"panel_kib": 16}),
+               ("ell", {}), ("csr_adaptive", {}), ("csr_vector", {}), ("mlp", {}), ("rules", {})]
+    plans, xs, refs, mats_of = [], [], [], []
+    for i in range(40):
+        A = mats[i % len(mats)]
+        dt = np.float64 if (i // 2) % 2 == 0 else np.float32
+        k, prm = choices[i % len(choices)]
+        rp, col, val = dev(A, dt)
+        try:
+            if k in ("mlp", "rules"):
+                p = Plan(rp, col, val, n=A.n, selector=k, segments=3 if i % 3 == 0 else 0)
+            else:
+                p = Plan(rp, col, val, n=A.n, selector=k, params=prm or None)
+        except Exception:  # kernel infeasible for this matrix (zero fill)
+            p = Plan(rp, col, val, n=A.n, selector="csr_adaptive")
+        x = S.uniform_vector(A.n, [73, i])
+        xv = vec(x, dt)
+        y = p.run(xv)
+        assert_parity(y.cpu().numpy(), A, x, dt)
+        plans.append(p)
+        xs.append(xv)
+        refs.append(y.cpu().numpy())
+    note("[batch] graph mode, 40 mixed plans")
+    B = Batch(plans, mode=1)
+    for rep in range(3):
+        ys = [torch.full((p.m,), float("nan"), dtype=x.dtype, device="cuda")
+              for p, x in zip(plans, xs)]   # new vectors: recapture on the first replay
+        for _ in range(2):
+            B.run(xs, ys)
+            torch.cuda.synchronize()
+            for y, r in zip(ys, refs):
+                assert np.array_equal(y.cpu().numpy().view(np.uint8), r.view(np.uint8)), rep
+            for y in ys:
+                y.fill_(float("nan"))
+    B.close()
+    with pytest.raises(capi.SpmvError):
+        Batch(plans[:17], mode=0)
+    with pytest.raises(capi.SpmvError):
+        Batch([plans[0], plans[2]], mode=0)   # float64 and float32
