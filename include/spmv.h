@@ -160,7 +160,12 @@ typedef struct {
                                    1/4 of free device memory                */
     spmv_selector_t model;      /* learned model (NULL: rules)                */
     int32_t autotune;           /* 1: time a few parameter points for the
-                                   chosen kernel and keep the fastest        */
+                                   chosen kernel and keep the fastest (the
+                                   paper's offline kernel search, Section
+                                   3); a point is only kept if its output on
+                                   an all-ones probe vector agrees with the
+                                   starting point's within twice the
+                                   accuracy bound (info.tune_rejected)     */
     int32_t use_params;         /* 1: take `params` as given                  */
     spmv_params params;
     int32_t segments;           /* >= 2: cut the rows into this many segments
@@ -240,6 +245,11 @@ typedef struct {
                                            ran                               */
     float stage_confidence;             /* MLP stage rule: confidence of the
                                            leaf reached, -1 if not consulted */
+    int32_t tune_rejected;              /* parameter points the autotuner
+                                           dropped because their output on
+                                           the all-ones probe left twice the
+                                           accuracy bound of the starting
+                                           point's (0 when all agree)      */
 } spmv_plan_info;
 
 typedef struct spmv_plan_s *spmv_plan_t;

@@ -68,7 +68,8 @@ class spmv_plan_info(ctypes.Structure):
                 ("t_select_ms", f64), ("t_convert_ms", f64), ("t_plan_ms", f64),
                 ("mlp_input", f32 * 12), ("rules_kernel", i32),
                 ("out_of_domain", i32), ("t_tune_ms", f64), ("bcsr_blocks", i64),
-                ("n_segments", i32), ("feature_stage", i32), ("stage_confidence", f32)]
+                ("n_segments", i32), ("feature_stage", i32), ("stage_confidence", f32),
+                ("tune_rejected", i32)]
 
 
 _SIGS = {

@@ -78,6 +78,28 @@ __global__ void k_fill_one(int64_t n, int elt, void *x) {
         ((float *)x)[i] = 1.0f;
 }
 
+// Row sums of |a_ij|: (|A||x|)_i for the all-ones probe vector.
+template <typename T>
+__global__ void k_row_abs_sum(int64_t m, const int32_t *__restrict__ rp,
+                              const T *__restrict__ val, double *__restrict__ out) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double s = 0.0;
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) s += fabs((double)val[p]);
+    out[i] = s;
+}
+
+// Sets *bad unless |y_i - ref_i| <= tol (|A||x|)_i for every row (a NaN
+// difference counts as a disagreement).
+template <typename T>
+__global__ void k_tune_check(int64_t m, const T *__restrict__ y, const T *__restrict__ ref,
+                             const double *__restrict__ absrow, double tol, unsigned *bad) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const double d = fabs((double)y[i] - (double)ref[i]);
+    if (!(d <= tol * absrow[i])) atomicOr(bad, 1u);
+}
+
 }  // namespace
 }  // namespace smat
 
@@ -978,16 +1000,36 @@ bool same_params(const spmv_params &a, const spmv_params &b) {
 // the same matrix between equivalent choices from one process to the next.
 constexpr double kSwitchMargin = 0.03;
 
-// Time the grid for the chosen kernel and keep the fastest variant.
+// Time the grid for the chosen kernel and keep the fastest variant.  Every
+// visited point must also reproduce the starting variant's output on the
+// all-ones probe vector within twice the accuracy contract (each result is
+// within the contract of the exact one): a point that does not is never
+// kept, and *rejected counts it.
 spmv_status autotune_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W, int reps,
-                             hipStream_t s, std::unique_ptr<Variant> &best) {
-    Dev xs, ys;
+                             hipStream_t s, std::unique_ptr<Variant> &best, int32_t *rejected) {
+    const int64_t m = P.m;
+    const unsigned g = (unsigned)((std::max<int64_t>(1, m) + 255) / 256);
+    Dev xs, ys, yref, absrow, bad;
     SMAT_TRY(xs.alloc((size_t)P.elt * std::max<int64_t>(1, P.n)));
-    SMAT_TRY(ys.alloc((size_t)P.elt * std::max<int64_t>(1, P.m)));
+    SMAT_TRY(ys.alloc((size_t)P.elt * std::max<int64_t>(1, m)));
+    SMAT_TRY(yref.alloc((size_t)P.elt * std::max<int64_t>(1, m)));
+    SMAT_TRY(absrow.alloc(sizeof(double) * (size_t)std::max<int64_t>(1, m)));
+    SMAT_TRY(bad.alloc(sizeof(unsigned)));
     if (P.n) k_fill_one<<<(unsigned)((P.n + 255) / 256), 256, 0, s>>>(P.n, P.elt, xs.p);
     SMAT_LAUNCHED("fill_one");
     double best_ms = 0;
     SMAT_TRY(time_variant(P, *best, xs.p, ys.p, reps, s, &best_ms));
+    if (m) {
+        SMAT_HIP(hipMemcpyAsync(yref.p, ys.p, (size_t)P.elt * m, hipMemcpyDeviceToDevice, s));
+        if (P.elt == 8)
+            k_row_abs_sum<double><<<g, 256, 0, s>>>(m, P.rp.as<int32_t>(), P.val.as<double>(),
+                                                    absrow.as<double>());
+        else
+            k_row_abs_sum<float><<<g, 256, 0, s>>>(m, P.rp.as<int32_t>(), P.val.as<float>(),
+                                                   absrow.as<double>());
+        SMAT_LAUNCHED("row_abs_sum");
+    }
+    const double tol = 2.0 * (P.elt == 8 ? 1e-12 : 2e-6);
     const int kernel = best->kernel;
     for (const spmv_params &p : tune_grid(kernel, best->prm, F, P.dtype)) {
         if (same_params(p, best->prm)) continue;
@@ -997,6 +1039,23 @@ spmv_status autotune_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork
         if (st != SPMV_OK) return st;
         double ms = 0;
         SMAT_TRY(time_variant(P, *V, xs.p, ys.p, reps, s, &ms));
+        if (m) {
+            unsigned h = 0;
+            SMAT_HIP(hipMemsetAsync(bad.p, 0, sizeof(unsigned), s));
+            if (P.elt == 8)
+                k_tune_check<double><<<g, 256, 0, s>>>(m, ys.as<double>(), yref.as<double>(),
+                                                       absrow.as<double>(), tol, bad.as<unsigned>());
+            else
+                k_tune_check<float><<<g, 256, 0, s>>>(m, ys.as<float>(), yref.as<float>(),
+                                                      absrow.as<double>(), tol, bad.as<unsigned>());
+            SMAT_LAUNCHED("tune_check");
+            SMAT_HIP(hipMemcpyAsync(&h, bad.p, sizeof(unsigned), hipMemcpyDeviceToHost, s));
+            SMAT_HIP(hipStreamSynchronize(s));
+            if (h) {
+                ++*rejected;
+                continue;
+            }
+        }
         if (ms < best_ms * (1.0 - kSwitchMargin)) {
             best_ms = ms;
             best = std::move(V);
@@ -1456,7 +1515,7 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
     }
     if (opts.autotune && !opts.use_params) {
         auto t_tune0 = std::chrono::steady_clock::now();
-        SMAT_TRY(autotune_variant(*P, F, W, opts.timing_reps, s, P->var));
+        SMAT_TRY(autotune_variant(*P, F, W, opts.timing_reps, s, P->var, &I.tune_rejected));
         SMAT_HIP(hipStreamSynchronize(s));
         I.t_tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
                                                                 t_tune0).count();

@@ -314,6 +314,61 @@ class _SegmentPlan(Plan):
         self.handle = None
 
 
+class TuneCache:
+    """Chosen kernel and parameters per matrix structure, kept as JSON (the
+    result of the paper's kernel search, reused instead of searched again).
+
+    The key is the device architecture, the value type and the integer
+    structure features (sizes, row-length moments, diagonals, bandwidth,
+    4x4 blocks); matrices alike in all of them share an entry.  A hit plans
+    with the recorded kernel and parameters (no selection, no search); a
+    miss plans with selection and autotuning and records the outcome.
+    Every kernel computes the same product, so a shared entry only affects
+    speed.
+    """
+
+    KEY_FEATURES = ("m", "n", "nnz", "sum_rd", "sum_rd2", "max_rd", "min_rd", "ndiags",
+                    "ntdiags", "bandwidth", "blocks4")
+
+    def __init__(self, path):
+        self.path = path
+        self.entries = {}
+        if os.path.exists(path):
+            with open(path) as fh:
+                self.entries = json.load(fh)
+        self.hits = self.misses = 0
+
+    def key(self, row_ptr, col, val, n):
+        torch = _torch()
+        f = features(row_ptr, col, val, n)
+        arch = torch.cuda.get_device_properties(val.device).gcnArchName.split(":")[0]
+        dt = "float64" if val.dtype == torch.float64 else "float32"
+        return "|".join([arch, dt] + [str(int(f[k])) for k in self.KEY_FEATURES])
+
+    def plan(self, row_ptr, col, val, n=None, **kw):
+        """A Plan from the cache, or a tuned one recorded into it."""
+        n = row_ptr.numel() - 1 if n is None else int(n)
+        k = self.key(row_ptr, col, val, n)
+        e = self.entries.get(k)
+        if e is not None:
+            self.hits += 1
+            return Plan(row_ptr, col, val, n=n, selector=e["kernel"], params=e["params"],
+                        stream=kw.get("stream"))
+        self.misses += 1
+        kw.setdefault("autotune", True)
+        p = Plan(row_ptr, col, val, n=n, **kw)
+        info = p.info()
+        if info["n_segments"] == 0:
+            self.entries[k] = {"kernel": info["kernel_name"], "params": info["params"]}
+        return p
+
+    def save(self):
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as fh:
+            json.dump(self.entries, fh, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+
 class Batch:
     """spmv_batch_*: all levels in one persistent launch (mode 0) or a graph (1)."""
 

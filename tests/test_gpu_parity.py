@@ -300,3 +300,49 @@ def test_segmented_plans(dtype):
         torch.cuda.synchronize()
         assert np.array_equal(y.cpu().numpy().view(np.uint8), ref.view(np.uint8)), mode
         B.close()
+
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
+def test_autotuned_plans_every_point_agrees(dtype):
+    """The autotuner checks every parameter point it times against its
+    starting point on an all-ones probe (twice the accuracy bound); on these
+    matrices no point is rejected, and the kept plan matches the oracle."""
+    from paper_1210_2536_amd.spmv import Plan
+    mats = [S.stencil_7pt(24), S.stencil_27pt(14),
+            S.uniform_g1(np.random.default_rng([80, 0]), 30_000),
+            S.zipf_g2(np.random.default_rng([80, 1]), 60_000),
+            S.blocks_g3(np.random.default_rng([80, 2]), 40_000)]
+    for i, A in enumerate(mats):
+        for sel in ("rules", "mlp"):
+            note(f"[autotune] {A.name} {np.dtype(dtype).name} {sel}")
+            rp, col, val = dev(A, dtype)
+            p = Plan(rp, col, val, n=A.n, selector=sel, autotune=True)
+            info = p.info()
+            assert info["tune_rejected"] == 0, (A.name, info["kernel_name"])
+            x = np.random.default_rng([81, i]).uniform(-1, 1, A.n)
+            assert_parity(p.run(vec(x, dtype)).cpu().numpy(), A, x, dtype)
+
+
+def test_tune_cache_round_trip(tmp_path):
+    """A tuned plan's kernel and parameters go into the JSON cache; a new
+    cache read from the file plans the same matrix with them, without
+    selection or search, and the result matches the oracle."""
+    from paper_1210_2536_amd.spmv import TuneCache
+    path = str(tmp_path / "tune.json")
+    A = S.zipf_g2(np.random.default_rng([82, 0]), 50_000)
+    x = np.random.default_rng([82, 1]).uniform(-1, 1, A.n)
+    for dtype in (np.float64, np.float32):
+        rp, col, val = dev(A, dtype)
+        c1 = TuneCache(path)
+        p1 = c1.plan(rp, col, val, n=A.n, selector="mlp")
+        assert c1.misses == 1 and c1.hits == 0
+        c1.save()
+        c2 = TuneCache(path)
+        p2 = c2.plan(rp, col, val, n=A.n)
+        assert c2.hits == 1 and c2.misses == 0
+        i1, i2 = p1.info(), p2.info()
+        assert i2["kernel"] == i1["kernel"] and i2["params"] == i1["params"]
+        assert i2["t_tune_ms"] == 0.0 and i2["selector_used"] == 3  # forced
+        assert_parity(p2.run(vec(x, dtype)).cpu().numpy(), A, x, dtype)
+    # both dtypes are kept apart
+    assert len(TuneCache(path).entries) == 2
