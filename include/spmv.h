@@ -139,6 +139,21 @@ typedef struct {
 
 typedef struct spmv_selector_s *spmv_selector_t;
 
+/* Device memory for a plan (an interface convention, not from the paper:
+ * the caller's framework may own all device memory, e.g. PyTorch's caching
+ * allocator).  alloc returns at least `bytes` bytes of device memory on the
+ * current device, 256-byte aligned, or NULL (plan creation then fails with
+ * ENOMEM); free returns a block from alloc with its size.  ctx is passed
+ * through.  alloc runs during spmv_plan_create and spmv_convert_roundtrip
+ * on the calling thread; free runs there and in spmv_plan_destroy.  Both
+ * NULL (the default): hipMalloc / hipFree.  Selectors and batches always
+ * use hipMalloc. */
+typedef struct {
+    void *(*alloc)(size_t bytes, void *ctx);
+    void (*free)(void *ptr, size_t bytes, void *ctx);
+    void *ctx;
+} spmv_allocator;
+
 typedef struct {
     int32_t selector;           /* spmv_selector_mode; default MLP when a model
                                    is given, RULES otherwise                  */
@@ -193,6 +208,8 @@ typedef struct {
                                    (the share of training matrices of the
                                    rule's leaf on which its kernel ran within
                                    5% of the fastest); <= 0: default 0.98  */
+    spmv_allocator allocator;   /* plan memory (see spmv_allocator); EINVAL
+                                   unless both callbacks or neither are set */
 } spmv_plan_opts;
 
 /* Feature parameters of Table 3 (Section 4) plus the selector's extras.

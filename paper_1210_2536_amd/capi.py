@@ -41,12 +41,20 @@ class spmv_params(ctypes.Structure):
                 ("panel_kib", i32), ("panel_xcd", i32), ("wide_loads", i32), ("bcsr_lanes", i32)]
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(vp, ctypes.c_size_t, vp)
+FREE_FN = ctypes.CFUNCTYPE(None, vp, ctypes.c_size_t, vp)
+
+
+class spmv_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", vp)]
+
+
 class spmv_plan_opts(ctypes.Structure):
     _fields_ = [("selector", i32), ("force_kernel", i32), ("confidence_tau", f32),
                 ("measure_topk", i32), ("timing_reps", i32), ("disable_mask", u32),
                 ("mem_cap_bytes", u64), ("model", vp), ("autotune", i32), ("use_params", i32),
                 ("params", spmv_params), ("segments", i32), ("staged", i32),
-                ("stage_conf", f32)]
+                ("stage_conf", f32), ("allocator", spmv_allocator)]
 
 
 class spmv_features(ctypes.Structure):

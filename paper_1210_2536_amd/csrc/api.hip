@@ -24,6 +24,8 @@ namespace {
 thread_local char g_err[1024] = "";
 }
 
+thread_local spmv_allocator g_alloc{};
+
 void set_error(const char *fmt, ...) {
     va_list ap;
     va_start(ap, fmt);
@@ -1168,6 +1170,7 @@ static spmv_status plan_create_segments(const spmv_csr *A, const spmv_plan_opts 
                                         hipStream_t s, spmv_plan_t *out,
                                         std::chrono::steady_clock::time_point t_start) {
     auto P = std::make_unique<spmv_plan_s>();
+    P->alloc = opts.allocator;
     P->m = A->m;
     P->n = A->n;
     P->nnz = A->nnz;
@@ -1252,6 +1255,11 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
         set_error("staged must be 0 or 1");
         return SPMV_EINVAL;
     }
+    if (!opts.allocator.alloc != !opts.allocator.free) {
+        set_error("allocator needs both alloc and free, or neither");
+        return SPMV_EINVAL;
+    }
+    AllocScope scope(opts.allocator);
     int mode = opts.selector;
     if (mode < 0) mode = opts.model ? SPMV_SELECT_MLP : SPMV_SELECT_RULES;
     if (mode > SPMV_SELECT_FORCED) {
@@ -1273,6 +1281,7 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
     if (opts.segments >= 2 && A->m >= 2 && A->nnz > 0)
         return plan_create_segments(A, opts, mode, s, out, t_start);
     auto P = std::make_unique<spmv_plan_s>();
+    P->alloc = opts.allocator;
     P->m = A->m;
     P->n = A->n;
     P->nnz = A->nnz;
@@ -1622,6 +1631,7 @@ extern "C" spmv_status spmv_convert_roundtrip(spmv_plan_t P, int32_t *rp, int32_
         return SPMV_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
+    AllocScope scope(P->alloc);
     if (!P->seg.empty()) {
         // each segment rebuilds its rows; their row pointers are shifted by
         // the entries before the segment (its last entry is the next start)

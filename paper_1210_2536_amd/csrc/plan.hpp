@@ -8,22 +8,55 @@
 
 namespace smat {
 
-// Device allocation owned by a plan or a candidate.
+// The caller's allocator in effect on this thread (both callbacks NULL: the
+// library's hipMalloc / hipFree).  Plan creation installs opts.allocator for
+// its duration with AllocScope.
+extern thread_local spmv_allocator g_alloc;
+
+struct AllocScope {
+    spmv_allocator saved;
+    explicit AllocScope(const spmv_allocator &a) : saved(g_alloc) { g_alloc = a; }
+    ~AllocScope() { g_alloc = saved; }
+    AllocScope(const AllocScope &) = delete;
+    AllocScope &operator=(const AllocScope &) = delete;
+};
+
+// Device allocation owned by a plan or a candidate; it remembers the
+// allocator it came from and returns the memory there.
 struct Dev {
     void *p = nullptr;
     size_t bytes = 0;
+    spmv_allocator from{};
     Dev() = default;
     Dev(const Dev &) = delete;
     Dev &operator=(const Dev &) = delete;
     ~Dev() { release(); }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (from.free)
+                from.free(p, bytes, from.ctx);
+            else
+                (void)hipFree(p);
+        }
         p = nullptr;
         bytes = 0;
+        from = spmv_allocator{};
     }
     spmv_status alloc(size_t b) {
         release();
         if (b == 0) b = 16;
+        if (g_alloc.alloc) {
+            p = g_alloc.alloc(b, g_alloc.ctx);
+            if (!p || (reinterpret_cast<uintptr_t>(p) & 255u)) {
+                if (p) g_alloc.free(p, b, g_alloc.ctx);
+                p = nullptr;
+                set_error("caller's allocator gave no 256-byte aligned block of %zu bytes", b);
+                return SPMV_ENOMEM;
+            }
+            from = g_alloc;
+            bytes = b;
+            return SPMV_OK;
+        }
         hipError_t e = hipMalloc(&p, b);
         if (e != hipSuccess) {
             p = nullptr;
@@ -85,6 +118,7 @@ struct spmv_selector_s {
 };
 
 struct spmv_plan_s {
+    spmv_allocator alloc{};            // the caller's allocator of this plan
     int64_t m = 0, n = 0, nnz = 0;
     int dtype = 0, elt = 4;
     int64_t m_pad = 0;

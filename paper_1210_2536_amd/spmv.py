@@ -169,6 +169,54 @@ def default_selector():
     return Selector.load(DEFAULT_WEIGHTS)
 
 
+class TorchAllocator:
+    """Plan memory from PyTorch's caching allocator (spmv_allocator): every
+    block is a uint8 tensor on the device, held until the library frees it."""
+
+    def __init__(self, device):
+        self.device = device
+        self.blocks = {}
+
+        def alloc(nbytes, ctx):
+            try:
+                t = _torch().empty(int(nbytes), dtype=_torch().uint8, device=self.device)
+            except Exception:  # out of memory: the library reports ENOMEM
+                return None
+            self.blocks[t.data_ptr()] = t
+            return t.data_ptr()
+
+        def free(ptr, nbytes, ctx):
+            try:
+                self.blocks.pop(ptr, None)
+            except Exception:  # interpreter shutting down
+                pass
+
+        self._alloc = C.ALLOC_FN(alloc)   # the callbacks must outlive every plan
+        self._free = C.FREE_FN(free)
+
+    def fill(self, opts):
+        opts.allocator.alloc = self._alloc
+        opts.allocator.free = self._free
+        opts.allocator.ctx = None
+
+    def bytes_held(self):
+        return sum(t.numel() for t in self.blocks.values())
+
+
+_TORCH_ALLOCATORS = {}
+
+
+def torch_allocator(device):
+    """The process-wide TorchAllocator of a device."""
+    torch = _torch()
+    device = torch.device(device)
+    if device.index is None:
+        device = torch.device(device.type, torch.cuda.current_device())
+    if device not in _TORCH_ALLOCATORS:
+        _TORCH_ALLOCATORS[device] = TorchAllocator(device)
+    return _TORCH_ALLOCATORS[device]
+
+
 class Plan:
     """spmv_plan_create / spmv_run over torch device tensors.
 
@@ -177,7 +225,8 @@ class Plan:
 
     def __init__(self, row_ptr, col, val, n=None, selector="rules", model=None,
                  tau=None, topk=None, reps=None, disable=(), mem_cap=0, params=None,
-                 autotune=False, segments=0, staged=True, stage_conf=None, stream=None):
+                 autotune=False, segments=0, staged=True, stage_conf=None,
+                 allocator="torch", stream=None):
         torch = _torch()
         m = row_ptr.numel() - 1
         n = m if n is None else int(n)
@@ -212,6 +261,11 @@ class Plan:
         o.staged = 1 if staged else 0
         if stage_conf is not None:
             o.stage_conf = float(stage_conf)
+        # plan memory from torch's caching allocator ("torch"), the library's
+        # hipMalloc (None), or a TorchAllocator given by the caller
+        self._allocator = torch_allocator(val.device) if allocator == "torch" else allocator
+        if self._allocator is not None:
+            self._allocator.fill(o)
         if selector == "mlp" and tau is None and model is not None and \
                 getattr(model, "tau", None) is not None:
             o.confidence_tau = model.tau

@@ -52,6 +52,13 @@ def test_status_strings_without_gpu():
     assert L.spmv_plan_opts_default(ctypes.byref(o)) == capi.SPMV_OK
     assert o.measure_topk == 3 and o.timing_reps == 5 and abs(o.confidence_tau - 0.1) < 1e-7
     assert o.staged == 1 and abs(o.stage_conf - 0.98) < 1e-7
+    assert not o.allocator.alloc and not o.allocator.free
+    # an allocator needs both callbacks (checked before any device work)
+    o.allocator.alloc = capi.ALLOC_FN(lambda nbytes, ctx: None)
+    csr = capi.spmv_csr(4, 4, 3, 1, 1, 1, 1)
+    assert L.spmv_plan_create(ctypes.byref(csr), ctypes.byref(o), None,
+                              ctypes.byref(out)) == capi.SPMV_EINVAL
+    assert b"allocator" in L.spmv_last_error()
 
 
 PROBE = r"""
@@ -66,7 +73,7 @@ int main(void) {
   O(spmv_plan_info, measured_ms) O(spmv_plan_info, features) O(spmv_plan_info, params)
   O(spmv_plan_info, m_pad) O(spmv_plan_info, t_plan_ms) O(spmv_features, aver_rd)
   O(spmv_plan_info, mlp_input) O(spmv_plan_info, rules_kernel) O(spmv_plan_info, out_of_domain) O(spmv_plan_info, t_tune_ms) O(spmv_plan_info, bcsr_blocks) O(spmv_plan_info, n_segments) O(spmv_plan_opts, segments)
-  O(spmv_plan_opts, staged) O(spmv_plan_opts, stage_conf) O(spmv_plan_info, feature_stage) O(spmv_plan_info, stage_confidence) O(spmv_plan_info, tune_rejected)
+  O(spmv_plan_opts, staged) O(spmv_plan_opts, stage_conf) O(spmv_plan_info, feature_stage) O(spmv_plan_info, stage_confidence) O(spmv_plan_info, tune_rejected) O(spmv_plan_opts, allocator) S(spmv_allocator)
   O(spmv_features, dia_feasible)
   return 0;
 }

@@ -346,3 +346,35 @@ def test_tune_cache_round_trip(tmp_path):
         assert_parity(p2.run(vec(x, dtype)).cpu().numpy(), A, x, dtype)
     # both dtypes are kept apart
     assert len(TuneCache(path).entries) == 2
+
+
+def test_plan_memory_from_the_callers_allocator():
+    """Plans take their device memory from the caller's allocator (here
+    PyTorch's caching allocator through spmv_allocator) and give it back on
+    destruction; with no allocator the library's own is used.  Results are
+    the same either way."""
+    import torch
+    from paper_1210_2536_amd.spmv import Plan, TorchAllocator
+    A = S.zipf_g2(np.random.default_rng([83, 0]), 40_000)
+    x = np.random.default_rng([83, 1]).uniform(-1, 1, A.n)
+    rp, col, val = dev(A, np.float64)
+    ta = TorchAllocator(torch.device("cuda", torch.cuda.current_device()))
+    for k in ("csr_adaptive", "coo", "ell", "csr_panel", "mlp"):
+        if k == "ell" and not OF.extract(A.m, A.n, A.row_ptr, A.col)["ell_feasible"]:
+            continue
+        note(f"[allocator] {k}")
+        kw = {"params": {"panel_kib": 16}} if k == "csr_panel" else {}
+        p = Plan(rp, col, val, n=A.n, selector=k, allocator=ta, autotune=(k == "mlp"), **kw)
+        held = ta.bytes_held()
+        assert held >= p.info()["device_bytes"] > 0, (k, held)
+        y = p.run(vec(x, np.float64)).cpu().numpy()
+        assert_parity(y, A, x, np.float64)
+        rp2, col2, v2 = p.roundtrip()    # temporaries through the allocator too
+        assert np.array_equal(col2.cpu().numpy(), A.col)
+        assert ta.bytes_held() == held
+        p.close()
+        assert ta.bytes_held() == 0, k
+        q = Plan(rp, col, val, n=A.n, selector=k, allocator=None, **kw)
+        assert ta.bytes_held() == 0
+        assert_parity(q.run(vec(x, np.float64)).cpu().numpy(), A, x, np.float64)
+        q.close()
