@@ -282,8 +282,14 @@ class Plan:
         self.dtype = val.dtype
         self.device = val.device
 
-    def run(self, x, y=None, stream=None):
+    def run(self, x, y=None, stream=None, out=None):
+        """y = A x on the current torch stream (or `stream`); y (or `out`)
+        is overwritten, or allocated when neither is given."""
         torch = _torch()
+        if out is not None:
+            if y is not None:
+                raise TypeError("give y or out, not both")
+            y = out
         if x.dtype != self.dtype or not x.is_contiguous() or x.numel() != self.n:
             raise TypeError("x must be a contiguous vector of length n and the matrix dtype")
         if y is None:

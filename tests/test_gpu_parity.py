@@ -71,6 +71,14 @@ def test_c1_laplacian_all_formats():
     for dtype in DTYPES:
         for k, y in _run_all(A, dtype, xp).items():
             assert np.array_equal(y.astype(np.float64), ref), (k, dtype)
+    # the call form plan(x, out=y) on the current torch stream
+    import torch
+    from paper_1210_2536_amd.spmv import Plan
+    rp, col, val = dev(A, np.float64)
+    plan = Plan(rp, col, val, n=A.n)
+    out = torch.full((A.m,), float("nan"), dtype=torch.float64, device="cuda")
+    assert plan(vec(xp, np.float64), out=out) is out
+    assert np.array_equal(out.cpu().numpy(), ref)
 
 
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
