@@ -97,6 +97,8 @@ def parse():
     ap.add_argument("--segments", type=int, default=0,
                     help="plan every matrix as this many row segments, each with its own "
                          "format and kernel (records and the step are per segment)")
+    ap.add_argument("--no-cold", action="store_true",
+                    help="skip the cold-cache runs (caches flushed before each SpMV)")
     ap.add_argument("--no-batch", action="store_true",
                     help="time plain back-to-back runs only (no graph / persistent trial)")
     ap.add_argument("--no-staged", action="store_true",
@@ -197,6 +199,39 @@ def main():
         r["rec"]["tuned_ms"] = time_run(r["tuned"], r["x"], r["y"])
         if r["plain"] is not None:
             r["rec"]["plain_ms"] = time_run(r["plain"], r["x"], r["py"])
+
+    # cold runs: the caches flushed by a 512 MiB copy (1 GiB of traffic, 4x
+    # the Infinity Cache) before each run, for working sets under 1 GB
+    cold = None
+    if not a.no_cold:
+        fl_src = torch.zeros(1 << 27, dtype=torch.float32, device=dev)
+        fl_dst = torch.empty_like(fl_src)
+        cold_ms = warm_ms = cold_flops = 0.0
+        n_cold = 0
+        for r in recs:
+            if r["rec"]["bytes"] >= 1e9:
+                continue
+            ts = []
+            for _ in range(3):
+                stream_copy(fl_dst, fl_src)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                r["tuned"].run(r["x"], r["y"])
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            r["rec"]["cold_ms"] = float(np.median(ts))
+            cold_ms += r["rec"]["cold_ms"]
+            warm_ms += r["rec"]["tuned_ms"]
+            cold_flops += 2.0 * r["rec"]["nnz"]
+            n_cold += 1
+        del fl_src, fl_dst
+        if n_cold:
+            cold = {"matrices": n_cold, "working_set": "< 1 GB",
+                    "cold_gflops": round(cold_flops / (cold_ms * 1e-3) / 1e9, 2),
+                    "warm_gflops": round(cold_flops / (warm_ms * 1e-3) / 1e9, 2),
+                    "timing": "one launch between events, median of 3, each after the flush"}
+            log(f"cold runs: {cold}")
     # Kernel symbol of each plan: the compiled kernel it launches (format
     # kernel, value type and the template parameters of its launch).
     def symbol(rec):
@@ -472,7 +507,26 @@ def main():
             used.append(A.name)
             if tsum >= a.cpu_seconds:
                 break
+        # the same oracle on one thread, over a bounded prefix of the sample
+        t1s, f1s, n1 = 0.0, 0.0, 0
+        done, sampled = set(), set(used)
+        for A, dt, xseed in items:
+            if id(A) in done or A.name not in sampled:
+                continue
+            done.add(id(A))
+            xv = S.uniform_vector(A.n, xseed)
+            rp64 = A.row_ptr.astype(np.int64)
+            vals = A.val.astype(np.float64)
+            t0c = time.perf_counter()
+            O.spmv_plain(rp64, A.col, vals, xv, nthreads=1)
+            t1s += time.perf_counter() - t0c
+            f1s += 2.0 * A.nnz
+            n1 += 1
+            if t1s >= a.cpu_seconds / 4:
+                break
         cpu = {"value": round(fsum / tsum / 1e9, 3), "unit": "GFLOP/s", "cores": threads,
+               "value_1_thread": round(f1s / t1s / 1e9, 3) if t1s else None,
+               "sample_1_thread": f"first {n1} sample matrices, one run each",
                "kind": "oracle",
                "sample": f"{len(used)} of {len(seen) if len(used) < len(items) else len(used)} "
                          f"distinct workload matrices in order (float64 values, naive sum, "
@@ -490,6 +544,16 @@ def main():
     select_units = [(r["rec"]["plan_ms"] - r["rec"]["tune_ms"]) / r["rec"]["plain_ms"]
                     for r in recs if r["rec"].get("plain_ms")]
     speedup = (plain_ms_step / ms_step) if plain_ms_step else None
+    # algorithmic GB/s by working set (per-plan event timings): sets of at
+    # least 0.9 GB (3.5x the Infinity Cache) stream from HBM, smaller ones
+    # are largely cache-resident
+    by_ws = {}
+    for tag, big in (("ge_0.9GB", True), ("lt_0.9GB_cache_resident", False)):
+        sel = [r["rec"] for r in recs if (r["rec"]["bytes"] >= 0.9e9) == big]
+        if sel:
+            by_ws[tag] = {"matrices": len(sel),
+                          "gbs": round(sum(x["bytes"] for x in sel) /
+                                       (sum(x["tuned_ms"] for x in sel) * 1e-3) / 1e9, 1)}
     plan_study = None
     if study:
         med = lambda tag, k: round(float(np.median([r[tag][k] for r in study])), 2)  # noqa: E731
@@ -521,8 +585,10 @@ def main():
                    "matrices": len(items), "nnz_per_step": int(flops / 2), "selector": selector,
                    "step": step_mode, "segments": a.segments, "staged": not a.no_staged},
         "step_trial": ml,
+        "cold": cold,
         "hbm_gbs": round(hbm_gbs, 1),
         "hbm_frac_peak": round(hbm_gbs / HBM_PEAK_GBS, 4),
+        "gbs_by_working_set": by_ws,
         "stream_copy_gbs": round(copy_gbs, 1),
         "plain_csr_gflops": round(flops / (plain_ms_step * 1e-3) / 1e9, 3) if plain_ms_step else None,
         "tuned_vs_plain": round(speedup, 4) if speedup else None,
