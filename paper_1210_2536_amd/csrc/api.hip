@@ -123,8 +123,8 @@ struct Scratch {
     RowStats rs;
     EntryStats es;
     DiagStats ds;
-    uint32_t flags;
-    uint32_t pad;
+    uint32_t flags;    // row_ptr check
+    uint32_t flags2;   // column checks
     double fit[5];
 };
 
@@ -147,8 +147,15 @@ spmv_status extract_rows(const spmv_csr &A, hipStream_t s, spmv_features &F, Fea
     Scratch h{};
     h.rs.min_rd = INT_MAX;
     SMAT_HIP(hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, s));
+    // the row_ptr check, the column checks (with the bandwidth) and the row
+    // pass share one synchronisation: the column and row passes stay in
+    // bounds whatever row_ptr holds, and their results are only used when
+    // the row_ptr check passes
     SMAT_TRY(launch_validate_rows(m, nnz, A.row_ptr_dev, &d->flags, s));
-    SMAT_HIP(hipMemcpyAsync(&h.flags, &d->flags, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    SMAT_TRY(launch_validate_entries(m, n, nnz, A.row_ptr_dev, A.col_dev, &d->flags2,
+                                     &d->es.bandwidth, s));
+    SMAT_TRY(launch_row_stats(m, A.row_ptr_dev, &d->rs, s));
+    SMAT_HIP(hipMemcpyAsync(&h, d, sizeof(Scratch), hipMemcpyDeviceToHost, s));
     SMAT_HIP(hipStreamSynchronize(s));
     if (h.flags) {
         set_error("invalid CSR row_ptr (flags 0x%x: %s%s%s)", h.flags,
@@ -157,13 +164,7 @@ spmv_status extract_rows(const spmv_csr &A, hipStream_t s, spmv_features &F, Fea
                   (h.flags & kBadRowPtrOrder) ? "row_ptr decreasing or out of range" : "");
         return SPMV_EINVAL;
     }
-    // column checks (with the bandwidth) and the row pass (which reads only
-    // row_ptr, valid by now) share one synchronisation
-    SMAT_TRY(launch_validate_entries(m, n, nnz, A.row_ptr_dev, A.col_dev, &d->flags,
-                                     &d->es.bandwidth, s));
-    SMAT_TRY(launch_row_stats(m, A.row_ptr_dev, &d->rs, s));
-    SMAT_HIP(hipMemcpyAsync(&h, d, sizeof(Scratch), hipMemcpyDeviceToHost, s));
-    SMAT_HIP(hipStreamSynchronize(s));
+    h.flags = h.flags2;
     if (h.flags) {
         set_error("invalid CSR columns (flags 0x%x: %s%s)", h.flags,
                   (h.flags & kBadColRange) ? "column out of [0, n) " : "",

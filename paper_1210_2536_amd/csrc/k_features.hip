@@ -47,7 +47,10 @@ __global__ void k_validate_rows(int64_t m, int64_t nnz, const int32_t *__restric
 }
 
 // Column checks, and the bandwidth max |j - i| on the way (meaningful once
-// the checks pass).
+// the checks pass).  It runs beside the row_ptr check, so it must stay in
+// bounds whatever row_ptr holds: rows are only looked up in rp[0..m] (m >= 1
+// whenever nnz > 0) and columns only read below nnz; a row_ptr that ends a
+// row past the last one is flagged as out of order.
 __global__ void k_validate_entries(int64_t m, int64_t n, int64_t nnz,
                                    const int32_t *__restrict__ rp,
                                    const int32_t *__restrict__ col, uint32_t *flags,
@@ -61,10 +64,14 @@ __global__ void k_validate_entries(int64_t m, int64_t n, int64_t nnz,
         int64_t row = row_of_entry(rp, m, p0);
         int64_t rend = rp[row + 1];
         for (int64_t p = p0; p < p1; ++p) {
-            while (p >= rend) rend = rp[++row + 1];
+            while (p >= rend && row + 1 < m) rend = rp[++row + 1];
+            if (p >= rend) {   // entries beyond rp[m]: a broken row_ptr
+                bad |= kBadRowPtrOrder;
+                break;
+            }
             int32_t c = col[p];
             if (c < 0 || (int64_t)c >= n) bad |= kBadColRange;
-            if (p + 1 < rend && col[p + 1] <= c) bad |= kBadColOrder;
+            if (p + 1 < rend && p + 1 < nnz && col[p + 1] <= c) bad |= kBadColOrder;
             int64_t d = (int64_t)c - row;
             int ad = (int)(d < 0 ? -d : d);
             bw = ad > bw ? ad : bw;

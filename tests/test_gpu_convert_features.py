@@ -135,6 +135,14 @@ def _bad_csr_cases():
     cases.append(("row_ptr_decreasing", r, good.col))
     r = good.row_ptr.copy(); r[0] = 1
     cases.append(("row_ptr0", r, good.col))
+    # row_ptr values far out of range: the column pass runs beside the
+    # row_ptr check and must stay in bounds anyway
+    r = good.row_ptr.copy(); r[3] = 2**31 - 1
+    cases.append(("row_ptr_huge", r, good.col))
+    r = good.row_ptr.copy(); r[4] = -5
+    cases.append(("row_ptr_negative", r, good.col))
+    r = np.zeros_like(good.row_ptr); r[-1] = good.row_ptr[-1]
+    cases.append(("row_ptr_all_in_last_row", r, good.col))   # valid, must pass
     return good, cases
 
 
@@ -144,11 +152,21 @@ def test_invalid_csr_is_rejected():
     from paper_1210_2536_amd.spmv import Plan
     good, cases = _bad_csr_cases()
     for name, rp, col in cases:
+        note(f"[invalid csr] {name}")
         B = S.CSR(good.m, good.n, rp, col, good.val, name)
         r, c, v = dev(B, np.float64)
+        if name == "row_ptr_all_in_last_row":
+            # every entry in the last row: columns repeat, so it is the
+            # column check that must refuse it
+            with pytest.raises(C.SpmvError) as ei:
+                Plan(r, c, v, n=good.n)
+            assert ei.value.status == C.SPMV_EINVAL and b"column" in C.lib().spmv_last_error()
+            continue
         with pytest.raises(C.SpmvError) as ei:
             Plan(r, c, v, n=good.n)
         assert ei.value.status == C.SPMV_EINVAL, name
+        assert b"row_ptr" in C.lib().spmv_last_error() or name in (
+            "unsorted", "duplicate", "col_too_big", "col_negative"), name
     # row_ptr[m] != nnz: give one value less
     r, c, v = dev(good, np.float64)
     with pytest.raises(C.SpmvError):
