@@ -274,8 +274,11 @@ class Plan:
             for k, v in params.items():
                 setattr(o.params, k, int(v))
         h = ctypes.c_void_p()
-        st = C.lib().spmv_plan_create(ctypes.byref(A), ctypes.byref(o), _stream_handle(stream),
-                                      ctypes.byref(h))
+        if val.device.type != "cuda" or row_ptr.device != val.device or col.device != val.device:
+            raise TypeError("row_ptr, col and val must be tensors on one GPU")
+        with torch.cuda.device(val.device):   # the library works on the current device
+            st = C.lib().spmv_plan_create(ctypes.byref(A), ctypes.byref(o),
+                                          _stream_handle(stream), ctypes.byref(h))
         C.check(st, "spmv_plan_create")
         self.handle = h
         self.m, self.n, self.nnz = m, n, int(col.numel())
@@ -296,8 +299,15 @@ class Plan:
             y = torch.empty(self.m, dtype=self.dtype, device=self.device)
         elif y.dtype != self.dtype or not y.is_contiguous() or y.numel() != self.m:
             raise TypeError("y must be a contiguous vector of length m and the matrix dtype")
-        C.check(C.lib().spmv_run(self.handle, _ptr(x), _ptr(y), _stream_handle(stream)),
-                "spmv_run")
+        if x.device != self.device or y.device != self.device:
+            raise TypeError("x and y must be on the plan's device")
+        if torch.cuda.current_device() == self.device.index:
+            C.check(C.lib().spmv_run(self.handle, _ptr(x), _ptr(y), _stream_handle(stream)),
+                    "spmv_run")
+        else:
+            with torch.cuda.device(self.device):   # the library works on the current device
+                C.check(C.lib().spmv_run(self.handle, _ptr(x), _ptr(y), _stream_handle(stream)),
+                        "spmv_run")
         return y
 
     __call__ = run

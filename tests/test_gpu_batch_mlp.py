@@ -166,7 +166,7 @@ def test_graph_batch_of_many_mixed_plans():
                 p = Plan(rp, col, val, n=A.n, selector=k, segments=3 if i % 3 == 0 else 0)
             else:
                 p = Plan(rp, col, val, n=A.n, selector=k, params=prm or None)
-        except Exception:  # kernel infeasible for this matrix (zero fill)
+        except capi.SpmvError:  # kernel infeasible for this matrix (zero fill)
             p = Plan(rp, col, val, n=A.n, selector="csr_adaptive")
         x = S.uniform_vector(A.n, [73, i])
         xv = vec(x, dt)
