@@ -596,10 +596,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64-accumulate (f32 and f64 storage)" if a.workload == "sweep" else
-                 ("f64" if all(dt == np.float64 for _, dt, _ in items) else "f64-accumulate"),
+        # every kernel multiplies and adds in float64 (float32 values and x
+        # are widened; float32 y is rounded once)
+        "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": workload_name,
+                   "storage": "+".join(sorted({np.dtype(dt).name for _, dt, _ in items})),
                    "matrices": len(items), "nnz_per_step": int(flops / 2), "selector": selector,
                    "step": step_mode, "segments": a.segments, "staged": not a.no_staged},
         "step_trial": ml,
