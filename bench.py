@@ -455,7 +455,7 @@ def main():
     # ---- selector hit rate against exhaustive timing (same session), and
     # the plan cost of untuned plans with all features up front vs staged
     # extraction (Table 6 analog, in plain-CSR SpMV times)
-    hit_rate = rules_hit_rate = None
+    hit_rate = rules_hit_rate = hit_rate_table = rules_hit_rate_table = None
     study = [] if selector in ("mlp", "rules") else None
     if a.segments >= 2:
         log("hit rate not measured for segmented plans (per segment, no whole-matrix best)")
@@ -476,9 +476,32 @@ def main():
             got = table.get(r["rec"]["kernel"], float("inf"))
             r["rec"]["exhaustive_ms"] = table
             r["rec"]["rules_kernel"] = capi.KERNELS[ei["rules_kernel"]]
-            r["rec"]["hit"] = bool(got <= 1.05 * best)
-            r["rec"]["rules_hit"] = bool(table.get(r["rec"]["rules_kernel"], float("inf"))
-                                         <= 1.05 * best)
+            best_k = min(table, key=table.get)
+
+            def judged(kernel, plan=None):
+                """Within 5% of the exhaustive best?  A miss by the table
+                (two timing sessions) that is under 1.5x is timed again,
+                the candidate and the best kernel side by side."""
+                t = table.get(kernel, float("inf"))
+                if t <= 1.05 * best:
+                    return True, True
+                if t > 1.5 * best or kernel == best_k:
+                    return False, False
+                own = plan is None
+                if own:
+                    plan = Plan(rp, col, val, n=A.n, selector=kernel)
+                bp = Plan(rp, col, val, n=A.n, selector=best_k)
+                tc, tb = [], []
+                for _ in range(3):
+                    tc.append(time_run(plan, r["x"], r["py"]))
+                    tb.append(time_run(bp, r["x"], r["py"]))
+                bp.close()
+                if own:
+                    plan.close()
+                return False, bool(np.median(tc) <= 1.05 * np.median(tb))
+
+            r["rec"]["hit_table"], r["rec"]["hit"] = judged(r["rec"]["kernel"], r["tuned"])
+            r["rec"]["rules_hit_table"], r["rec"]["rules_hit"] = judged(r["rec"]["rules_kernel"])
             if study is not None and r["rec"].get("plain_ms"):
                 row = {}
                 order = (("all", False), ("staged", True))
@@ -497,7 +520,10 @@ def main():
             del rp, col, val
         hit_rate = hits / len(recs)
         rules_hit_rate = sum(r["rec"]["rules_hit"] for r in recs) / len(recs)
-        log(f"hit rate {hit_rate:.3f} (rules {rules_hit_rate:.3f}), geomean slowdown "
+        hit_rate_table = sum(r["rec"]["hit_table"] for r in recs) / len(recs)
+        rules_hit_rate_table = sum(r["rec"]["rules_hit_table"] for r in recs) / len(recs)
+        log(f"hit rate {hit_rate:.3f} (rules {rules_hit_rate:.3f}); against the exhaustive table "
+            f"alone {hit_rate_table:.3f} (rules {rules_hit_rate_table:.3f}); geomean slowdown "
             f"{np.exp(np.mean(np.log(slow))):.4f}")
 
     # ---- CPU oracle baseline on a bounded sample of the same workload
@@ -614,6 +640,9 @@ def main():
         "tuned_vs_plain": round(speedup, 4) if speedup else None,
         "hit_rate": round(hit_rate, 4) if hit_rate is not None else None,
         "rules_hit_rate": round(rules_hit_rate, 4) if hit_rate is not None else None,
+        "hit_rate_table_only": round(hit_rate_table, 4) if hit_rate is not None else None,
+        "rules_hit_rate_table_only":
+            round(rules_hit_rate_table, 4) if hit_rate is not None else None,
         "plan_cost_plain_csr_units_median": round(float(np.median(plan_units)), 2) if plan_units else None,
         "plan_cost_untuned_plain_csr_units_median":
             round(float(np.median(select_units)), 2) if select_units else None,
