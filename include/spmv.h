@@ -131,10 +131,14 @@ typedef struct {
                                    one row per lane; 0 = default (1 from
                                    2^20 rows on, 2 below)                  */
     int32_t bcsr_lanes;         /* BCSR: lanes per block row, a power of two
-                                   in [1, 64] (0 = default: the mean blocks
+                                   in [1, 64].  float32: one block per lane
+                                   at a time (0 = default: the mean blocks
                                    per block row rounded up to a power of
-                                   two; float64 widens it as the 1e-12 bound
-                                   needs)                                   */
+                                   two).  float64: 8 lanes read a block
+                                   together, so lanes / 8 blocks of a row
+                                   are read at once (values below 8 are
+                                   raised to 8; 0 = default 8, widened as
+                                   the 1e-12 bound needs)                  */
 } spmv_params;
 
 typedef struct spmv_selector_s *spmv_selector_t;

@@ -318,7 +318,7 @@ void panel_geometry(const spmv_features &F, int elt, const spmv_params &p, int64
 // is reused through the cache; the CSR kernels revisit partly consumed cache
 // lines and random gathers from a large x do better with the default policy
 // (measured on gfx950).
-spmv_params resolve_params(int kernel, spmv_params p, const spmv_features &F) {
+spmv_params resolve_params(int kernel, spmv_params p, const spmv_features &F, int elt) {
     if (p.stream_nt == 0) {
         bool dense_stream = kernel == SPMV_K_ELL || kernel == SPMV_K_DIA ||
                             kernel == SPMV_K_DIA_DIRECT;
@@ -329,11 +329,17 @@ spmv_params resolve_params(int kernel, spmv_params p, const spmv_features &F) {
     // slower on smaller matrices)
     if (p.wide_loads == 0) p.wide_loads = F.m >= (1 << 20) ? 1 : 2;
     if (p.bcsr_lanes == 0) {
-        // about one block per lane for a block row of mean length (measured
-        // best on dense 4x4 block matrices)
         const int64_t mb = std::max<int64_t>(1, (F.m + 3) / 4);
         const int64_t avg = (std::max<int64_t>(0, F.blocks4) + mb - 1) / mb;
-        p.bcsr_lanes = std::max(1, std::min(64, pow2_ceil(std::max<int64_t>(1, avg))));
+        const int per_row = std::max(1, std::min(64, pow2_ceil(std::max<int64_t>(1, avg))));
+        if (elt == 8)
+            // one block of the row at a time by its 8 lanes once the block
+            // rows alone fill the GPU (measured best on dense 4x4 block
+            // matrices from 2^16 block rows); below, a lane group per block
+            p.bcsr_lanes = mb >= (1 << 16) ? 8 : std::min(64, 8 * per_row);
+        else
+            // about one block per lane for a block row of mean length
+            p.bcsr_lanes = per_row;
     }
     return p;
 }
@@ -402,6 +408,15 @@ spmv_status check_params(const spmv_params &p) {
     return SPMV_OK;
 }
 
+// Longest float64 summation chain of a BCSR lane with L lanes per block
+// row (the float64 kernel: 8 lanes per block): 2 products per block for
+// ceil(4 max_RD / G) blocks (G = L / 8 lane groups), then 1 + log2 G
+// shuffled additions.
+int64_t bcsr_f64_depth(int64_t max_rd, int L) {
+    const int64_t G = std::max(1, L / 8);
+    return 2 * ((4 * max_rd + G - 1) / G) + 1 + ilog2((int)G);
+}
+
 // Longest COO chain: a row spans at most this many chunks in float64.
 constexpr int64_t kCooMaxChunksPerRow = 3000;
 constexpr int64_t kSplitSegment = 512 * 1024;   // entries per split segment (512 threads)
@@ -441,14 +456,15 @@ uint32_t feasible_mask(const spmv_features &F, int dtype, int64_t m_pad, uint64_
     {
         // BCSR 4x4: the zero-fill rule (Section 2.3) applied to blocks --
         // stored block slots at most 20x the entries (fill >= 5%) -- plus the
-        // storage cap; float64 chains: a lane adds at most
-        // 4 ceil(4 max_RD / L) products per row, L <= 64.
+        // storage cap; float64 chains: with 64 lanes (8 groups of 8) a lane
+        // adds 2 ceil(4 max_RD / 8) products (a block row has at most
+        // 4 max_RD blocks) and 4 shuffled partial sums.
         const uint64_t nb = (uint64_t)std::max<int64_t>(0, F.blocks4);
         const uint64_t mb = (uint64_t)(F.m + 3) / 4;
         const uint64_t bytes = nb * (uint64_t)(16 * elt + 6) + 4u * (mb + 1);
         bool ok = nb > 0 && 16u * nb <= 20u * (uint64_t)F.nnz && bytes <= cap &&
                   16u * nb < (1ull << 31);
-        if (f64 && 4 * ((4 * F.max_rd + 63) / 64) + 6 > kFp64MaxDepth) ok = false;
+        if (f64 && bcsr_f64_depth(F.max_rd, 64) > kFp64MaxDepth) ok = false;
         if (ok) mask |= 1u << SPMV_K_BCSR;
     }
     {
@@ -535,7 +551,7 @@ void raw_features(const spmv_features &F, int dtype, float out[12]) {
 
 spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W, int kernel,
                           const spmv_params &prm_in, hipStream_t s, Variant &V) {
-    const spmv_params prm = resolve_params(kernel, prm_in, F);
+    const spmv_params prm = resolve_params(kernel, prm_in, F, P.elt);
     V.kernel = kernel;
     V.prm = prm;
     const int64_t m = P.m, n = P.n, nnz = P.nnz;
@@ -568,8 +584,8 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
                                     V.bpres.as<uint16_t>(), s));
         if (P.dtype == SPMV_F64) {
             // keep every lane's chain within the float64 bound
-            int L = V.prm.bcsr_lanes;
-            while (L < 64 && 4 * ((4 * F.max_rd + L - 1) / L) + ilog2(L) > kFp64MaxDepth) L *= 2;
+            int L = std::max(8, V.prm.bcsr_lanes);
+            while (L < 64 && bcsr_f64_depth(F.max_rd, L) > kFp64MaxDepth) L *= 2;
             V.prm.bcsr_lanes = L;
         }
         SMAT_HIP(hipStreamSynchronize(s));
@@ -946,10 +962,11 @@ std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_
                     }
         break;
     case SPMV_K_BCSR:
-        for (int f : {1, 2, 4})  // lanes at half, equal and twice the default
-            for (int nt : nts) {
+        for (int f : {1, 2, 4, 8})  // float64: 8, 16, 32, 64 lanes; float32:
+            for (int nt : nts) {     // half, equal and twice the default
+                if (dtype != SPMV_F64 && f == 8) continue;
                 spmv_params p = b;
-                p.bcsr_lanes = std::max(1, std::min(64, b.bcsr_lanes * f / 2));
+                p.bcsr_lanes = dtype == SPMV_F64 ? 8 * f : std::max(1, std::min(64, b.bcsr_lanes * f / 2));
                 p.stream_nt = nt;
                 add(p);
             }

@@ -288,11 +288,22 @@ __global__ __launch_bounds__(256) void k_dia_direct(int64_t m, int64_t n, int64_
 }
 
 // ---------------------------------------------------------------- BCSR 4x4
-// A group of L lanes per block row (4 rows); lane l takes blocks l, l+L, ...
-// of its block row.  A block's 16 values (row-major) arrive in 16-byte
-// loads, its 4 x values in one (element-aligned) load away from the last
-// column block; each lane keeps one running sum per row (products of a
+// Two lane mappings, chosen by value type (both measured on gfx950):
+//
+// float32 (k_bcsr): a group of L lanes per block row; lane l takes blocks l,
+// l+L, ... of its block row.  A block's 16 values (row-major) arrive in
+// 16-byte loads, its 4 x values in one (element-aligned) load away from the
+// last column block; each lane keeps one running sum per row (products of a
 // block in column order), and the L lanes' sums are added by xor shuffles.
+//
+// float64 (k_bcsr_coop): a block's 128 bytes are read by 8 lanes together,
+// 16 bytes (half a row) each, so consecutive lanes read consecutive 16-byte
+// pieces and a wave's loads are fully coalesced.  A block row has L lanes
+// (8 <= L <= 64): G = L / 8 groups, group g taking blocks g, g + G, ... of
+// the row.  A lane reads the 2 x values under its piece in one load and
+// keeps one running sum for its row; lanes of the same row (the pair inside
+// a block, then the G groups) are added by xor shuffles in a fixed order.
+//
 // Zero-filled positions add exact zeros.
 template <typename T, int L, bool NT>
 __global__ __launch_bounds__(256) void k_bcsr(int64_t mb, int64_t m, int64_t n,
@@ -344,6 +355,48 @@ __global__ __launch_bounds__(256) void k_bcsr(int64_t mb, int64_t m, int64_t n,
         for (int rr = 0; rr < 4; ++rr)
             if (4 * R + rr < m) y[4 * R + rr] = (T)acc[rr];
     }
+}
+
+template <int L, bool NT>
+__global__ __launch_bounds__(256) void k_bcsr_coop(int64_t mb, int64_t m, int64_t n,
+                                                   const int32_t *__restrict__ brp,
+                                                   const int32_t *__restrict__ bcol,
+                                                   const double *__restrict__ bval,
+                                                   const double *__restrict__ x,
+                                                   double *__restrict__ y) {
+    constexpr int S = 8;                    // lanes per block, 2 values each
+    constexpr int G = L / S;                // blocks of a row in flight
+    static_assert(L >= S && L <= 64 && (L & (L - 1)) == 0, "lanes per block row");
+    typedef double vec2 __attribute__((ext_vector_type(2)));
+    const int64_t R = (int64_t)blockIdx.x * (blockDim.x / L) + threadIdx.x / L;
+    const int lane = threadIdx.x & (L - 1);
+    const int g = lane / S, j = lane % S;
+    const int row = j / 2;                  // block row of this lane's piece
+    const int cc0 = 2 * (j % 2);            // first column of the piece
+    double acc = 0.0;
+    if (R < mb) {
+        const int32_t kb = brp[R], ke = brp[R + 1];
+        for (int32_t k = kb + g; k < ke; k += G) {
+            const vec2 w = ld<NT>(reinterpret_cast<const vec2 *>(bval + (int64_t)k * 16) + j);
+            const int64_t c0 = (int64_t)ld<NT>(bcol + k) * 4 + cc0;
+            double x0, x1;
+            if (c0 + 2 <= n) {
+                vec2 t;
+                __builtin_memcpy(&t, x + c0, sizeof(t));
+                x0 = t[0];
+                x1 = t[1];
+            } else {
+                x0 = c0 < n ? x[c0] : 0.0;
+                x1 = c0 + 1 < n ? x[c0 + 1] : 0.0;
+            }
+            acc = fma(w[0], x0, acc);
+            acc = fma(w[1], x1, acc);
+        }
+    }
+    acc += __shfl_xor(acc, 1, L);   // the two halves of a block row
+#pragma unroll
+    for (int off = S; off < L; off <<= 1) acc += __shfl_xor(acc, off, L);
+    if (R < mb && g == 0 && cc0 == 0 && 4 * R + row < m) y[4 * R + row] = acc;
 }
 
 // ---------------------------------------------------------------- COO
@@ -632,13 +685,27 @@ spmv_status bcsr_dispatch(int64_t m, int64_t n, const int32_t *brp, const int32_
         set_error("bcsr: lanes must be a power of two in [1, min(64, block)], got %d", lanes);
         return SPMV_EINVAL;
     }
-    const unsigned g = grid_for(mb, block / lanes);
+    if constexpr (sizeof(T) == 8) {
+        if (lanes < 8) lanes = 8;  // a float64 block takes 8 lanes
+        if (lanes > block) {
+            set_error("bcsr: block of %d threads cannot hold %d lanes per block row", block,
+                      lanes);
+            return SPMV_EINVAL;
+        }
+        const unsigned g = grid_for(mb, block / lanes);
+#define L_CASE(L)                                                                          \
+    case L: k_bcsr_coop<L, NT><<<g, block, 0, s>>>(mb, m, n, brp, bcol, bval, x, y); break;
+        switch (lanes) { L_CASE(8) L_CASE(16) L_CASE(32) L_CASE(64) }
+#undef L_CASE
+    } else {
+        const unsigned g = grid_for(mb, block / lanes);
 #define L_CASE(L)                                                                            \
     case L: k_bcsr<T, L, NT><<<g, block, 0, s>>>(mb, m, n, brp, bcol, bval, x, y); break;
-    switch (lanes) {
-        L_CASE(1) L_CASE(2) L_CASE(4) L_CASE(8) L_CASE(16) L_CASE(32) L_CASE(64)
-    }
+        switch (lanes) {
+            L_CASE(1) L_CASE(2) L_CASE(4) L_CASE(8) L_CASE(16) L_CASE(32) L_CASE(64)
+        }
 #undef L_CASE
+    }
     SMAT_LAUNCHED("bcsr");
     return SPMV_OK;
 }

@@ -180,6 +180,7 @@ def test_tiny_tiles_force_every_boundary(dtype):
               S.blocks_g3(np.random.default_rng([48, 1]), 3000)):
         xm = S.uniform_vector(M.n, [48, M.m])
         for prm in ({}, {"bcsr_lanes": 1}, {"bcsr_lanes": 4, "block": 64}, {"bcsr_lanes": 64},
+                    {"bcsr_lanes": 8}, {"bcsr_lanes": 32, "block": 64},
                     {"bcsr_lanes": 16, "stream_nt": 1}):
             for k, y in _run_all(M, dtype, xm, kernels=("bcsr",), params=prm).items():
                 assert_parity(y, M, xm, dtype)
