@@ -128,6 +128,41 @@ struct Scratch {
     double fit[5];
 };
 
+// The scratch zeroed (min_rd at INT_MAX) by one small kernel rather than a
+// copy from pageable host memory.
+__global__ void k_init_scratch(Scratch *d) {
+    unsigned *w = reinterpret_cast<unsigned *>(d);
+    for (unsigned i = threadIdx.x; i < sizeof(Scratch) / sizeof(unsigned); i += blockDim.x) w[i] = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) d->rs.min_rd = INT_MAX;
+}
+
+// The scratch read back into pinned host memory (one block per thread, kept
+// for the process), which the copy engine writes directly; NULL if pinned
+// memory is unavailable (a stack copy is used then).
+Scratch *pinned_scratch() {
+    thread_local Scratch *p = nullptr;
+    thread_local bool tried = false;
+    if (!tried) {
+        tried = true;
+        if (hipHostMalloc(reinterpret_cast<void **>(&p), sizeof(Scratch), hipHostMallocDefault) !=
+            hipSuccess) {
+            p = nullptr;
+            (void)hipGetLastError();
+        }
+    }
+    return p;
+}
+
+spmv_status read_scratch(const Scratch *d, Scratch &h, hipStream_t s) {
+    Scratch *pin = pinned_scratch();
+    Scratch *dst = pin ? pin : &h;
+    SMAT_HIP(hipMemcpyAsync(dst, d, sizeof(Scratch), hipMemcpyDeviceToHost, s));
+    SMAT_HIP(hipStreamSynchronize(s));
+    if (pin) h = *pin;
+    return SPMV_OK;
+}
+
 // Feature extraction in stages, in the order the format search consumes them
 // (Section 6: DIA first, then ELL and CSR, COO last):
 //   rows    validation, row statistics and bandwidth -- everything the ELL
@@ -145,8 +180,8 @@ spmv_status extract_rows(const spmv_csr &A, hipStream_t s, spmv_features &F, Fea
     SMAT_TRY(W.scratch.alloc(sizeof(Scratch)));
     Scratch *d = W.scratch.as<Scratch>();
     Scratch h{};
-    h.rs.min_rd = INT_MAX;
-    SMAT_HIP(hipMemcpyAsync(d, &h, sizeof(h), hipMemcpyHostToDevice, s));
+    k_init_scratch<<<1, 64, 0, s>>>(d);
+    SMAT_LAUNCHED("init_scratch");
     // the row_ptr check, the column checks (with the bandwidth) and the row
     // pass share one synchronisation: the column and row passes stay in
     // bounds whatever row_ptr holds, and their results are only used when
@@ -155,8 +190,7 @@ spmv_status extract_rows(const spmv_csr &A, hipStream_t s, spmv_features &F, Fea
     SMAT_TRY(launch_validate_entries(m, n, nnz, A.row_ptr_dev, A.col_dev, &d->flags2,
                                      &d->es.bandwidth, s));
     SMAT_TRY(launch_row_stats(m, A.row_ptr_dev, &d->rs, s));
-    SMAT_HIP(hipMemcpyAsync(&h, d, sizeof(Scratch), hipMemcpyDeviceToHost, s));
-    SMAT_HIP(hipStreamSynchronize(s));
+    SMAT_TRY(read_scratch(d, h, s));
     if (h.flags) {
         set_error("invalid CSR row_ptr (flags 0x%x: %s%s%s)", h.flags,
                   (h.flags & kBadRowPtr0) ? "row_ptr[0] != 0 " : "",
@@ -220,8 +254,7 @@ spmv_status extract_entries(const spmv_csr &A, hipStream_t s, spmv_features &F, 
                                     census ? W.diag_hist.as<unsigned>() : nullptr, rest, s));
     if (census) SMAT_TRY(launch_diag_stats(m, n, W.diag_hist.as<unsigned>(), &d->ds, s));
     Scratch h{};
-    SMAT_HIP(hipMemcpyAsync(&h, d, sizeof(Scratch), hipMemcpyDeviceToHost, s));
-    SMAT_HIP(hipStreamSynchronize(s));
+    SMAT_TRY(read_scratch(d, h, s));
     if (rest) {
         F.blocks4 = (int64_t)h.es.blocks4;
         F.block_fill = F.blocks4 ? (double)nnz / (16.0 * (double)F.blocks4) : 0.0;
