@@ -116,8 +116,14 @@ struct FeatureWork {
     Dev scratch;   // RowStats + EntryStats + DiagStats + flags + fit sums
     Dev row_hist;
     Dev diag_hist; // m + n - 1 bins; later the diagonal -> slot map
-    bool census = false;
+    bool census = false;       // the census was taken (DIA could be feasible)
+    bool census_done = false;  // the census question is settled
 };
+
+// Matrices with at most this many diagonal bins (m + n - 1) take the census
+// together with the CSR checks, gated on the device by their outcome: one
+// synchronisation less, for a histogram small enough to clear in passing.
+constexpr int64_t kCensusWithChecksBins = int64_t(1) << 22;
 
 struct Scratch {
     RowStats rs;
@@ -175,6 +181,15 @@ spmv_status read_scratch(const Scratch *d, Scratch &h, hipStream_t s) {
 // synchronisation.
 enum : unsigned { kStageCensus = 1, kStageRest = 2 };
 
+void set_census(spmv_features &F, const DiagStats &ds, int64_t m, int64_t nnz, FeatureWork &W) {
+    W.census = true;
+    F.ndiags = (int64_t)ds.ndiags;
+    F.ntdiags = (int64_t)ds.ntrue;
+    F.ntdiags_ratio = F.ndiags ? (double)F.ntdiags / (double)F.ndiags : 0.0;
+    F.er_dia = F.ndiags ? (double)nnz / ((double)F.ndiags * (double)m) : 0.0;
+    F.dia_feasible = (__int128)F.ndiags * m <= (__int128)20 * nnz;
+}
+
 spmv_status extract_rows(const spmv_csr &A, hipStream_t s, spmv_features &F, FeatureWork &W) {
     const int64_t m = A.m, n = A.n, nnz = A.nnz;
     SMAT_TRY(W.scratch.alloc(sizeof(Scratch)));
@@ -190,6 +205,16 @@ spmv_status extract_rows(const spmv_csr &A, hipStream_t s, spmv_features &F, Fea
     SMAT_TRY(launch_validate_entries(m, n, nnz, A.row_ptr_dev, A.col_dev, &d->flags2,
                                      &d->es.bandwidth, s));
     SMAT_TRY(launch_row_stats(m, A.row_ptr_dev, &d->rs, s));
+    // small matrices: the census too, run on the device only if the checks
+    // pass and DIA can still be feasible
+    const bool with_census = nnz > 0 && m + n - 1 <= kCensusWithChecksBins;
+    if (with_census) {
+        SMAT_TRY(W.diag_hist.alloc(sizeof(unsigned) * (size_t)(m + n - 1)));
+        SMAT_HIP(hipMemsetAsync(W.diag_hist.p, 0, W.diag_hist.bytes, s));
+        SMAT_TRY(launch_entry_stats(m, n, nnz, A.row_ptr_dev, A.col_dev, &d->es,
+                                    W.diag_hist.as<unsigned>(), false, s, &d->flags, &d->rs));
+        SMAT_TRY(launch_diag_stats(m, n, W.diag_hist.as<unsigned>(), &d->ds, s));
+    }
     SMAT_TRY(read_scratch(d, h, s));
     if (h.flags) {
         set_error("invalid CSR row_ptr (flags 0x%x: %s%s%s)", h.flags,
@@ -227,6 +252,11 @@ spmv_status extract_rows(const spmv_csr &A, hipStream_t s, spmv_features &F, Fea
     F.blocks4 = -1;
     F.block_fill = -1.0;
     F.R = std::numeric_limits<double>::quiet_NaN();
+    if (with_census) {
+        W.census_done = true;
+        if (F.ell_feasible) set_census(F, h.ds, m, nnz, W);
+        if (!F.dia_feasible) W.diag_hist.release();
+    }
     return SPMV_OK;
 }
 
@@ -244,7 +274,7 @@ spmv_status extract_entries(const spmv_csr &A, hipStream_t s, spmv_features &F, 
     }
     // ---- entry pass: diagonal census (while DIA may still be feasible,
     // since Ndiags >= max_RD) and / or the 4x4 block count
-    const bool census = (what & kStageCensus) && F.ell_feasible && nnz > 0;
+    const bool census = (what & kStageCensus) && !W.census_done && F.ell_feasible && nnz > 0;
     if (census) {
         SMAT_TRY(W.diag_hist.alloc(sizeof(unsigned) * (size_t)(m + n - 1)));
         SMAT_HIP(hipMemsetAsync(W.diag_hist.p, 0, W.diag_hist.bytes, s));
@@ -262,19 +292,15 @@ spmv_status extract_entries(const spmv_csr &A, hipStream_t s, spmv_features &F, 
                                                                      : 0.0;
     }
     if (census) {
-        W.census = true;
-        F.ndiags = (int64_t)h.ds.ndiags;
-        F.ntdiags = (int64_t)h.ds.ntrue;
-        F.ntdiags_ratio = F.ndiags ? (double)F.ntdiags / (double)F.ndiags : 0.0;
-        F.er_dia = F.ndiags ? (double)nnz / ((double)F.ndiags * (double)m) : 0.0;
-        F.dia_feasible = (__int128)F.ndiags * m <= (__int128)20 * nnz;
-    } else if (what & kStageCensus) {
+        set_census(F, h.ds, m, nnz, W);
+    } else if ((what & kStageCensus) && !W.census_done) {
         F.ndiags = -1;
         F.ntdiags = 0;
         F.ntdiags_ratio = 0.0;
         F.er_dia = 0.0;
         F.dia_feasible = 0;
     }
+    if (what & kStageCensus) W.census_done = true;
     if (!keep_census || !F.dia_feasible) W.diag_hist.release();
     W.row_hist.release();
     return SPMV_OK;
@@ -1374,7 +1400,7 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
         // without a possible stop, census and rest share one pass
         if (!may_stop)
             SMAT_TRY(extract_entries(*A, s, F, W, kStageCensus | kStageRest, true));
-        else if (F.ell_feasible && A->nnz > 0)
+        else if (F.ell_feasible && A->nnz > 0 && !W.census_done)
             SMAT_TRY(extract_entries(*A, s, F, W, kStageCensus, true));
         auto t2 = std::chrono::steady_clock::now();
         I.t_validate_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();

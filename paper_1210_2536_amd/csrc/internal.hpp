@@ -65,7 +65,8 @@ spmv_status launch_powerlaw_fit(const unsigned int *hist, int max_rd, int64_t m,
                                 hipStream_t s);
 spmv_status launch_entry_stats(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
                                const int32_t *col, EntryStats *out, unsigned int *diag_hist,
-                               bool blocks, hipStream_t s);
+                               bool blocks, hipStream_t s, const uint32_t *gate = nullptr,
+                               const RowStats *gate_rs = nullptr);
 spmv_status launch_diag_stats(int64_t m, int64_t n, const unsigned int *diag_hist, DiagStats *out,
                               hipStream_t s);
 spmv_status launch_diag_compact(int64_t m, int64_t n, unsigned int *diag_hist, int32_t *offsets,

@@ -215,10 +215,19 @@ __device__ __forceinline__ bool row_has_block(const int32_t *__restrict__ rp,
 
 // BLOCKS: count the nonempty aligned 4x4 blocks (a few binary searches per
 // block start); with a histogram, take the diagonal census.  Either or both.
+//
+// A census launched together with the CSR checks (gate, gate_rs non-NULL)
+// runs only when both checks passed (gate[0] | gate[1] == 0) and the
+// zero-fill bound still allows DIA (max_RD M <= 20 NNZ); the checks and the
+// row pass precede it on the stream.  Every thread reads the same words, so
+// a workgroup leaves as a whole.
 template <bool BLOCKS>
 __global__ void k_entry_stats(int64_t m, int64_t n, int64_t nnz, const int32_t *__restrict__ rp,
                               const int32_t *__restrict__ col, EntryStats *out,
-                              unsigned int *diag_hist) {
+                              unsigned int *diag_hist, const uint32_t *gate,
+                              const RowStats *gate_rs) {
+    if (gate && (gate[0] | gate[1])) return;
+    if (gate_rs && (int64_t)gate_rs->max_rd * m > 20 * nnz) return;
     __shared__ int hkey[kHash];
     __shared__ unsigned int hcnt[kHash];
     __shared__ unsigned long long lds_u[kBlock / kWave];
@@ -419,14 +428,17 @@ spmv_status launch_powerlaw_fit(const unsigned int *hist, int max_rd, int64_t m,
 
 spmv_status launch_entry_stats(int64_t m, int64_t n, int64_t nnz, const int32_t *rp,
                                const int32_t *col, EntryStats *out, unsigned int *diag_hist,
-                               bool blocks, hipStream_t s) {
+                               bool blocks, hipStream_t s, const uint32_t *gate,
+                               const RowStats *gate_rs) {
     if (nnz == 0) return SPMV_OK;
     int64_t threads = (nnz + kEntryRun - 1) / kEntryRun;
     const unsigned g = grid_for(threads, kBlock, INT_MAX);
     if (blocks)
-        k_entry_stats<true><<<g, kBlock, 0, s>>>(m, n, nnz, rp, col, out, diag_hist);
+        k_entry_stats<true><<<g, kBlock, 0, s>>>(m, n, nnz, rp, col, out, diag_hist, gate,
+                                                 gate_rs);
     else
-        k_entry_stats<false><<<g, kBlock, 0, s>>>(m, n, nnz, rp, col, out, diag_hist);
+        k_entry_stats<false><<<g, kBlock, 0, s>>>(m, n, nnz, rp, col, out, diag_hist, gate,
+                                                  gate_rs);
     SMAT_LAUNCHED("entry_stats");
     return SPMV_OK;
 }
