@@ -176,7 +176,7 @@ def main():
                        tune_ms=info["t_tune_ms"] if k == 0 else 0.0,
                        bytes=workloads.plan_bytes(pi), confidence=pi["confidence"],
                        n_measured=pi["n_measured"], params=pi["params"],
-                       feature_stage=pi["feature_stage"])
+                       feature_stage=pi["feature_stage"], long_lanes=pi["long_lanes"])
             recs.append(dict(rec=rec, tuned=part, plain=plain if k == 0 else None, x=x,
                              y=y[r0:r0 + part.m], py=y, owner=tuned))
         del rp, col, val
@@ -256,10 +256,13 @@ def main():
         p, k = rec["params"], rec["kernel"]
         t = "double" if rec["dtype"] == "float64" else "float"
         nt = "true" if p["stream_nt"] == 1 else "false"
+        # long rows through LDS: the binned launch without them, then theirs
+        long = f" + k_long_rows_lds<{rec['long_lanes']}>" if rec.get("long_lanes") else ""
+        rest = "_rest" if long else ""
         if k == "csr_vector":
             return f"k_csr_vector<{t}, {p['vector_lanes']}, {nt}>"
         if k == "csr_adaptive":
-            return f"k_csr_adaptive<{t}, {nt}>"
+            return f"k_csr_adaptive{rest}<{t}, {nt}>{long}"
         v = (16 // (8 if t == "double" else 4)) if p["wide_loads"] == 1 else 1
         if k == "ell":
             return f"k_ell<{t}, {p['ell_unroll']}, {nt}, {v}>"
@@ -269,11 +272,13 @@ def main():
         if k == "coo":
             return f"k_coo<{t}, {nt}> + k_coo_fixup<{t}>"
         if k == "bcsr":
+            if t == "double":   # 8 lanes per block
+                return f"k_bcsr_coop<{p['bcsr_lanes']}, {nt}>"
             return f"k_bcsr<{t}, {p['bcsr_lanes']}, {nt}>"
         if k == "csr_panel":
             if p["panel_xcd"] != 2:
-                return f"k_csr_panel_xcd<{t}, {nt}> + k_panel_reduce<{t}>"
-            return f"k_csr_panel<{t}, {nt}, false|true>"
+                return f"k_csr_panel_xcd{rest}<{t}, {nt}> + k_panel_reduce{rest}<{t}>{long}"
+            return f"k_csr_panel{rest}<{t}, {nt}, false|true>{long}"
         return f"k_csr_scalar<{t}>"
 
     sym_time = {}

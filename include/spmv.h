@@ -139,6 +139,15 @@ typedef struct {
                                    are read at once (values below 8 are
                                    raised to 8; 0 = default 8, widened as
                                    the 1e-12 bound needs)                  */
+    int32_t long_lds;           /* CSR_ADAPTIVE and CSR_PANEL, float64: 1 =
+                                   the rows of the longest bin (a workgroup
+                                   each) leave the binned launch for a kernel
+                                   that streams x through LDS in column
+                                   chunks, 16-32 such rows per workgroup of
+                                   1024 threads; 2 = off; 0 = default (on
+                                   from 4096 such rows).  Off in float32 and
+                                   for rows too long for the 1e-12 bound
+                                   with 64 lanes per row                   */
 } spmv_params;
 
 typedef struct spmv_selector_s *spmv_selector_t;
@@ -271,6 +280,9 @@ typedef struct {
                                            the all-ones probe left twice the
                                            accuracy bound of the starting
                                            point's (0 when all agree)      */
+    int32_t long_lanes;                 /* params.long_lds in effect: lanes per
+                                           long row (32 or 64), else 0      */
+    int64_t long_rows;                  /* rows taken by that kernel        */
 } spmv_plan_info;
 
 typedef struct spmv_plan_s *spmv_plan_t;

@@ -417,6 +417,7 @@ void merge_params(spmv_params &p, const spmv_params &u) {
     if (u.panel_xcd > 0) p.panel_xcd = u.panel_xcd;
     if (u.wide_loads > 0) p.wide_loads = u.wide_loads;
     if (u.bcsr_lanes > 0) p.bcsr_lanes = u.bcsr_lanes;
+    if (u.long_lds > 0) p.long_lds = u.long_lds;
 }
 
 spmv_status check_params(const spmv_params &p) {
@@ -458,6 +459,10 @@ spmv_status check_params(const spmv_params &p) {
     }
     if (p.wide_loads < 0 || p.wide_loads > 2) {
         set_error("params.wide_loads must be 0 (default), 1 (on) or 2 (off)");
+        return SPMV_EINVAL;
+    }
+    if (p.long_lds < 0 || p.long_lds > 2) {
+        set_error("params.long_lds must be 0 (default), 1 (on) or 2 (off)");
         return SPMV_EINVAL;
     }
     if (p.bcsr_lanes != 0 && !(pow2(p.bcsr_lanes) && p.bcsr_lanes <= 64)) {
@@ -815,6 +820,58 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
             SMAT_HIP(hipStreamSynchronize(s));
         }
         V.bin_scratch.release();
+        // float64: the longest bin (a workgroup per row) leaves the binned
+        // launch for the kernel that streams x through LDS, when its rows
+        // are many (default) and short enough for the float64 chain bound
+        {
+            const int64_t n7 = (int64_t)V.bin_off[8] - V.bin_off[7];
+            int ll = prm.long_lds ? prm.long_lds : (P.dtype == SPMV_F64 && n7 >= 4096 ? 1 : 2);
+            int tpr = n7 >= 8192 ? 32 : 64;
+            if (ll == 1 && P.dtype == SPMV_F64 &&
+                (F.max_rd + tpr - 1) / tpr + ilog2(tpr) > kFp64MaxDepth)
+                tpr = 64;
+            if (P.dtype != SPMV_F64 || n7 == 0 ||
+                (F.max_rd + tpr - 1) / tpr + ilog2(tpr) > kFp64MaxDepth)
+                ll = 2;
+            V.prm.long_lds = ll;
+            if (ll == 1) {
+                SMAT_TRY(long_rows_lds_prepare());
+                V.long_tpr = tpr;
+                V.n_long = n7;
+                // the long rows longest first, so that the rows of one
+                // workgroup (which waits for its longest) are alike
+                {
+                    Dev be;
+                    SMAT_TRY(be.alloc(sizeof(int64_t) * 2 * (size_t)n7));
+                    const int32_t *r7 = V.bin_rows.as<int32_t>() + V.bin_off[7];
+                    k_gather_rowptr<<<(unsigned)((n7 + 255) / 256), 256, 0, s>>>(
+                        n7, r7, P.rp.as<int32_t>(), be.as<int64_t>());
+                    SMAT_LAUNCHED("gather_rowptr");
+                    std::vector<int64_t> h(2 * (size_t)n7);
+                    std::vector<int32_t> rows(n7);
+                    SMAT_HIP(hipMemcpyAsync(h.data(), be.p, sizeof(int64_t) * 2 * n7,
+                                            hipMemcpyDeviceToHost, s));
+                    SMAT_HIP(hipMemcpyAsync(rows.data(), r7, sizeof(int32_t) * n7,
+                                            hipMemcpyDeviceToHost, s));
+                    SMAT_HIP(hipStreamSynchronize(s));
+                    std::vector<int64_t> ord(n7);
+                    for (int64_t i = 0; i < n7; ++i) ord[i] = i;
+                    std::stable_sort(ord.begin(), ord.end(), [&](int64_t a, int64_t b) {
+                        return h[2 * a + 1] - h[2 * a] > h[2 * b + 1] - h[2 * b];
+                    });
+                    std::vector<int32_t> sorted(n7);
+                    for (int64_t i = 0; i < n7; ++i) sorted[i] = rows[ord[i]];
+                    SMAT_TRY(V.long_rows.alloc(sizeof(int32_t) * (size_t)n7));
+                    SMAT_HIP(hipMemcpyAsync(V.long_rows.p, sorted.data(), sizeof(int32_t) * n7,
+                                            hipMemcpyHostToDevice, s));
+                    SMAT_HIP(hipStreamSynchronize(s));
+                }
+                const unsigned b7 = V.alaunch.first[1];  // workgroups of bin 7
+                V.arest = V.alaunch;
+                V.arest.first[0] = 0;
+                for (int q = 1; q < 9; ++q) V.arest.first[q] = V.alaunch.first[q] - b7;
+            }
+        }
         if (panels) {
             if (ns > 0) {
                 set_error("column panels cannot hold rows longer than %lld entries",
@@ -865,19 +922,35 @@ spmv_status run_variant(const spmv_plan_s &P, const Variant &V, const void *x, v
         return run_csr_vector(elt, nt, V.prm.vector_lanes, m, P.rp.as<int32_t>(),
                               P.col.as<int32_t>(), P.val.p, x, y, V.prm.block, s);
     case SPMV_K_CSR_ADAPTIVE: {
-        SMAT_TRY(run_csr_adaptive(elt, nt, V.alaunch, V.bin_rows.as<int32_t>(),
-                                  P.rp.as<int32_t>(), P.col.as<int32_t>(), P.val.p, x, y, s));
+        SMAT_TRY(run_csr_adaptive(elt, nt, V.long_tpr != 0, V.long_tpr ? V.arest : V.alaunch,
+                                  V.bin_rows.as<int32_t>(), P.rp.as<int32_t>(),
+                                  P.col.as<int32_t>(), P.val.p, x, y, s));
         if (V.nsplit_rows)
             SMAT_TRY(run_csr_split(elt, V.nsplit_segs, V.split_segs.as<int64_t>(),
                                    V.split_partials.as<double>(), V.nsplit_rows,
                                    V.split_begin.as<int64_t>(), V.split_rows.as<int32_t>(),
                                    P.col.as<int32_t>(), P.val.p, x, y, s));
+        if (V.long_tpr)
+            SMAT_TRY(run_long_rows_lds(V.long_tpr, V.n_long, V.long_rows.as<int32_t>(),
+                                       P.rp.as<int32_t>(), P.col.as<int32_t>(),
+                                       P.val.as<double>(), (const double *)x, P.n, (double *)y,
+                                       s));
         return SPMV_OK;
     }
-    case SPMV_K_CSR_PANEL:
-        return run_csr_panels(elt, nt, V.alaunch, V.bin_rows.as<int32_t>(), V.P, m,
-                              V.prow.as<int32_t>(), V.pcol.as<int32_t>(), V.pval.p, x, y,
-                              V.prm.panel_xcd != 2 ? V.ppart.p : nullptr, s);
+    case SPMV_K_CSR_PANEL: {
+        const int64_t lo = V.long_tpr ? V.alaunch.row_begin[7] : 0;
+        const int64_t hi = V.long_tpr ? V.alaunch.row_begin[8] : 0;
+        SMAT_TRY(run_csr_panels(elt, nt, V.long_tpr ? V.arest : V.alaunch,
+                                V.bin_rows.as<int32_t>(), V.P, m, V.prow.as<int32_t>(),
+                                V.pcol.as<int32_t>(), V.pval.p, x, y,
+                                V.prm.panel_xcd != 2 ? V.ppart.p : nullptr, lo, hi, s));
+        if (V.long_tpr)
+            SMAT_TRY(run_long_rows_lds(V.long_tpr, V.n_long, V.long_rows.as<int32_t>(),
+                                       P.rp.as<int32_t>(), P.col.as<int32_t>(),
+                                       P.val.as<double>(), (const double *)x, P.n, (double *)y,
+                                       s));
+        return SPMV_OK;
+    }
     case SPMV_K_BCSR:
         return run_bcsr(elt, nt, m, P.n, V.brp.as<int32_t>(), V.bcol.as<int32_t>(), V.bval.p, x,
                         y, V.prm.bcsr_lanes, std::min(V.prm.block, 256), s);
@@ -976,12 +1049,15 @@ std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_
         break;
     case SPMV_K_CSR_ADAPTIVE:
         for (int rpl : {1, 2, 4})
-            for (int nt : nts) {
-                spmv_params p = b;
-                p.adaptive_rows_per_lane = rpl;
-                p.stream_nt = nt;
-                add(p);
-            }
+            for (int nt : nts)
+                for (int ll : {1, 2}) {  // long rows through LDS (float64) or not
+                    if (ll == 1 && dtype != SPMV_F64) continue;
+                    spmv_params p = b;
+                    p.adaptive_rows_per_lane = rpl;
+                    p.stream_nt = nt;
+                    p.long_lds = ll;
+                    add(p);
+                }
         break;
     case SPMV_K_ELL:
         for (int u : {2, 4})
@@ -1045,10 +1121,13 @@ std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_
                 if (std::find(seen.begin(), seen.end(), std::make_pair(mode, P)) != seen.end())
                     continue;
                 seen.push_back({mode, P});
-                for (int nt : nts) {
-                    p.stream_nt = nt;
-                    add(p);
-                }
+                for (int nt : nts)
+                    for (int ll : {1, 2}) {  // long rows through LDS (float64) or not
+                        if (ll == 1 && dtype != SPMV_F64) continue;
+                        p.stream_nt = nt;
+                        p.long_lds = ll;
+                        add(p);
+                    }
             }
         break;
     }
@@ -1143,9 +1222,10 @@ spmv_status autotune_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork
     return SPMV_OK;
 }
 
-bool needs_csr(int kernel) {
-    return kernel == SPMV_K_CSR_SCALAR || kernel == SPMV_K_CSR_VECTOR ||
-           kernel == SPMV_K_CSR_ADAPTIVE || kernel == SPMV_K_COO;
+bool needs_csr(const Variant &V) {
+    const int k = V.kernel;
+    return k == SPMV_K_CSR_SCALAR || k == SPMV_K_CSR_VECTOR || k == SPMV_K_CSR_ADAPTIVE ||
+           k == SPMV_K_COO || (k == SPMV_K_CSR_PANEL && V.long_tpr);  // long rows read the CSR
 }
 
 }  // namespace
@@ -1608,7 +1688,7 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
     }
     SMAT_HIP(hipStreamSynchronize(s));
     W.diag_hist.release();
-    if (!needs_csr(chosen)) {
+    if (!needs_csr(*P->var)) {
         P->rp.release();
         P->col.release();
         P->val.release();
@@ -1622,6 +1702,8 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
                : chosen == SPMV_K_BCSR         ? SPMV_FMT_BCSR
                                                : SPMV_FMT_DIA;
     I.bcsr_blocks = P->var->nblocks;
+    I.long_lanes = P->var->long_tpr;
+    I.long_rows = P->var->n_long;
     I.params = P->var->prm;
     I.ell_width = P->var->K;
     I.dia_ndiags = P->var->D;

@@ -298,8 +298,9 @@ extern "C" spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplan
             break;
         case SPMV_K_CSR_ADAPTIVE:
             // one work item per workgroup of the level's binned launch; rows
-            // split into segments need their own kernels
-            d.kind = V.nsplit_rows > 0 ? -1 : LK_ADAPTIVE;
+            // split into segments or long rows through LDS need their own
+            // kernels
+            d.kind = (V.nsplit_rows > 0 || V.long_tpr) ? -1 : LK_ADAPTIVE;
             d.alaunch = V.alaunch;
             d.rows = V.bin_rows.as<int32_t>();
             d.tile_rows = 1;

@@ -138,15 +138,25 @@ struct AdaptiveLaunch {
     unsigned row_begin[9];
     int lane_shift;   // column panels: lane width of bin b is 2^max(0, b - shift)
 };
-spmv_status run_csr_adaptive(int elt, bool nt, const AdaptiveLaunch &a, const int32_t *rows,
-                             const int32_t *rp, const int32_t *col, const void *val,
-                             const void *x, void *y, hipStream_t s);
+// rest: the launch geometry leaves out the longest bin (another kernel
+// takes those rows); launched under its own kernel name.
+spmv_status run_csr_adaptive(int elt, bool nt, bool rest, const AdaptiveLaunch &a,
+                             const int32_t *rows, const int32_t *rp, const int32_t *col,
+                             const void *val, const void *x, void *y, hipStream_t s);
 // Column panels; prow is P x (m+1) position-indexed segment starts.  With
 // `partial` (P x m values) all panels run in one launch, one per XCD, and a
 // second kernel adds the partials; without it, one launch per panel.
 spmv_status run_csr_panels(int elt, bool nt, const AdaptiveLaunch &a, const int32_t *rows, int P,
                            int64_t m, const int32_t *prow, const int32_t *pcol, const void *pval,
-                           const void *x, void *y, void *partial, hipStream_t s);
+                           const void *x, void *y, void *partial, int64_t skip_lo,
+                           int64_t skip_hi, hipStream_t s);
+// float64 long rows (the binned order's longest bin) with x streamed through
+// LDS; tpr (32 or 64) lanes per row.  prepare() raises the kernels' dynamic
+// LDS limit (call before the first launch, outside graph capture).
+spmv_status long_rows_lds_prepare();
+spmv_status run_long_rows_lds(int tpr, int64_t nrows, const int32_t *rows, const int32_t *rp,
+                              const int32_t *col, const double *val, const double *x, int64_t n,
+                              double *y, hipStream_t s);
 // Build column panels of width w from a CSR matrix whose rows are visited in
 // the binned order `rows`.  cnt: P*(m+1) ints; prow: P*(m+1)+1 ints; inv: m
 // ints; scan: P*(m+1)/4096+1 unsigned.

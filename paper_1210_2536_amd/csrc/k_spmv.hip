@@ -72,6 +72,18 @@ __global__ __launch_bounds__(kAdaptBlock) void k_csr_adaptive(AdaptiveLaunch a,
     adaptive_block<T, NT>(a, blockIdx.x, rows, rp, col, val, x, y, part);
 }
 
+// The same launch without the longest bin, whose rows another kernel takes
+// (the launch geometry has it empty); its own name keeps the two launch
+// forms apart in kernel traces.  Likewise the *_rest panel kernels below.
+template <typename T, bool NT>
+__global__ __launch_bounds__(kAdaptBlock) void k_csr_adaptive_rest(
+    AdaptiveLaunch a, const int32_t *__restrict__ rows, const int32_t *__restrict__ rp,
+    const int32_t *__restrict__ col, const T *__restrict__ val, const T *__restrict__ x,
+    T *__restrict__ y) {
+    __shared__ double part[kAdaptBlock / kWave];
+    adaptive_block<T, NT>(a, blockIdx.x, rows, rp, col, val, x, y, part);
+}
+
 // ---------------------------------------------------------------- CSR panels
 // Cache blocking of x for matrices whose columns are spread over an x too
 // large for L2: the columns are cut into P panels whose slice of x fits in
@@ -158,6 +170,15 @@ __global__ __launch_bounds__(kAdaptBlock) void k_csr_panel(AdaptiveLaunch a,
     panel_block<T, NT, ACC ? kOutAdd : kOutStore>(a, blockIdx.x, rows, prow, col, val, x, y, part);
 }
 
+template <typename T, bool NT, bool ACC>
+__global__ __launch_bounds__(kAdaptBlock) void k_csr_panel_rest(
+    AdaptiveLaunch a, const int32_t *__restrict__ rows, const int32_t *__restrict__ prow,
+    const int32_t *__restrict__ col, const T *__restrict__ val, const T *__restrict__ x,
+    T *__restrict__ y) {
+    __shared__ double part[kAdaptBlock / kWave];
+    panel_block<T, NT, ACC ? kOutAdd : kOutStore>(a, blockIdx.x, rows, prow, col, val, x, y, part);
+}
+
 // All P = 8 G panels in one launch.  Workgroups are dispatched to the eight
 // XCDs in turn, so workgroup w runs on XCD w mod 8; it serves panel
 // (w mod 8) + 8 g, where g = w / (8 nblk) is the group of 8 panels the launch
@@ -167,7 +188,22 @@ __global__ __launch_bounds__(kAdaptBlock) void k_csr_panel(AdaptiveLaunch a,
 // Each panel writes its own partial vector; k_panel_reduce adds them in
 // panel order.
 template <typename T, bool NT>
-__global__ __launch_bounds__(kAdaptBlock) void k_csr_panel_xcd(AdaptiveLaunch a, int P, int64_t m,
+__device__ __forceinline__ void panel_xcd_block(const AdaptiveLaunch &a, int64_t m,
+                                                const int32_t *__restrict__ rows,
+                                                const int32_t *__restrict__ prow,
+                                                const int32_t *__restrict__ col,
+                                                const T *__restrict__ val, const T *__restrict__ x,
+                                                T *__restrict__ partial, double *part) {
+    const unsigned nblk = a.first[8];
+    const unsigned w = blockIdx.x;
+    const int panel = (int)(w % 8u + 8u * (w / (8u * nblk)));
+    const unsigned bid = (w / 8u) % nblk;
+    panel_block<T, NT, kOutPosition>(a, bid, rows, prow + (int64_t)panel * (m + 1), col, val, x,
+                                     partial + (int64_t)panel * m, part);
+}
+
+template <typename T, bool NT>
+__global__ __launch_bounds__(kAdaptBlock) void k_csr_panel_xcd(AdaptiveLaunch a, int64_t m,
                                                                const int32_t *__restrict__ rows,
                                                                const int32_t *__restrict__ prow,
                                                                const int32_t *__restrict__ col,
@@ -175,13 +211,16 @@ __global__ __launch_bounds__(kAdaptBlock) void k_csr_panel_xcd(AdaptiveLaunch a,
                                                                const T *__restrict__ x,
                                                                T *__restrict__ partial) {
     __shared__ double part[kAdaptBlock / kWave];
-    const unsigned nblk = a.first[8];
-    const unsigned w = blockIdx.x;
-    const int panel = (int)(w % 8u + 8u * (w / (8u * nblk)));
-    const unsigned bid = (w / 8u) % nblk;
-    panel_block<T, NT, kOutPosition>(a, bid, rows, prow + (int64_t)panel * (m + 1), col, val, x,
-                                     partial + (int64_t)panel * m, part);
-    (void)P;
+    panel_xcd_block<T, NT>(a, m, rows, prow, col, val, x, partial, part);
+}
+
+template <typename T, bool NT>
+__global__ __launch_bounds__(kAdaptBlock) void k_csr_panel_xcd_rest(
+    AdaptiveLaunch a, int64_t m, const int32_t *__restrict__ rows, const int32_t *__restrict__ prow,
+    const int32_t *__restrict__ col, const T *__restrict__ val, const T *__restrict__ x,
+    T *__restrict__ partial) {
+    __shared__ double part[kAdaptBlock / kWave];
+    panel_xcd_block<T, NT>(a, m, rows, prow, col, val, x, partial, part);
 }
 
 // y[rows[i]] = sum over panels, in panel order, of the partials at binned
@@ -191,6 +230,19 @@ __global__ void k_panel_reduce(int P, int64_t m, const int32_t *__restrict__ row
                                const T *__restrict__ partial, T *__restrict__ y) {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= m) return;
+    double s = 0.0;
+    for (int p = 0; p < P; ++p) s += (double)partial[(int64_t)p * m + i];
+    y[rows[i]] = (T)s;
+}
+
+// The same, leaving out binned positions [skip_lo, skip_hi) (the longest
+// bin, whose rows another kernel writes).
+template <typename T>
+__global__ void k_panel_reduce_rest(int P, int64_t m, const int32_t *__restrict__ rows,
+                                    const T *__restrict__ partial, T *__restrict__ y,
+                                    int64_t skip_lo, int64_t skip_hi) {
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= m || (i >= skip_lo && i < skip_hi)) return;
     double s = 0.0;
     for (int p = 0; p < P; ++p) s += (double)partial[(int64_t)p * m + i];
     y[rows[i]] = (T)s;
@@ -285,6 +337,88 @@ __global__ __launch_bounds__(256) void k_dia_direct(int64_t m, int64_t n, int64_
                                                     const T *__restrict__ x, T *__restrict__ y) {
     const int64_t r0 = (int64_t)blockIdx.x * blockDim.x * RPT * V;
     dia_tile_direct<T, RPT, NT, V>(r0, m, n, m_pad, D, offs, data, x, y);
+}
+
+// ---------------------------------------------------------------- long rows, x in LDS
+// float64 rows of the longest bin (a workgroup each in the binned kernels)
+// in groups of G = 1024 / TPR per workgroup.  x streams through LDS in
+// column chunks of kLongChunk values with two buffers: the next chunk
+// travels through registers (16-byte loads) while the current one is used,
+// one barrier per chunk.  Lane t of a row takes the row's entries t, t + TPR,
+// t + 2 TPR, ... in that order; since a row's columns ascend, the entries of
+// one chunk come before those of the next, so a lane stops at its first
+// entry past the chunk and resumes there.  Lane sums stay in registers
+// across chunks and are added by xor shuffles at the end.  Rows of TPR lanes
+// keep a float64 chain of length/TPR + log2 TPR.
+constexpr int kLongChunk = 8192;                 // float64 x values per chunk
+constexpr int kLongThreads = 1024;
+constexpr size_t kLongLds = 2u * kLongChunk * sizeof(double);
+
+template <int TPR>
+__global__ __launch_bounds__(kLongThreads) void k_long_rows_lds(
+    int64_t nrows, const int32_t *__restrict__ rows, const int32_t *__restrict__ rp,
+    const int32_t *__restrict__ col, const double *__restrict__ val,
+    const double *__restrict__ x, int64_t n, double *__restrict__ y) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    typedef double d2 __attribute__((ext_vector_type(2)));
+    constexpr int PIECES = kLongChunk / 2;      // 16-byte pieces per chunk
+    constexpr int PER = PIECES / kLongThreads;  // pieces per thread
+    constexpr int U = 4;                        // entries requested ahead
+    constexpr int G = kLongThreads / TPR;
+    static_assert(PIECES % kLongThreads == 0, "chunk must split evenly");
+    const int t = threadIdx.x % TPR;
+    const int64_t ri = (int64_t)blockIdx.x * G + threadIdx.x / TPR;
+    const bool active = ri < nrows;
+    const int32_t row = active ? rows[ri] : 0;
+    int64_t p = active ? (int64_t)rp[row] + t : 0;
+    const int64_t e = active ? (int64_t)rp[row + 1] : 0;
+    double acc = 0.0;
+    const int64_t nchunks = (n + kLongChunk - 1) / kLongChunk;
+    d2 stage[PER];
+    auto fetch = [&](int64_t c) {
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int64_t j0 = c * kLongChunk + 2 * ((int64_t)q * kLongThreads + threadIdx.x);
+            if (j0 + 2 <= n) {
+                __builtin_memcpy(&stage[q], x + j0, sizeof(d2));
+            } else {
+                stage[q][0] = j0 < n ? x[j0] : 0.0;
+                stage[q][1] = 0.0;
+            }
+        }
+    };
+    fetch(0);
+    for (int64_t c = 0; c < nchunks; ++c) {
+        d2 *buf = reinterpret_cast<d2 *>(smem) + (c & 1) * PIECES;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) buf[q * kLongThreads + threadIdx.x] = stage[q];
+        __syncthreads();
+        if (c + 1 < nchunks) fetch(c + 1);
+        const double *xs = reinterpret_cast<const double *>(buf);
+        const int64_t c0 = c * kLongChunk;
+        const int64_t cend = c0 + kLongChunk < n ? c0 + kLongChunk : n;
+        bool go = p < e;
+        while (go) {
+            int32_t cc[U];
+            double vv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) cc[u] = p + u * TPR < e ? col[p + u * TPR] : INT_MAX;
+#pragma unroll
+            for (int u = 0; u < U; ++u) vv[u] = p + u * TPR < e ? val[p + u * TPR] : 0.0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (go && cc[u] < cend) {
+                    acc = fma(vv[u], xs[cc[u] - c0], acc);
+                    p += TPR;
+                } else {
+                    go = false;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int off = TPR / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, TPR);
+    if (t == 0 && active) y[row] = acc;
 }
 
 // ---------------------------------------------------------------- BCSR 4x4
@@ -637,15 +771,21 @@ spmv_status coo_dispatch(int64_t m, int64_t nnz, const int32_t *ri, const int32_
 }
 
 template <typename T>
-spmv_status adaptive_dispatch(bool nt, const AdaptiveLaunch &a, const int32_t *rows,
+spmv_status adaptive_dispatch(bool nt, bool rest, const AdaptiveLaunch &a, const int32_t *rows,
                               const int32_t *rp, const int32_t *col, const T *val, const T *x,
                               T *y, hipStream_t s) {
     const unsigned nblk = a.first[8];
     if (nblk == 0) return SPMV_OK;
-    if (nt)
+    if (rest) {
+        if (nt)
+            k_csr_adaptive_rest<T, true><<<nblk, kAdaptBlock, 0, s>>>(a, rows, rp, col, val, x, y);
+        else
+            k_csr_adaptive_rest<T, false><<<nblk, kAdaptBlock, 0, s>>>(a, rows, rp, col, val, x, y);
+    } else if (nt) {
         k_csr_adaptive<T, true><<<nblk, kAdaptBlock, 0, s>>>(a, rows, rp, col, val, x, y);
-    else
+    } else {
         k_csr_adaptive<T, false><<<nblk, kAdaptBlock, 0, s>>>(a, rows, rp, col, val, x, y);
+    }
     SMAT_LAUNCHED("csr_adaptive");
     return SPMV_OK;
 }
@@ -653,23 +793,43 @@ spmv_status adaptive_dispatch(bool nt, const AdaptiveLaunch &a, const int32_t *r
 template <typename T, bool NT>
 spmv_status panel_dispatch(const AdaptiveLaunch &a, const int32_t *rows, int P, int64_t m,
                            const int32_t *prow, const int32_t *pcol, const T *pval, const T *x,
-                           T *y, T *partial, hipStream_t s) {
+                           T *y, T *partial, int64_t skip_lo, int64_t skip_hi, hipStream_t s) {
     const unsigned nblk = a.first[8];
-    if (nblk == 0) return SPMV_OK;
+    const bool rest = skip_hi > skip_lo;
+    if (nblk == 0 && !rest) return SPMV_OK;
     if (partial) {
-        k_csr_panel_xcd<T, NT><<<nblk * (unsigned)P, kAdaptBlock, 0, s>>>(a, P, m, rows, prow,
-                                                                          pcol, pval, x, partial);
-        SMAT_LAUNCHED("csr_panel_xcd");
-        k_panel_reduce<T><<<grid_for(m, 256), 256, 0, s>>>(P, m, rows, partial, y);
+        if (nblk) {
+            if (rest)
+                k_csr_panel_xcd_rest<T, NT><<<nblk * (unsigned)P, kAdaptBlock, 0, s>>>(
+                    a, m, rows, prow, pcol, pval, x, partial);
+            else
+                k_csr_panel_xcd<T, NT><<<nblk * (unsigned)P, kAdaptBlock, 0, s>>>(
+                    a, m, rows, prow, pcol, pval, x, partial);
+            SMAT_LAUNCHED("csr_panel_xcd");
+        }
+        if (rest)
+            k_panel_reduce_rest<T><<<grid_for(m, 256), 256, 0, s>>>(P, m, rows, partial, y,
+                                                                    skip_lo, skip_hi);
+        else
+            k_panel_reduce<T><<<grid_for(m, 256), 256, 0, s>>>(P, m, rows, partial, y);
         SMAT_LAUNCHED("panel_reduce");
         return SPMV_OK;
     }
+    if (nblk == 0) return SPMV_OK;
     for (int p = 0; p < P; ++p) {
         const int32_t *pr = prow + (int64_t)p * (m + 1);
-        if (p == 0)
+        if (rest) {
+            if (p == 0)
+                k_csr_panel_rest<T, NT, false><<<nblk, kAdaptBlock, 0, s>>>(a, rows, pr, pcol,
+                                                                             pval, x, y);
+            else
+                k_csr_panel_rest<T, NT, true><<<nblk, kAdaptBlock, 0, s>>>(a, rows, pr, pcol, pval,
+                                                                            x, y);
+        } else if (p == 0) {
             k_csr_panel<T, NT, false><<<nblk, kAdaptBlock, 0, s>>>(a, rows, pr, pcol, pval, x, y);
-        else
+        } else {
             k_csr_panel<T, NT, true><<<nblk, kAdaptBlock, 0, s>>>(a, rows, pr, pcol, pval, x, y);
+        }
         SMAT_LAUNCHED("csr_panel");
     }
     return SPMV_OK;
@@ -724,18 +884,21 @@ spmv_status run_bcsr(int elt, bool nt, int64_t m, int64_t n, const int32_t *brp,
 
 spmv_status run_csr_panels(int elt, bool nt, const AdaptiveLaunch &a, const int32_t *rows, int P,
                            int64_t m, const int32_t *prow, const int32_t *pcol, const void *pval,
-                           const void *x, void *y, void *partial, hipStream_t s) {
+                           const void *x, void *y, void *partial, int64_t skip_lo,
+                           int64_t skip_hi, hipStream_t s) {
     if (elt == 8)
         return nt ? panel_dispatch<double, true>(a, rows, P, m, prow, pcol, (const double *)pval,
                                                  (const double *)x, (double *)y,
-                                                 (double *)partial, s)
+                                                 (double *)partial, skip_lo, skip_hi, s)
                   : panel_dispatch<double, false>(a, rows, P, m, prow, pcol, (const double *)pval,
                                                   (const double *)x, (double *)y,
-                                                  (double *)partial, s);
+                                                  (double *)partial, skip_lo, skip_hi, s);
     return nt ? panel_dispatch<float, true>(a, rows, P, m, prow, pcol, (const float *)pval,
-                                            (const float *)x, (float *)y, (float *)partial, s)
+                                            (const float *)x, (float *)y, (float *)partial,
+                                            skip_lo, skip_hi, s)
               : panel_dispatch<float, false>(a, rows, P, m, prow, pcol, (const float *)pval,
-                                             (const float *)x, (float *)y, (float *)partial, s);
+                                             (const float *)x, (float *)y, (float *)partial,
+                                             skip_lo, skip_hi, s);
 }
 
 // Typed entry points: elt selects float (4) or double (8), nt the streaming
@@ -769,14 +932,41 @@ spmv_status run_csr_vector(int elt, bool nt, int lanes, int64_t nrows, const int
 #undef CALL
 }
 
-spmv_status run_csr_adaptive(int elt, bool nt, const AdaptiveLaunch &a, const int32_t *rows,
-                             const int32_t *rp, const int32_t *col, const void *val,
-                             const void *x, void *y, hipStream_t s) {
+spmv_status run_csr_adaptive(int elt, bool nt, bool rest, const AdaptiveLaunch &a,
+                             const int32_t *rows, const int32_t *rp, const int32_t *col,
+                             const void *val, const void *x, void *y, hipStream_t s) {
     if (elt == 8)
-        return adaptive_dispatch<double>(nt, a, rows, rp, col, (const double *)val,
+        return adaptive_dispatch<double>(nt, rest, a, rows, rp, col, (const double *)val,
                                          (const double *)x, (double *)y, s);
-    return adaptive_dispatch<float>(nt, a, rows, rp, col, (const float *)val, (const float *)x,
-                                    (float *)y, s);
+    return adaptive_dispatch<float>(nt, rest, a, rows, rp, col, (const float *)val,
+                                    (const float *)x, (float *)y, s);
+}
+
+spmv_status long_rows_lds_prepare() {
+    // the kernels use more than the default 64 KB of dynamic LDS
+    SMAT_HIP(hipFuncSetAttribute((const void *)k_long_rows_lds<32>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLongLds));
+    SMAT_HIP(hipFuncSetAttribute((const void *)k_long_rows_lds<64>,
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLongLds));
+    return SPMV_OK;
+}
+
+spmv_status run_long_rows_lds(int tpr, int64_t nrows, const int32_t *rows, const int32_t *rp,
+                              const int32_t *col, const double *val, const double *x, int64_t n,
+                              double *y, hipStream_t s) {
+    if (nrows == 0) return SPMV_OK;
+    if (tpr != 32 && tpr != 64) {
+        set_error("long rows: %d lanes per row (32 or 64)", tpr);
+        return SPMV_EINVAL;
+    }
+    const int64_t G = kLongThreads / tpr;
+    const unsigned g = (unsigned)((nrows + G - 1) / G);
+    if (tpr == 32)
+        k_long_rows_lds<32><<<g, kLongThreads, kLongLds, s>>>(nrows, rows, rp, col, val, x, n, y);
+    else
+        k_long_rows_lds<64><<<g, kLongThreads, kLongLds, s>>>(nrows, rows, rp, col, val, x, n, y);
+    SMAT_LAUNCHED("long_rows_lds");
+    return SPMV_OK;
 }
 
 spmv_status run_csr_split(int elt, int64_t nseg, const int64_t *segs, double *partials,

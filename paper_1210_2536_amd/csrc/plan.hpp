@@ -92,6 +92,12 @@ struct Variant {
     int P = 0;
     int64_t panel_w = 0;
     int64_t nsplit_rows = 0, nsplit_segs = 0;
+    // float64 long rows through LDS: lanes per row (0: off), their count,
+    // and the binned launch without them
+    int long_tpr = 0;
+    int64_t n_long = 0;
+    AdaptiveLaunch arest{};
+    Dev long_rows;   // the long rows, longest first
     // BCSR 4x4
     Dev brp, bcol, bval, bpres;
     int64_t nblocks = 0;
@@ -100,7 +106,7 @@ struct Variant {
                eval.bytes + dia_off.bytes + dia_data.bytes + dia_present.bytes + dia_win.bytes +
                bin_rows.bytes + bin_scratch.bytes + split_segs.bytes + split_partials.bytes +
                split_begin.bytes + split_rows.bytes + prow.bytes + pcol.bytes + pval.bytes +
-               ppart.bytes + brp.bytes + bcol.bytes + bval.bytes + bpres.bytes;
+               ppart.bytes + brp.bytes + bcol.bytes + bval.bytes + bpres.bytes + long_rows.bytes;
     }
 };
 

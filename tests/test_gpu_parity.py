@@ -387,3 +387,48 @@ def test_plan_memory_from_the_callers_allocator():
         assert ta.bytes_held() == 0
         assert_parity(q.run(vec(x, np.float64)).cpu().numpy(), A, x, np.float64)
         q.close()
+
+
+def test_long_rows_through_lds():
+    """float64 rows of the longest bin taken by the kernel that streams x
+    through LDS in column chunks (several chunks and a partial one, rows
+    that skip chunks), inside the binned CSR kernel and the column panels,
+    alone and in a persistent batch; float32 ignores the switch."""
+    import torch
+    from paper_1210_2536_amd.spmv import Batch, Plan
+    rng = np.random.default_rng(84)
+    mats = [S.zipf_g2(np.random.default_rng([84, 0]), 20_000),       # 3 chunks of 8192
+            S.uniform_g1(np.random.default_rng([84, 1]), 9000),
+            S.random_csr(rng, 300, 17_000, 0.02),                   # 340 per row, 3 chunks
+            S.random_csr(rng, 50, 5000, 0.3)]                       # one partial chunk
+    for i, A in enumerate(mats):
+        x = np.random.default_rng([85, i]).uniform(-1, 1, A.n)
+        for k, extra in (("csr_adaptive", {}), ("csr_panel", {"panel_kib": 16}),
+                         ("csr_panel", {"panel_kib": 16, "panel_xcd": 2})):
+            for wg in (64, 256):
+                note(f"[long lds] {A.name} {k} {extra} wg_min={wg}")
+                prm = dict(extra, long_lds=1, adaptive_wg_min=wg)
+                rp, col, val = dev(A, np.float64)
+                p = Plan(rp, col, val, n=A.n, selector=k, params=prm)
+                assert p.info()["params"]["long_lds"] in (1, 2)
+                y = p.run(vec(x, np.float64)).cpu().numpy()
+                assert_parity(y, A, x, np.float64)
+                if k == "csr_adaptive":
+                    B = Batch([p], mode=0)
+                    yb = torch.full((A.m,), float("nan"), dtype=torch.float64, device="cuda")
+                    B.run([vec(x, np.float64)], [yb])
+                    torch.cuda.synchronize()
+                    assert np.array_equal(yb.cpu().numpy().view(np.uint8), y.view(np.uint8))
+        rp, col, val = dev(A, np.float32)
+        p = Plan(rp, col, val, n=A.n, selector="csr_adaptive",
+                 params={"long_lds": 1, "adaptive_wg_min": 64})
+        assert p.info()["params"]["long_lds"] == 2
+        assert_parity(p.run(vec(x, np.float32)).cpu().numpy(), A, x, np.float32)
+    # the switch is used where it was asked for
+    A = mats[0]
+    rp, col, val = dev(A, np.float64)
+    on = Plan(rp, col, val, n=A.n, selector="csr_adaptive",
+              params={"long_lds": 1, "adaptive_wg_min": 64}).info()["params"]["long_lds"]
+    off = Plan(rp, col, val, n=A.n, selector="csr_adaptive",
+               params={"long_lds": 2, "adaptive_wg_min": 64}).info()["params"]["long_lds"]
+    assert on == 1 and off == 2
