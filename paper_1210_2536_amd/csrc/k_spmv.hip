@@ -375,6 +375,15 @@ __global__ __launch_bounds__(kLongThreads) void k_long_rows_lds(
     double acc = 0.0;
     const int64_t nchunks = (n + kLongChunk - 1) / kLongChunk;
     d2 stage[PER];
+    // the lane's next U entries (col INT_MAX past the row's end)
+    int32_t cc[U];
+    double vv[U];
+    auto window = [&]() {
+#pragma unroll
+        for (int u = 0; u < U; ++u) cc[u] = p + u * TPR < e ? col[p + u * TPR] : INT_MAX;
+#pragma unroll
+        for (int u = 0; u < U; ++u) vv[u] = p + u * TPR < e ? val[p + u * TPR] : 0.0;
+    };
     auto fetch = [&](int64_t c) {
 #pragma unroll
         for (int q = 0; q < PER; ++q) {
@@ -388,6 +397,7 @@ __global__ __launch_bounds__(kLongThreads) void k_long_rows_lds(
         }
     };
     fetch(0);
+    window();
     for (int64_t c = 0; c < nchunks; ++c) {
         d2 *buf = reinterpret_cast<d2 *>(smem) + (c & 1) * PIECES;
 #pragma unroll
@@ -397,23 +407,22 @@ __global__ __launch_bounds__(kLongThreads) void k_long_rows_lds(
         const double *xs = reinterpret_cast<const double *>(buf);
         const int64_t c0 = c * kLongChunk;
         const int64_t cend = c0 + kLongChunk < n ? c0 + kLongChunk : n;
-        bool go = p < e;
-        while (go) {
-            int32_t cc[U];
-            double vv[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) cc[u] = p + u * TPR < e ? col[p + u * TPR] : INT_MAX;
-#pragma unroll
-            for (int u = 0; u < U; ++u) vv[u] = p + u * TPR < e ? val[p + u * TPR] : 0.0;
+        // columns ascend, so the window's entries inside the chunk are a
+        // prefix of it; the window is refilled after each pass, the last
+        // refill of a chunk being the first window of the next (its loads
+        // are in flight across the barrier)
+        for (;;) {
+            int k = 0;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (go && cc[u] < cend) {
+                if (cc[u] < cend) {
                     acc = fma(vv[u], xs[cc[u] - c0], acc);
-                    p += TPR;
-                } else {
-                    go = false;
+                    ++k;
                 }
             }
+            p += (int64_t)k * TPR;
+            window();
+            if (k < U) break;
         }
     }
 #pragma unroll
