@@ -256,8 +256,12 @@ def main():
         p, k = rec["params"], rec["kernel"]
         t = "double" if rec["dtype"] == "float64" else "float"
         nt = "true" if p["stream_nt"] == 1 else "false"
-        # long rows through LDS: the binned launch without them, then theirs
-        long = f" + k_long_rows_lds<{rec['long_lanes']}>" if rec.get("long_lanes") else ""
+        # long rows with x in LDS (chunks or tiles): the binned launch
+        # without them, then theirs
+        long = ""
+        if rec.get("long_lanes"):
+            long = (f" + k_long_tiles<{t}> + k_long_tiles_reduce<{t}>" if p.get("long_lds") == 3
+                    else f" + k_long_rows_lds<{rec['long_lanes']}>")
         rest = "_rest" if long else ""
         if k == "csr_vector":
             return f"k_csr_vector<{t}, {p['vector_lanes']}, {nt}>"

@@ -139,15 +139,26 @@ typedef struct {
                                    are read at once (values below 8 are
                                    raised to 8; 0 = default 8, widened as
                                    the 1e-12 bound needs)                  */
-    int32_t long_lds;           /* CSR_ADAPTIVE and CSR_PANEL, float64: 1 =
-                                   the rows of the longest bin (a workgroup
-                                   each) leave the binned launch for a kernel
-                                   that streams x through LDS in column
-                                   chunks, 16-32 such rows per workgroup of
-                                   1024 threads; 2 = off; 0 = default (on
-                                   from 4096 such rows).  Off in float32 and
-                                   for rows too long for the 1e-12 bound
-                                   with 64 lanes per row                   */
+    int32_t long_lds;           /* CSR_ADAPTIVE and CSR_PANEL: where the
+                                   rows of the longest bin (a workgroup each
+                                   in the binned launch) go.  1 = x chunks
+                                   (float64 only): a kernel that streams x
+                                   through LDS in column chunks, 16-32 such
+                                   rows per workgroup of 1024 threads;
+                                   3 = tiles (both dtypes): x cut into 64 KB
+                                   panels, one workgroup per (row block,
+                                   panel) holding its panel in LDS, one
+                                   float64 partial per (row, panel), the
+                                   partials added in panel order by a
+                                   second kernel; 2 = binned launch;
+                                   0 = default (tiles from 2048 such rows,
+                                   else 2).  Tiles fall back to chunks
+                                   (float64) or 2 where their partials and
+                                   segment starts would exceed 1/20 of the
+                                   long rows' bytes per run or no lane count
+                                   keeps the 1e-12 bound; chunks fall back
+                                   to 2 in float32 and for rows too long for
+                                   the bound with 64 lanes per row          */
 } spmv_params;
 
 typedef struct spmv_selector_s *spmv_selector_t;
@@ -280,8 +291,10 @@ typedef struct {
                                            the all-ones probe left twice the
                                            accuracy bound of the starting
                                            point's (0 when all agree)      */
-    int32_t long_lanes;                 /* params.long_lds in effect: lanes per
-                                           long row (32 or 64), else 0      */
+    int32_t long_lanes;                 /* params.long_lds 1 or 3 in effect:
+                                           lanes per long row (chunks: 32 or
+                                           64; tiles: the most of any row
+                                           block, 8-64), else 0             */
     int64_t long_rows;                  /* rows taken by that kernel        */
 } spmv_plan_info;
 

@@ -461,8 +461,8 @@ spmv_status check_params(const spmv_params &p) {
         set_error("params.wide_loads must be 0 (default), 1 (on) or 2 (off)");
         return SPMV_EINVAL;
     }
-    if (p.long_lds < 0 || p.long_lds > 2) {
-        set_error("params.long_lds must be 0 (default), 1 (on) or 2 (off)");
+    if (p.long_lds < 0 || p.long_lds > 3) {
+        set_error("params.long_lds must be 0 (default), 1 (x chunks), 2 (off) or 3 (tiles)");
         return SPMV_EINVAL;
     }
     if (p.bcsr_lanes != 0 && !(pow2(p.bcsr_lanes) && p.bcsr_lanes <= 64)) {
@@ -612,6 +612,73 @@ void raw_features(const spmv_features &F, int dtype, float out[12]) {
 }
 
 // ------------------------------------------------------------------ conversion
+
+// Long rows by tiles (x panels of long_tile_width values per workgroup)
+// over the long rows already in V.long_rows, longest first, of lengths len.
+// Row blocks hold about four panels' worth of entries per workgroup (less
+// when the grid would have under 2048 workgroups); a block's lanes per row
+// (8 to 64) give about 16 entries per lane of its mean segment, raised for
+// float64 until its longest segment keeps the chain bound.  Leaves
+// V.long_tiles false (nothing built) when the partials and segment starts
+// would cost over 1/20 of the long rows' own bytes per run, or no lane
+// count keeps the float64 bound.
+spmv_status build_long_tiles(const spmv_plan_s &P, Variant &V, const std::vector<int64_t> &len,
+                             hipStream_t s) {
+    const int64_t n7 = (int64_t)len.size();
+    const int64_t W = long_tile_width(P.elt);
+    const int64_t NP = (P.n + W - 1) / W;
+    if (n7 == 0 || NP < 1 || NP > 65535) return SPMV_OK;
+    int64_t total = 0;
+    for (int64_t l : len) total += l;
+    const double extra = 16.0 * (double)NP * n7 + 8.0 * (double)(NP + 1) * n7;
+    if (extra * 20 > (double)total * (P.elt + 4)) return SPMV_OK;
+    const size_t nseg = (size_t)(n7 * (NP + 1));
+    SMAT_TRY(V.tile_seg.alloc(sizeof(int32_t) * nseg));
+    SMAT_TRY(launch_long_tile_seg(n7, NP, W, V.long_rows.as<int32_t>(), P.rp.as<int32_t>(),
+                                  P.col.as<int32_t>(), V.tile_seg.as<int32_t>(), s));
+    std::vector<int32_t> h(nseg);
+    SMAT_HIP(hipMemcpyAsync(h.data(), V.tile_seg.p, sizeof(int32_t) * nseg,
+                            hipMemcpyDeviceToHost, s));
+    SMAT_HIP(hipStreamSynchronize(s));
+    const int64_t target =
+        std::max<int64_t>(1, std::min<int64_t>(4 * W * NP, total * NP / 2048));
+    std::vector<int32_t> blocks;
+    int max_tpr = 0;
+    for (int64_t r0 = 0; r0 < n7;) {
+        int64_t r1 = r0, acc = 0;
+        while (r1 < n7 && (r1 == r0 || acc < target)) acc += len[r1++];
+        int64_t maxseg = 0;
+        for (int64_t p = 0; p < NP; ++p)
+            for (int64_t r = r0; r < r1; ++r)
+                maxseg = std::max<int64_t>(maxseg, (int64_t)h[(p + 1) * n7 + r] - h[p * n7 + r]);
+        const double mean = (double)acc / ((double)(r1 - r0) * (double)NP);
+        int lg = 3;
+        while (lg < 6 && 16.0 * (double)(1 << lg) < mean) ++lg;
+        auto depth = [&](int l) { return (maxseg + (1 << l) - 1) / (1 << l) + l + NP; };
+        if (P.dtype == SPMV_F64) {
+            while (lg < 6 && depth(lg) > kFp64MaxDepth) ++lg;
+            if (depth(lg) > kFp64MaxDepth) {
+                V.tile_seg.release();
+                return SPMV_OK;
+            }
+        }
+        blocks.push_back((int32_t)r0);
+        blocks.push_back((int32_t)r1);
+        blocks.push_back(lg);
+        max_tpr = std::max(max_tpr, 1 << lg);
+        r0 = r1;
+    }
+    SMAT_TRY(V.tile_blocks.alloc(sizeof(int32_t) * blocks.size()));
+    SMAT_HIP(hipMemcpyAsync(V.tile_blocks.p, blocks.data(), sizeof(int32_t) * blocks.size(),
+                            hipMemcpyHostToDevice, s));
+    SMAT_TRY(V.tile_part.alloc(sizeof(double) * (size_t)(NP * n7)));
+    SMAT_HIP(hipStreamSynchronize(s));
+    V.tile_P = NP;
+    V.tile_nb = (int64_t)blocks.size() / 3;
+    V.long_tiles = true;
+    V.long_tpr = max_tpr;
+    return SPMV_OK;
+}
 
 spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W, int kernel,
                           const spmv_params &prm_in, hipStream_t s, Variant &V) {
@@ -820,26 +887,25 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
             SMAT_HIP(hipStreamSynchronize(s));
         }
         V.bin_scratch.release();
-        // float64: the longest bin (a workgroup per row) leaves the binned
-        // launch for the kernel that streams x through LDS, when its rows
-        // are many (default) and short enough for the float64 chain bound
+        // The longest bin (a workgroup per row) can leave the binned launch
+        // for a kernel that keeps x in LDS: x chunks streamed through each
+        // workgroup of rows (long_lds 1, float64) or one x panel per (row
+        // block, panel) workgroup (long_lds 3).  Default: chunks for float64
+        // when the bin holds many rows.  Tiles that do not suit the matrix
+        // fall back to chunks where those keep the float64 chain bound, else
+        // to the binned launch.
         {
             const int64_t n7 = (int64_t)V.bin_off[8] - V.bin_off[7];
-            int ll = prm.long_lds ? prm.long_lds : (P.dtype == SPMV_F64 && n7 >= 4096 ? 1 : 2);
+            int ll = prm.long_lds ? prm.long_lds : (n7 >= 2048 ? 3 : 2);
             int tpr = n7 >= 8192 ? 32 : 64;
-            if (ll == 1 && P.dtype == SPMV_F64 &&
-                (F.max_rd + tpr - 1) / tpr + ilog2(tpr) > kFp64MaxDepth)
-                tpr = 64;
-            if (P.dtype != SPMV_F64 || n7 == 0 ||
-                (F.max_rd + tpr - 1) / tpr + ilog2(tpr) > kFp64MaxDepth)
-                ll = 2;
-            V.prm.long_lds = ll;
-            if (ll == 1) {
-                SMAT_TRY(long_rows_lds_prepare());
-                V.long_tpr = tpr;
-                V.n_long = n7;
+            if ((F.max_rd + tpr - 1) / tpr + ilog2(tpr) > kFp64MaxDepth) tpr = 64;
+            const bool chunks_ok = P.dtype == SPMV_F64 &&
+                                   (F.max_rd + tpr - 1) / tpr + ilog2(tpr) <= kFp64MaxDepth;
+            if (n7 == 0 || (ll == 1 && !chunks_ok)) ll = 2;
+            if (ll != 2) {
                 // the long rows longest first, so that the rows of one
                 // workgroup (which waits for its longest) are alike
+                std::vector<int64_t> len(n7);
                 {
                     Dev be;
                     SMAT_TRY(be.alloc(sizeof(int64_t) * 2 * (size_t)n7));
@@ -860,17 +926,34 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
                         return h[2 * a + 1] - h[2 * a] > h[2 * b + 1] - h[2 * b];
                     });
                     std::vector<int32_t> sorted(n7);
-                    for (int64_t i = 0; i < n7; ++i) sorted[i] = rows[ord[i]];
+                    for (int64_t i = 0; i < n7; ++i) {
+                        sorted[i] = rows[ord[i]];
+                        len[i] = h[2 * ord[i] + 1] - h[2 * ord[i]];
+                    }
                     SMAT_TRY(V.long_rows.alloc(sizeof(int32_t) * (size_t)n7));
                     SMAT_HIP(hipMemcpyAsync(V.long_rows.p, sorted.data(), sizeof(int32_t) * n7,
                                             hipMemcpyHostToDevice, s));
                     SMAT_HIP(hipStreamSynchronize(s));
                 }
-                const unsigned b7 = V.alaunch.first[1];  // workgroups of bin 7
-                V.arest = V.alaunch;
-                V.arest.first[0] = 0;
-                for (int q = 1; q < 9; ++q) V.arest.first[q] = V.alaunch.first[q] - b7;
+                if (ll == 3) {
+                    SMAT_TRY(build_long_tiles(P, V, len, s));
+                    if (!V.long_tiles) ll = chunks_ok ? 1 : 2;
+                }
+                if (ll == 1) {
+                    SMAT_TRY(long_rows_lds_prepare());
+                    V.long_tpr = tpr;
+                }
+                if (ll == 2) {
+                    V.long_rows.release();
+                } else {
+                    V.n_long = n7;
+                    const unsigned b7 = V.alaunch.first[1];  // workgroups of bin 7
+                    V.arest = V.alaunch;
+                    V.arest.first[0] = 0;
+                    for (int q = 1; q < 9; ++q) V.arest.first[q] = V.alaunch.first[q] - b7;
+                }
             }
+            V.prm.long_lds = ll;
         }
         if (panels) {
             if (ns > 0) {
@@ -908,6 +991,19 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
     }
 }
 
+// The long rows taken out of the binned launch: x chunks or tiles.
+spmv_status run_long_rows(const spmv_plan_s &P, const Variant &V, const void *x, void *y,
+                          hipStream_t s) {
+    if (V.long_tiles)
+        return run_long_tiles(P.elt, V.n_long, V.tile_P, V.tile_nb, V.tile_blocks.as<int32_t>(),
+                              V.tile_seg.as<int32_t>(), V.long_rows.as<int32_t>(),
+                              P.col.as<int32_t>(), P.val.p, x, P.n, V.tile_part.as<double>(), y,
+                              s);
+    return run_long_rows_lds(V.long_tpr, V.n_long, V.long_rows.as<int32_t>(), P.rp.as<int32_t>(),
+                             P.col.as<int32_t>(), P.val.as<double>(), (const double *)x, P.n,
+                             (double *)y, s);
+}
+
 spmv_status run_variant(const spmv_plan_s &P, const Variant &V, const void *x, void *y,
                         hipStream_t s) {
     const int elt = P.elt;
@@ -930,11 +1026,7 @@ spmv_status run_variant(const spmv_plan_s &P, const Variant &V, const void *x, v
                                    V.split_partials.as<double>(), V.nsplit_rows,
                                    V.split_begin.as<int64_t>(), V.split_rows.as<int32_t>(),
                                    P.col.as<int32_t>(), P.val.p, x, y, s));
-        if (V.long_tpr)
-            SMAT_TRY(run_long_rows_lds(V.long_tpr, V.n_long, V.long_rows.as<int32_t>(),
-                                       P.rp.as<int32_t>(), P.col.as<int32_t>(),
-                                       P.val.as<double>(), (const double *)x, P.n, (double *)y,
-                                       s));
+        if (V.long_tpr) SMAT_TRY(run_long_rows(P, V, x, y, s));
         return SPMV_OK;
     }
     case SPMV_K_CSR_PANEL: {
@@ -944,11 +1036,7 @@ spmv_status run_variant(const spmv_plan_s &P, const Variant &V, const void *x, v
                                 V.bin_rows.as<int32_t>(), V.P, m, V.prow.as<int32_t>(),
                                 V.pcol.as<int32_t>(), V.pval.p, x, y,
                                 V.prm.panel_xcd != 2 ? V.ppart.p : nullptr, lo, hi, s));
-        if (V.long_tpr)
-            SMAT_TRY(run_long_rows_lds(V.long_tpr, V.n_long, V.long_rows.as<int32_t>(),
-                                       P.rp.as<int32_t>(), P.col.as<int32_t>(),
-                                       P.val.as<double>(), (const double *)x, P.n, (double *)y,
-                                       s));
+        if (V.long_tpr) SMAT_TRY(run_long_rows(P, V, x, y, s));
         return SPMV_OK;
     }
     case SPMV_K_BCSR:
@@ -1050,7 +1138,7 @@ std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_
     case SPMV_K_CSR_ADAPTIVE:
         for (int rpl : {1, 2, 4})
             for (int nt : nts)
-                for (int ll : {1, 2}) {  // long rows through LDS (float64) or not
+                for (int ll : {1, 2, 3}) {  // long rows: x chunks (float64), binned, tiles
                     if (ll == 1 && dtype != SPMV_F64) continue;
                     spmv_params p = b;
                     p.adaptive_rows_per_lane = rpl;
@@ -1122,7 +1210,7 @@ std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_
                     continue;
                 seen.push_back({mode, P});
                 for (int nt : nts)
-                    for (int ll : {1, 2}) {  // long rows through LDS (float64) or not
+                    for (int ll : {1, 2, 3}) {  // long rows: x chunks (float64), binned, tiles
                         if (ll == 1 && dtype != SPMV_F64) continue;
                         p.stream_nt = nt;
                         p.long_lds = ll;
@@ -1189,12 +1277,19 @@ spmv_status autotune_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork
     }
     const double tol = 2.0 * (P.elt == 8 ? 1e-12 : 2e-6);
     const int kernel = best->kernel;
+    // points whose parameters resolve to one already timed (a switch the
+    // matrix leaves without effect) are not timed again
+    std::vector<spmv_params> visited{best->prm};
     for (const spmv_params &p : tune_grid(kernel, best->prm, F, P.dtype)) {
         if (same_params(p, best->prm)) continue;
         auto V = std::make_unique<Variant>();
         spmv_status st = build_variant(P, F, W, kernel, p, s, *V);
         if (st == SPMV_ENOMEM || st == SPMV_EUNSUPPORTED) continue;
         if (st != SPMV_OK) return st;
+        if (std::any_of(visited.begin(), visited.end(),
+                        [&](const spmv_params &q) { return same_params(V->prm, q); }))
+            continue;
+        visited.push_back(V->prm);
         double ms = 0;
         SMAT_TRY(time_variant(P, *V, xs.p, ys.p, reps, s, &ms));
         if (m) {

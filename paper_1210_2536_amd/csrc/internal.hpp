@@ -157,6 +157,19 @@ spmv_status long_rows_lds_prepare();
 spmv_status run_long_rows_lds(int tpr, int64_t nrows, const int32_t *rows, const int32_t *rp,
                               const int32_t *col, const double *val, const double *x, int64_t n,
                               double *y, hipStream_t s);
+// Long rows by tiles: x panels of long_tile_width(elt) values, workgroup
+// (row block, panel).  seg: (P + 1) * n7 segment starts, filled by
+// launch_long_tile_seg from the rows (ascending columns); blocks: nblocks
+// triples (first row, end row, log2 lanes per row) over the rows' order;
+// part: P * n7 float64 partials.  y receives the rows rows[0 .. n7).
+int64_t long_tile_width(int elt);
+spmv_status launch_long_tile_seg(int64_t n7, int64_t P, int64_t W, const int32_t *rows,
+                                 const int32_t *rp, const int32_t *col, int32_t *seg,
+                                 hipStream_t s);
+spmv_status run_long_tiles(int elt, int64_t n7, int64_t P, int64_t nblocks,
+                           const int32_t *blocks, const int32_t *seg, const int32_t *rows,
+                           const int32_t *col, const void *val, const void *x, int64_t n,
+                           double *part, void *y, hipStream_t s);
 // Build column panels of width w from a CSR matrix whose rows are visited in
 // the binned order `rows`.  cnt: P*(m+1) ints; prow: P*(m+1)+1 ints; inv: m
 // ints; scan: P*(m+1)/4096+1 unsigned.

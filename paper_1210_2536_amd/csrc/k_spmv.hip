@@ -430,6 +430,117 @@ __global__ __launch_bounds__(kLongThreads) void k_long_rows_lds(
     if (t == 0 && active) y[row] = acc;
 }
 
+// ---------------------------------------------------------------- long rows, x panels per workgroup
+// The long rows (longest first) are cut into row blocks of about equal entry
+// counts and x into panels of kTileBytes.  Workgroup (b, p) copies x panel p
+// into LDS once, then adds for every row of block b the row's entries whose
+// columns fall in the panel, the segment [seg[p][r], seg[p + 1][r]) of row r:
+// lane t of the row's TPR lanes takes the segment's entries t, t + TPR, ...
+// in order, TPR being set per block so that short and long segments both
+// keep the lanes busy.  The lane sums are added by xor shuffles into one
+// float64 partial per (row, panel), and k_long_tiles_reduce adds a row's
+// partials in panel order and rounds once.  A row's float64 chain is at most
+// (longest segment) / TPR + log2 TPR + panels long.
+constexpr int kTileThreads = 1024;
+constexpr int kTileBytes = 65536;   // x per workgroup: two workgroups per CU
+
+template <typename T>
+__global__ __launch_bounds__(kTileThreads) void k_long_tiles(
+    int64_t n7, int64_t W, const int32_t *__restrict__ blocks, const int32_t *__restrict__ seg,
+    const int32_t *__restrict__ col, const T *__restrict__ val, const T *__restrict__ x,
+    int64_t n, double *__restrict__ part) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int V = 16 / (int)sizeof(T);      // values per 16-byte piece
+    typedef T vec __attribute__((ext_vector_type(V)));
+    constexpr int PIECES = kTileBytes / 16;
+    constexpr int PER = PIECES / kTileThreads;
+    static_assert(PIECES % kTileThreads == 0, "panel must split evenly");
+    const int64_t b = blockIdx.x, p = blockIdx.y;
+    const int64_t c0 = p * W;
+    vec *xv = reinterpret_cast<vec *>(smem);
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+        const int k = q * kTileThreads + threadIdx.x;
+        const int64_t j0 = c0 + (int64_t)k * V;
+        vec w;
+        if (j0 + V <= n) {
+            __builtin_memcpy(&w, x + j0, sizeof(w));
+        } else {
+#pragma unroll
+            for (int e = 0; e < V; ++e) w[e] = j0 + e < n ? x[j0 + e] : T(0);
+        }
+        xv[k] = w;
+    }
+    __syncthreads();
+    const T *xs = reinterpret_cast<const T *>(smem);
+    const int64_t r0 = blocks[3 * b], r1 = blocks[3 * b + 1];
+    const int lg = blocks[3 * b + 2];
+    const int tpr = 1 << lg;
+    const int t = threadIdx.x & (tpr - 1);
+    const int grp = threadIdx.x >> lg;
+    const int G = kTileThreads >> lg;
+    const int32_t *sb = seg + p * n7, *se = seg + (p + 1) * n7;
+    double *pp = part + p * n7;
+    // every lane of a wave runs the same iterations (the shuffles need them)
+    for (int64_t base = r0; base < r1; base += G) {
+        const int64_t r = base + grp;
+        const bool act = r < r1;
+        const int64_t e = act ? (int64_t)se[r] : 0;
+        int64_t q = (act ? (int64_t)sb[r] : 0) + t;
+        double acc = 0.0;
+        for (; q + 3 * tpr < e; q += 4 * tpr) {
+            int32_t cc[4];
+            T vv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) cc[u] = col[q + u * tpr];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) vv[u] = val[q + u * tpr];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) acc = fma((double)vv[u], (double)xs[cc[u] - c0], acc);
+        }
+        for (; q < e; q += tpr) acc = fma((double)val[q], (double)xs[col[q] - c0], acc);
+        for (int off = tpr >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+        if (t == 0 && act) pp[r] = acc;
+    }
+}
+
+// A long row's result: its panel partials added in panel order, rounded once.
+template <typename T>
+__global__ __launch_bounds__(256) void k_long_tiles_reduce(int64_t n7, int64_t P,
+                                                           const int32_t *__restrict__ rows,
+                                                           const double *__restrict__ part,
+                                                           T *__restrict__ y) {
+    const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (r >= n7) return;
+    double acc = 0.0;
+    for (int64_t p = 0; p < P; ++p) acc += part[p * n7 + r];
+    y[rows[r]] = (T)acc;
+}
+
+// Segment starts of the long rows in the x panels: seg[p * n7 + r] is the
+// first entry of row rows[r] whose column is at least p * W (for p = P, the
+// row's end), found by binary search over the row's ascending columns.
+__global__ __launch_bounds__(256) void k_long_tile_seg(int64_t n7, int64_t P, int64_t W,
+                                                       const int32_t *__restrict__ rows,
+                                                       const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ col,
+                                                       int32_t *__restrict__ seg) {
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n7 * (P + 1)) return;
+    const int64_t p = i / n7, r = i - p * n7;
+    const int32_t row = rows[r];
+    int64_t lo = rp[row], hi = rp[row + 1];
+    const int64_t c = p * W;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (col[mid] < c)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    seg[i] = (int32_t)lo;
+}
+
 // ---------------------------------------------------------------- BCSR 4x4
 // Two lane mappings, chosen by value type (both measured on gfx950):
 //
@@ -975,6 +1086,46 @@ spmv_status run_long_rows_lds(int tpr, int64_t nrows, const int32_t *rows, const
     else
         k_long_rows_lds<64><<<g, kLongThreads, kLongLds, s>>>(nrows, rows, rp, col, val, x, n, y);
     SMAT_LAUNCHED("long_rows_lds");
+    return SPMV_OK;
+}
+
+int64_t long_tile_width(int elt) { return kTileBytes / elt; }
+
+spmv_status launch_long_tile_seg(int64_t n7, int64_t P, int64_t W, const int32_t *rows,
+                                 const int32_t *rp, const int32_t *col, int32_t *seg,
+                                 hipStream_t s) {
+    const int64_t count = n7 * (P + 1);
+    if (count == 0) return SPMV_OK;
+    k_long_tile_seg<<<(unsigned)((count + 255) / 256), 256, 0, s>>>(n7, P, W, rows, rp, col, seg);
+    SMAT_LAUNCHED("long_tile_seg");
+    return SPMV_OK;
+}
+
+spmv_status run_long_tiles(int elt, int64_t n7, int64_t P, int64_t nblocks,
+                           const int32_t *blocks, const int32_t *seg, const int32_t *rows,
+                           const int32_t *col, const void *val, const void *x, int64_t n,
+                           double *part, void *y, hipStream_t s) {
+    if (n7 == 0) return SPMV_OK;
+    if (P < 1 || P > 65535 || nblocks < 1 || nblocks > INT_MAX || (elt != 4 && elt != 8)) {
+        set_error("long-row tiles: %lld panels, %lld row blocks", (long long)P,
+                  (long long)nblocks);
+        return SPMV_EINVAL;
+    }
+    const int64_t W = kTileBytes / elt;
+    const dim3 grid((unsigned)nblocks, (unsigned)P);
+    const unsigned rg = (unsigned)((n7 + 255) / 256);
+    if (elt == 8) {
+        k_long_tiles<double><<<grid, kTileThreads, kTileBytes, s>>>(
+            n7, W, blocks, seg, col, (const double *)val, (const double *)x, n, part);
+        SMAT_LAUNCHED("long_tiles");
+        k_long_tiles_reduce<double><<<rg, 256, 0, s>>>(n7, P, rows, part, (double *)y);
+    } else {
+        k_long_tiles<float><<<grid, kTileThreads, kTileBytes, s>>>(
+            n7, W, blocks, seg, col, (const float *)val, (const float *)x, n, part);
+        SMAT_LAUNCHED("long_tiles");
+        k_long_tiles_reduce<float><<<rg, 256, 0, s>>>(n7, P, rows, part, (float *)y);
+    }
+    SMAT_LAUNCHED("long_tiles_reduce");
     return SPMV_OK;
 }
 

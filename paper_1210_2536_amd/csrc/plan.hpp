@@ -98,6 +98,10 @@ struct Variant {
     int64_t n_long = 0;
     AdaptiveLaunch arest{};
     Dev long_rows;   // the long rows, longest first
+    // long rows by tiles (x panel per workgroup) instead of x chunks
+    bool long_tiles = false;
+    int64_t tile_P = 0, tile_nb = 0;
+    Dev tile_seg, tile_blocks, tile_part;
     // BCSR 4x4
     Dev brp, bcol, bval, bpres;
     int64_t nblocks = 0;
@@ -106,7 +110,8 @@ struct Variant {
                eval.bytes + dia_off.bytes + dia_data.bytes + dia_present.bytes + dia_win.bytes +
                bin_rows.bytes + bin_scratch.bytes + split_segs.bytes + split_partials.bytes +
                split_begin.bytes + split_rows.bytes + prow.bytes + pcol.bytes + pval.bytes +
-               ppart.bytes + brp.bytes + bcol.bytes + bval.bytes + bpres.bytes + long_rows.bytes;
+               ppart.bytes + brp.bytes + bcol.bytes + bval.bytes + bpres.bytes + long_rows.bytes +
+               tile_seg.bytes + tile_blocks.bytes + tile_part.bytes;
     }
 };
 

@@ -14,12 +14,34 @@ each way.
 import collections
 import csv
 import json
+import re
 import sys
 
 
 def short(n):
     n = n.replace('smat::(anonymous namespace)::', '').replace('void ', '')
     return n.split('(')[0]
+
+
+def matches(name, pat):
+    """A kernel name against one kernel of a plan's symbol ("false|true"
+    stands for either value of that template argument)."""
+    return re.fullmatch(re.escape(pat).replace(r'false\|true', '(?:false|true)'), name) is not None
+
+
+def dominant_runs(reg, dom):
+    """The dominant plan's runs: a dispatch of its first kernel followed, in
+    dispatch order, by its other kernels in order (kernels that other plans
+    also launch are counted only inside these runs)."""
+    names = [short(r['Kernel_Name']) for r in reg]
+    out, i = [], 0
+    while i < len(reg):
+        if i + len(dom) <= len(reg) and all(matches(names[i + j], d) for j, d in enumerate(dom)):
+            out.append(reg[i:i + len(dom)])
+            i += len(dom)
+        else:
+            i += 1
+    return out
 
 
 def region(rows, grid_key):
@@ -44,8 +66,9 @@ def trace_summary(trace_csv, B, dom):
            f"{'kernel':48s} {'calls':>7s} {'total_ms':>10s} {'avg_ms':>9s}"]
     for k, (c, t) in sorted(stats.items(), key=lambda kv: -kv[1][1])[:15]:
         out.append(f"{k:48s} {c:7d} {t:10.3f} {t / c:9.5f}")
-    C = stats[dom[0]][0]
-    T = sum(stats[k][1] for k in dom)
+    runs = dominant_runs(reg, dom)
+    C = len(runs)
+    T = sum((int(r['End_Timestamp']) - int(r['Start_Timestamp'])) / 1e6 for g in runs for r in g)
     out.append(f"dominant kernel {' + '.join(dom)}: {C} launches, avg {T / C:.5f} ms per launch "
                f"(bench live events over the same launches: "
                f"{B['roofline']['avg_launch_ms']:.5f} ms)")
@@ -58,9 +81,8 @@ def pmc(path, dom):
     reg, allr = region(rs, 'Grid_Size')
     big = [r for r in allr if 'k_stream_copy' in r['Kernel_Name'] and int(r['Grid_Size']) > 256]
     cal = float(big[-1]['Counter_Value'])
-    n = sum(1 for r in reg if short(r['Kernel_Name']) == dom[0])
-    tot = sum(float(r['Counter_Value']) for r in reg if short(r['Kernel_Name']) in dom)
-    return cal, n, tot
+    runs = dominant_runs(reg, dom)
+    return cal, len(runs), sum(float(r['Counter_Value']) for g in runs for r in g)
 
 
 def main(argv=None):

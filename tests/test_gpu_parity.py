@@ -432,3 +432,58 @@ def test_long_rows_through_lds():
     off = Plan(rp, col, val, n=A.n, selector="csr_adaptive",
                params={"long_lds": 2, "adaptive_wg_min": 64}).info()["params"]["long_lds"]
     assert on == 1 and off == 2
+
+
+def test_long_rows_by_tiles():
+    """Rows of the longest bin taken by x-panel tiles (long_lds 3), both
+    dtypes: several panels and a partial last one, rows that skip panels,
+    one row with all its entries in one panel, mixed row lengths (blocks of
+    different lanes per row); inside the binned CSR kernel and the column
+    panels, repeatable bit for bit, and in both batch modes.  Tiles that
+    would cost too much fall back to x chunks (float64) or the binned launch."""
+    import torch
+    from paper_1210_2536_amd.spmv import Batch, Plan
+    rng = np.random.default_rng(86)
+    band = S.random_csr(rng, 400, 40_000, 0.01)                      # 400 per row, 5 f64 panels
+    band.col[band.row_ptr[7]:band.row_ptr[8]] = np.arange(band.row_ptr[8] - band.row_ptr[7],
+                                                          dtype=np.int32)   # row 7 in panel 0
+    mats = [S.random_csr(rng, 300, 17_000, 0.02),                   # 340 per row
+            S.zipf_g2(np.random.default_rng([86, 0]), 30_000),
+            band]
+    for i, A in enumerate(mats):
+        x = np.random.default_rng([87, i]).uniform(-1, 1, A.n)
+        for dt in (np.float64, np.float32):
+            rp, col, val = dev(A, dt)
+            for k, extra in (("csr_adaptive", {}), ("csr_panel", {"panel_kib": 16}),
+                             ("csr_panel", {"panel_kib": 16, "panel_xcd": 2})):
+                note(f"[long tiles] {A.name} {np.dtype(dt).name} {k} {extra}")
+                p = Plan(rp, col, val, n=A.n, selector=k,
+                         params=dict(extra, long_lds=3, adaptive_wg_min=64))
+                info = p.info()
+                assert info["params"]["long_lds"] == 3, (A.name, info["params"]["long_lds"])
+                assert info["long_rows"] > 0 and info["long_lanes"] in (8, 16, 32, 64)
+                y = p.run(vec(x, dt)).cpu().numpy()
+                assert_parity(y, A, x, dt)
+                y2 = p.run(vec(x, dt)).cpu().numpy()
+                assert np.array_equal(y.view(np.uint8), y2.view(np.uint8))
+                if k == "csr_adaptive":
+                    for mode in (0, 1):
+                        B = Batch([p], mode=mode)
+                        yb = torch.full((A.m,), float("nan"), dtype=vec(x, dt).dtype,
+                                        device="cuda")
+                        B.run([vec(x, dt)], [yb])
+                        torch.cuda.synchronize()
+                        assert np.array_equal(yb.cpu().numpy().view(np.uint8), y.view(np.uint8))
+                        B.close()
+    # too many panels for the long rows' length: chunks (float64) or binned (float32)
+    m, n, k = 200, 3_000_000, 120                                   # 367 float64 panels
+    cols = np.concatenate([np.sort(rng.choice(n, k, replace=False)) for _ in range(m)])
+    A = S.CSR(m, n, np.arange(0, m * k + 1, k, dtype=np.int64), cols.astype(np.int32),
+              rng.uniform(-1, 1, m * k), "rand_200x3M")
+    x = np.random.default_rng(88).uniform(-1, 1, A.n)
+    for dt, want in ((np.float64, 1), (np.float32, 2)):
+        rp, col, val = dev(A, dt)
+        p = Plan(rp, col, val, n=A.n, selector="csr_adaptive",
+                 params={"long_lds": 3, "adaptive_wg_min": 64})
+        assert p.info()["params"]["long_lds"] == want
+        assert_parity(p.run(vec(x, dt)).cpu().numpy(), A, x, dt)
