@@ -145,14 +145,16 @@ typedef struct {
                                    (float64 only): a kernel that streams x
                                    through LDS in column chunks, 16-32 such
                                    rows per workgroup of 1024 threads;
-                                   3 = tiles (both dtypes): x cut into 64 KB
-                                   panels, one workgroup per (row block,
-                                   panel) holding its panel in LDS, one
-                                   float64 partial per (row, panel), the
-                                   partials added in panel order by a
-                                   second kernel; 2 = binned launch;
-                                   0 = default (tiles from 2048 such rows,
-                                   else 2).  Tiles fall back to chunks
+                                   3 = tiles (both dtypes) for the rows
+                                   longer than min(adaptive_wg_min, 1024):
+                                   x cut into 64 KB panels, one workgroup
+                                   per (row block, panel) holding its panel
+                                   in LDS, one float64 partial per (row,
+                                   panel), the partials added in panel
+                                   order by a second kernel; 2 = binned
+                                   launch; 0 = default (tiles from 1024
+                                   rows longer than 1024, else 2).  Tiles
+                                   fall back to chunks
                                    (float64) or 2 where their partials and
                                    segment starts would exceed 1/20 of the
                                    long rows' bytes per run or no lane count

@@ -485,6 +485,8 @@ int64_t bcsr_f64_depth(int64_t max_rd, int L) {
 constexpr int64_t kCooMaxChunksPerRow = 3000;
 constexpr int64_t kSplitSegment = 512 * 1024;   // entries per split segment (512 threads)
 constexpr int64_t kSplitMin = 256 * 4000;       // longer rows than this are split
+constexpr int kTileRowMin = 1024;       // tiles take rows longer than this (or wg_min)
+constexpr int64_t kTileRowsDefault = 1024;   // default: tiles from this many such rows
 
 // Kernels that can hold this matrix (zero-fill rule, storage cap) and, when
 // `accuracy` is set, also keep every float64 summation chain short enough for
@@ -821,7 +823,6 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
             spec.upper[b] = rpl << b;
             V.bin_lanes[b] = 1 << b;
         }
-        spec.upper[6] = std::max(prm.adaptive_wg_min, spec.upper[5]);  // width 64
         V.bin_lanes[6] = 64;
         spec.upper[7] = (int)kSplitMin;   // one workgroup per row
         spec.upper[8] = INT_MAX;          // split rows
@@ -830,13 +831,16 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
         unsigned nblk = (unsigned)std::max<int64_t>(1, (m + 255) / 256);
         SMAT_TRY(V.bin_rows.alloc(sizeof(int32_t) * std::max<int64_t>(1, m)));
         SMAT_TRY(V.bin_scratch.alloc(sizeof(unsigned) * ((size_t)nblk * kAdaptiveBins + kAdaptiveBins + 1)));
-        unsigned *blk = V.bin_scratch.as<unsigned>();
-        unsigned *offs = blk + (size_t)nblk * kAdaptiveBins;
-        SMAT_TRY(launch_bin_rows(m, P.rp.as<int32_t>(), spec, blk, V.bin_rows.as<int32_t>(), offs, s));
-        SMAT_HIP(hipMemcpyAsync(V.bin_off, offs, sizeof(V.bin_off), hipMemcpyDeviceToHost, s));
-        SMAT_HIP(hipStreamSynchronize(s));
-        // one launch over bins 7..0 (longest rows first)
-        {
+        // bins with rows longer than wg in bin 7, then one launch over bins
+        // 7..0 (longest rows first)
+        auto bin = [&](int wg) -> spmv_status {
+            spec.upper[6] = std::max(wg, spec.upper[5]);  // width 64
+            unsigned *blk = V.bin_scratch.as<unsigned>();
+            unsigned *offs = blk + (size_t)nblk * kAdaptiveBins;
+            SMAT_TRY(launch_bin_rows(m, P.rp.as<int32_t>(), spec, blk, V.bin_rows.as<int32_t>(),
+                                     offs, s));
+            SMAT_HIP(hipMemcpyAsync(V.bin_off, offs, sizeof(V.bin_off), hipMemcpyDeviceToHost, s));
+            SMAT_HIP(hipStreamSynchronize(s));
             unsigned blocks = 0;
             for (int q = 0; q < 8; ++q) {
                 int b = 7 - q;
@@ -847,7 +851,14 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
             }
             V.alaunch.first[8] = blocks;
             for (int b = 0; b < 9; ++b) V.alaunch.row_begin[b] = V.bin_off[b];
-        }
+            return SPMV_OK;
+        };
+        // tiles (asked for, or the default's candidate) take the rows longer
+        // than kTileRowMin as well; the binned launch's own threshold is
+        // restored below when they are not used
+        const bool try_tiles = prm.long_lds == 0 || prm.long_lds == 3;
+        int wg = try_tiles ? std::min(prm.adaptive_wg_min, kTileRowMin) : prm.adaptive_wg_min;
+        SMAT_TRY(bin(wg));
         // split rows: segment table on the host from their row_ptr entries
         int64_t ns = V.bin_off[9] - V.bin_off[8];
         if (ns > 0) {
@@ -886,17 +897,17 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
                                     hipMemcpyHostToDevice, s));
             SMAT_HIP(hipStreamSynchronize(s));
         }
-        V.bin_scratch.release();
         // The longest bin (a workgroup per row) can leave the binned launch
         // for a kernel that keeps x in LDS: x chunks streamed through each
         // workgroup of rows (long_lds 1, float64) or one x panel per (row
-        // block, panel) workgroup (long_lds 3).  Default: chunks for float64
-        // when the bin holds many rows.  Tiles that do not suit the matrix
-        // fall back to chunks where those keep the float64 chain bound, else
-        // to the binned launch.
-        {
+        // block, panel) workgroup (long_lds 3).  Default: tiles from
+        // kTileRowsDefault rows longer than kTileRowMin.  Tiles that do not
+        // suit the matrix fall back to chunks where those keep the float64
+        // chain bound, else to the binned launch.
+        int ll = prm.long_lds;
+        for (;;) {
             const int64_t n7 = (int64_t)V.bin_off[8] - V.bin_off[7];
-            int ll = prm.long_lds ? prm.long_lds : (n7 >= 2048 ? 3 : 2);
+            if (ll == 0) ll = n7 >= kTileRowsDefault ? 3 : 2;
             int tpr = n7 >= 8192 ? 32 : 64;
             if ((F.max_rd + tpr - 1) / tpr + ilog2(tpr) > kFp64MaxDepth) tpr = 64;
             const bool chunks_ok = P.dtype == SPMV_F64 &&
@@ -939,22 +950,31 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
                     SMAT_TRY(build_long_tiles(P, V, len, s));
                     if (!V.long_tiles) ll = chunks_ok ? 1 : 2;
                 }
-                if (ll == 1) {
-                    SMAT_TRY(long_rows_lds_prepare());
-                    V.long_tpr = tpr;
-                }
-                if (ll == 2) {
-                    V.long_rows.release();
-                } else {
-                    V.n_long = n7;
-                    const unsigned b7 = V.alaunch.first[1];  // workgroups of bin 7
-                    V.arest = V.alaunch;
-                    V.arest.first[0] = 0;
-                    for (int q = 1; q < 9; ++q) V.arest.first[q] = V.alaunch.first[q] - b7;
-                }
             }
-            V.prm.long_lds = ll;
+            if (ll != 3 && wg != prm.adaptive_wg_min && n7 > 0) {
+                // no tiles: bins with the binned launch's own threshold
+                V.long_rows.release();
+                wg = prm.adaptive_wg_min;
+                SMAT_TRY(bin(wg));
+                continue;
+            }
+            if (ll == 1) {
+                SMAT_TRY(long_rows_lds_prepare());
+                V.long_tpr = tpr;
+            }
+            if (ll == 2) {
+                V.long_rows.release();
+            } else {
+                V.n_long = n7;
+                const unsigned b7 = V.alaunch.first[1];  // workgroups of bin 7
+                V.arest = V.alaunch;
+                V.arest.first[0] = 0;
+                for (int q = 1; q < 9; ++q) V.arest.first[q] = V.alaunch.first[q] - b7;
+            }
+            break;
         }
+        V.prm.long_lds = ll;
+        V.bin_scratch.release();
         if (panels) {
             if (ns > 0) {
                 set_error("column panels cannot hold rows longer than %lld entries",

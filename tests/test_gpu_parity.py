@@ -487,3 +487,32 @@ def test_long_rows_by_tiles():
                  params={"long_lds": 3, "adaptive_wg_min": 64})
         assert p.info()["params"]["long_lds"] == want
         assert_parity(p.run(vec(x, dt)).cpu().numpy(), A, x, dt)
+
+
+def test_long_rows_default_mode():
+    """Default: tiles take the rows longer than 1024 when there are at least
+    1024 of them; with fewer, the binned launch keeps its own threshold
+    (rows up to adaptive_wg_min with 64 lanes each), and both give the
+    oracle's result."""
+    from paper_1210_2536_amd.spmv import Plan
+    rng = np.random.default_rng(89)
+    n = 50_000
+
+    def mat(n_long, n_short):
+        lens = np.concatenate([rng.integers(1100, 3000, n_long), rng.integers(1, 40, n_short)])
+        rng.shuffle(lens)
+        cols = [np.sort(rng.choice(n, k, replace=False)) for k in lens]
+        rp = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        return S.CSR(len(lens), n, rp, np.concatenate(cols).astype(np.int32),
+                     rng.uniform(-1, 1, int(rp[-1])), f"long{n_long}")
+    for A, want in ((mat(2100, 3000), 3), (mat(300, 3000), 2)):
+        x = np.random.default_rng(90).uniform(-1, 1, A.n)
+        for dt in (np.float64, np.float32):
+            for k in ("csr_adaptive", "csr_panel"):
+                note(f"[long default] {A.name} {np.dtype(dt).name} {k}")
+                rp, col, val = dev(A, dt)
+                p = Plan(rp, col, val, n=A.n, selector=k)
+                info = p.info()
+                assert info["params"]["long_lds"] == want, (A.name, k, info["params"]["long_lds"])
+                assert info["long_rows"] == (2100 if want == 3 else 0)
+                assert_parity(p.run(vec(x, dt)).cpu().numpy(), A, x, dt)
