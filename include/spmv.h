@@ -173,7 +173,14 @@ typedef struct spmv_selector_s *spmv_selector_t;
  * through.  alloc runs during spmv_plan_create and spmv_convert_roundtrip
  * on the calling thread; free runs there and in spmv_plan_destroy.  Both
  * NULL (the default): hipMalloc / hipFree.  Selectors and batches always
- * use hipMalloc. */
+ * use hipMalloc.
+ * Stream rule: a block freed during spmv_plan_create or
+ * spmv_convert_roundtrip may still be in use by work queued on that call's
+ * stream, so the allocator must not hand it out again before that work is
+ * done (a stream-ordered pool whose blocks belong to that stream does this,
+ * as PyTorch's caching allocator does for blocks allocated on it).
+ * spmv_plan_destroy synchronises the plan's device before it calls free,
+ * so runs of the plan on any stream have finished by then. */
 typedef struct {
     void *(*alloc)(size_t bytes, void *ctx);
     void (*free)(void *ptr, size_t bytes, void *ctx);
@@ -317,7 +324,11 @@ spmv_status spmv_plan_create(const spmv_csr *csr, const spmv_plan_opts *opts,
 
 /* y_dev[0..m) = A x_dev[0..n) (y overwritten, never accumulated into).
  * Asynchronous on `stream`, no allocation, no synchronisation.  x and y
- * must not overlap (EINVAL).  m = 0 is a no-op; n = 0 allows x_dev = NULL. */
+ * must not overlap (EINVAL).  m = 0 is a no-op; n = 0 allows x_dev = NULL.
+ * The result is defined for finite x: the DIA and BCSR kernels multiply
+ * their zero-filled slots by x too, so an Inf or NaN in x at a column that a
+ * row does not store can turn that row into NaN there, where the CSR, COO
+ * and ELL kernels give the product of the stored entries only. */
 spmv_status spmv_run(spmv_plan_t plan, const void *x_dev, void *y_dev, void *stream);
 
 /* Copy the plan's report into *out (host). */

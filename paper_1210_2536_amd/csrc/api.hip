@@ -1443,6 +1443,7 @@ static spmv_status plan_create_segments(const spmv_csr *A, const spmv_plan_opts 
                                         std::chrono::steady_clock::time_point t_start) {
     auto P = std::make_unique<spmv_plan_s>();
     P->alloc = opts.allocator;
+    SMAT_HIP(hipGetDevice(&P->device));
     P->m = A->m;
     P->n = A->n;
     P->nnz = A->nnz;
@@ -1554,6 +1555,7 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
         return plan_create_segments(A, opts, mode, s, out, t_start);
     auto P = std::make_unique<spmv_plan_s>();
     P->alloc = opts.allocator;
+    SMAT_HIP(hipGetDevice(&P->device));
     P->m = A->m;
     P->n = A->n;
     P->nnz = A->nnz;
@@ -1894,8 +1896,22 @@ extern "C" spmv_status spmv_plan_info_get(spmv_plan_t P, spmv_plan_info *out) {
 }
 
 extern "C" spmv_status spmv_plan_destroy(spmv_plan_t P) {
+    if (!P) return SPMV_OK;
+    // Memory from a caller's allocator goes back to the caller, who may hand
+    // it out again at once, while runs of this plan on any stream may still
+    // read it: the plan's device is synchronised first.  (hipFree, the
+    // default, synchronises by itself.)
+    spmv_status st = SPMV_OK;
+    if (P->alloc.free) {
+        int cur = -1;
+        hipError_t e = hipGetDevice(&cur);
+        if (e == hipSuccess && P->device >= 0 && cur != P->device) e = hipSetDevice(P->device);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+        if (e != hipSuccess) st = hip_fail(e, "spmv_plan_destroy: device synchronisation");
+        if (cur >= 0 && cur != P->device) (void)hipSetDevice(cur);
+    }
     delete P;
-    return SPMV_OK;
+    return st;
 }
 
 extern "C" spmv_status spmv_convert_roundtrip(spmv_plan_t P, int32_t *rp, int32_t *col, void *val,

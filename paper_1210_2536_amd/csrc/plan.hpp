@@ -130,6 +130,7 @@ struct spmv_selector_s {
 
 struct spmv_plan_s {
     spmv_allocator alloc{};            // the caller's allocator of this plan
+    int device = -1;                   // the device the plan was created on
     int64_t m = 0, n = 0, nnz = 0;
     int dtype = 0, elt = 4;
     int64_t m_pad = 0;

@@ -171,15 +171,27 @@ def default_selector():
 
 class TorchAllocator:
     """Plan memory from PyTorch's caching allocator (spmv_allocator): every
-    block is a uint8 tensor on the device, held until the library frees it."""
+    block is a uint8 tensor on the device, held until the library frees it.
+
+    Blocks are allocated for the stream the plan is created on (``stream``,
+    set by Plan while it creates), so a block the library frees during plan
+    creation is only reused by PyTorch after the work already queued on that
+    stream; spmv_plan_destroy synchronises the device before it frees the
+    plan's own blocks, so runs on any stream have ended by then."""
 
     def __init__(self, device):
         self.device = device
         self.blocks = {}
+        self.stream = None
 
         def alloc(nbytes, ctx):
+            torch = _torch()
             try:
-                t = _torch().empty(int(nbytes), dtype=_torch().uint8, device=self.device)
+                if self.stream is not None:
+                    with torch.cuda.stream(self.stream):
+                        t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+                else:
+                    t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
             except Exception:  # out of memory: the library reports ENOMEM
                 return None
             self.blocks[t.data_ptr()] = t
@@ -277,8 +289,15 @@ class Plan:
         if val.device.type != "cuda" or row_ptr.device != val.device or col.device != val.device:
             raise TypeError("row_ptr, col and val must be tensors on one GPU")
         with torch.cuda.device(val.device):   # the library works on the current device
-            st = C.lib().spmv_plan_create(ctypes.byref(A), ctypes.byref(o),
-                                          _stream_handle(stream), ctypes.byref(h))
+            cs = stream if stream is not None else torch.cuda.current_stream()
+            if self._allocator is not None:
+                self._allocator.stream = cs
+            try:
+                st = C.lib().spmv_plan_create(ctypes.byref(A), ctypes.byref(o),
+                                              _stream_handle(cs), ctypes.byref(h))
+            finally:
+                if self._allocator is not None:
+                    self._allocator.stream = None
         C.check(st, "spmv_plan_create")
         self.handle = h
         self.m, self.n, self.nnz = m, n, int(col.numel())

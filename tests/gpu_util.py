@@ -30,15 +30,23 @@ def note(msg):
     sys.stdout.flush()
 
 
-def assert_parity(y_gpu, A, x, dtype, rows=None):
-    """Compare GPU output with the float64 oracle on the same (rounded) data."""
-    val = np.asarray(A.val).astype(dtype).astype(np.float64)
-    xx = np.asarray(x).astype(dtype).astype(np.float64)
+def assert_parity(y_gpu, A, x, dtype, rows=None, ref=None):
+    """Compare GPU output with the float64 oracle on the same (rounded) data.
+
+    ref: the oracle's (y, (|A||x|)) for these inputs when already computed
+    (full vectors only)."""
     y = np.asarray(y_gpu, dtype=np.float64)
-    if rows is None:
-        ref, absax = O.spmv_accurate(A.row_ptr, A.col, val, xx)
+    if ref is not None:
+        assert rows is None
+        ref, absax = ref
     else:
-        ref, absax = O.spmv_rows(A.row_ptr, A.col, val, xx, rows)
+        val = np.asarray(A.val).astype(dtype).astype(np.float64)
+        xx = np.asarray(x).astype(dtype).astype(np.float64)
+        if rows is None:
+            ref, absax = O.spmv_accurate(A.row_ptr, A.col, val, xx)
+        else:
+            ref, absax = O.spmv_rows(A.row_ptr, A.col, val, xx, rows)
+    assert y.shape == ref.shape, (y.shape, ref.shape)
     tol = TOL[dtype]
     err = np.abs(y - ref)
     bound = tol * absax
