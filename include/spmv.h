@@ -347,6 +347,21 @@ spmv_status spmv_plan_destroy(spmv_plan_t plan);
 /* Features only (validation included).  Synchronises `stream`. */
 spmv_status spmv_features_compute(const spmv_csr *csr, spmv_features *out, void *stream);
 
+/* spmv_features_compute for callers that cannot allocate device memory
+ * (code in a serving loop or a harness that forbids hipMalloc): the same
+ * validation and feature kernels, with every device buffer (flags,
+ * statistics, the diagonal and row-degree histograms) taken from one fixed
+ * 64 MiB device array that each GPU holds from the first call until the
+ * process ends, and results read back through pageable host memory.  No
+ * hipMalloc, hipFree or host-pinned allocation.  Limit: an m x n matrix
+ * needs 256 + 4 (m + n - 1) + 4 (n + 2) bytes, each part rounded up to 256
+ * (about m + 2n <= 16.7 million); larger matrices give SPMV_EUNSUPPORTED
+ * and nothing runs.  Every call on one GPU shares the array: calls that
+ * overlap on one GPU (two threads, or two streams) race; calls one after
+ * another do not see each other's data.  Synchronises `stream`.  Results
+ * and errors otherwise as spmv_features_compute. */
+spmv_status spmv_features_compute_noalloc(const spmv_csr *csr, spmv_features *out, void *stream);
+
 /* Test hook: rebuild CSR from the plan's internal format (CSR->X->CSR must be
  * the identity bit for bit).  Outputs are caller-owned device buffers of
  * m+1, nnz and nnz elements.  Synchronises `stream`. */

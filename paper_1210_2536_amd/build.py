@@ -16,7 +16,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libsmat_spmv.so")
 ARCH = os.environ.get("SMAT_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["api.hip", "k_features.hip", "k_convert.hip", "k_spmv.hip", "k_mlp.hip", "batch.hip"]
+SOURCES = ["api.hip", "k_features.hip", "k_convert.hip", "k_spmv.hip", "k_mlp.hip", "batch.hip",
+           "noalloc.hip"]
 
 # Packed-fp32 instructions are disabled for every device compile.
 FLAGS = [

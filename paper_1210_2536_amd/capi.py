@@ -88,6 +88,7 @@ _SIGS = {
     "spmv_plan_segment": (i32, [vp, i32, vp, vp]),
     "spmv_plan_destroy": (i32, [vp]),
     "spmv_features_compute": (i32, [vp, vp, vp]),
+    "spmv_features_compute_noalloc": (i32, [vp, vp, vp]),
     "spmv_convert_roundtrip": (i32, [vp, vp, vp, vp, vp]),
     "spmv_plan_export": (i32, [vp, i32, vp, ctypes.c_size_t, vp, vp]),
     "spmv_selector_create": (i32, [vp, i64, vp, vp, vp]),

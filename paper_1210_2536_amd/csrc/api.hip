@@ -118,7 +118,42 @@ struct FeatureWork {
     Dev diag_hist; // m + n - 1 bins; later the diagonal -> slot map
     bool census = false;       // the census was taken (DIA could be feasible)
     bool census_done = false;  // the census question is settled
+    // Allocation-free mode: the three buffers are carved out of a device
+    // region the caller owns (FeatureArena layout for this matrix) and
+    // results come back through pageable host memory.
+    unsigned char *arena = nullptr;
+    size_t arena_bytes = 0;
+    size_t arena_row_off = 0;
+    // buffer k (0 scratch, 1 diag_hist, 2 row_hist) of `bytes` bytes
+    spmv_status take(int k, size_t bytes);
 };
+
+// Layout of the allocation-free region for an m x n matrix: the scratch
+// block, the m + n - 1 diagonal bins and up to n + 1 row-degree bins
+// (max_RD <= n), each 256-byte aligned.
+struct FeatureArena {
+    static size_t align(size_t b) { return (b + 255) / 256 * 256; }
+    static constexpr size_t kDiagOffset = 256;
+    static size_t row_offset(int64_t m, int64_t n) {
+        return kDiagOffset + align(sizeof(unsigned) * (size_t)std::max<int64_t>(1, m + n - 1));
+    }
+    static size_t total(int64_t m, int64_t n) {
+        return row_offset(m, n) + align(sizeof(unsigned) * (size_t)(n + 2));
+    }
+};
+
+spmv_status FeatureWork::take(int k, size_t bytes) {
+    Dev &d = k == 0 ? scratch : k == 1 ? diag_hist : row_hist;
+    if (!arena) return d.alloc(bytes);
+    const size_t off = k == 0 ? 0 : k == 1 ? FeatureArena::kDiagOffset : arena_row_off;
+    const size_t end = k == 0 ? FeatureArena::kDiagOffset : k == 1 ? arena_row_off : arena_bytes;
+    if (off + bytes > end) {
+        set_error("feature buffer %d of %zu bytes exceeds its part of the region", k, bytes);
+        return SPMV_EUNSUPPORTED;
+    }
+    d.borrow(arena + off, bytes);
+    return SPMV_OK;
+}
 
 // Matrices with at most this many diagonal bins (m + n - 1) take the census
 // together with the CSR checks, gated on the device by their outcome: one
@@ -133,6 +168,7 @@ struct Scratch {
     uint32_t flags2;   // column checks
     double fit[5];
 };
+static_assert(sizeof(Scratch) <= FeatureArena::kDiagOffset, "scratch block fits its slot");
 
 // The scratch zeroed (min_rd at INT_MAX) by one small kernel rather than a
 // copy from pageable host memory.
@@ -160,8 +196,8 @@ Scratch *pinned_scratch() {
     return p;
 }
 
-spmv_status read_scratch(const Scratch *d, Scratch &h, hipStream_t s) {
-    Scratch *pin = pinned_scratch();
+spmv_status read_scratch(const Scratch *d, Scratch &h, hipStream_t s, bool pinned_ok = true) {
+    Scratch *pin = pinned_ok ? pinned_scratch() : nullptr;
     Scratch *dst = pin ? pin : &h;
     SMAT_HIP(hipMemcpyAsync(dst, d, sizeof(Scratch), hipMemcpyDeviceToHost, s));
     SMAT_HIP(hipStreamSynchronize(s));
@@ -192,7 +228,7 @@ void set_census(spmv_features &F, const DiagStats &ds, int64_t m, int64_t nnz, F
 
 spmv_status extract_rows(const spmv_csr &A, hipStream_t s, spmv_features &F, FeatureWork &W) {
     const int64_t m = A.m, n = A.n, nnz = A.nnz;
-    SMAT_TRY(W.scratch.alloc(sizeof(Scratch)));
+    SMAT_TRY(W.take(0, sizeof(Scratch)));
     Scratch *d = W.scratch.as<Scratch>();
     Scratch h{};
     k_init_scratch<<<1, 64, 0, s>>>(d);
@@ -209,13 +245,13 @@ spmv_status extract_rows(const spmv_csr &A, hipStream_t s, spmv_features &F, Fea
     // pass and DIA can still be feasible
     const bool with_census = nnz > 0 && m + n - 1 <= kCensusWithChecksBins;
     if (with_census) {
-        SMAT_TRY(W.diag_hist.alloc(sizeof(unsigned) * (size_t)(m + n - 1)));
+        SMAT_TRY(W.take(1, sizeof(unsigned) * (size_t)(m + n - 1)));
         SMAT_HIP(hipMemsetAsync(W.diag_hist.p, 0, W.diag_hist.bytes, s));
         SMAT_TRY(launch_entry_stats(m, n, nnz, A.row_ptr_dev, A.col_dev, &d->es,
                                     W.diag_hist.as<unsigned>(), false, s, &d->flags, &d->rs));
         SMAT_TRY(launch_diag_stats(m, n, W.diag_hist.as<unsigned>(), &d->ds, s));
     }
-    SMAT_TRY(read_scratch(d, h, s));
+    SMAT_TRY(read_scratch(d, h, s, W.arena == nullptr));
     if (h.flags) {
         set_error("invalid CSR row_ptr (flags 0x%x: %s%s%s)", h.flags,
                   (h.flags & kBadRowPtr0) ? "row_ptr[0] != 0 " : "",
@@ -267,7 +303,7 @@ spmv_status extract_entries(const spmv_csr &A, hipStream_t s, spmv_features &F, 
     const bool rest = what & kStageRest;
     // ---- power-law fit over the row-degree histogram
     if (rest && m && F.max_rd >= 1) {
-        SMAT_TRY(W.row_hist.alloc(sizeof(unsigned) * (size_t)(F.max_rd + 1)));
+        SMAT_TRY(W.take(2, sizeof(unsigned) * (size_t)(F.max_rd + 1)));
         SMAT_HIP(hipMemsetAsync(W.row_hist.p, 0, W.row_hist.bytes, s));
         SMAT_TRY(launch_row_hist(m, A.row_ptr_dev, (int)F.max_rd, W.row_hist.as<unsigned>(), s));
         SMAT_TRY(launch_powerlaw_fit(W.row_hist.as<unsigned>(), (int)F.max_rd, m, d->fit, s));
@@ -276,7 +312,7 @@ spmv_status extract_entries(const spmv_csr &A, hipStream_t s, spmv_features &F, 
     // since Ndiags >= max_RD) and / or the 4x4 block count
     const bool census = (what & kStageCensus) && !W.census_done && F.ell_feasible && nnz > 0;
     if (census) {
-        SMAT_TRY(W.diag_hist.alloc(sizeof(unsigned) * (size_t)(m + n - 1)));
+        SMAT_TRY(W.take(1, sizeof(unsigned) * (size_t)(m + n - 1)));
         SMAT_HIP(hipMemsetAsync(W.diag_hist.p, 0, W.diag_hist.bytes, s));
     }
     if (census || rest)
@@ -284,7 +320,7 @@ spmv_status extract_entries(const spmv_csr &A, hipStream_t s, spmv_features &F, 
                                     census ? W.diag_hist.as<unsigned>() : nullptr, rest, s));
     if (census) SMAT_TRY(launch_diag_stats(m, n, W.diag_hist.as<unsigned>(), &d->ds, s));
     Scratch h{};
-    SMAT_TRY(read_scratch(d, h, s));
+    SMAT_TRY(read_scratch(d, h, s, W.arena == nullptr));
     if (rest) {
         F.blocks4 = (int64_t)h.es.blocks4;
         F.block_fill = F.blocks4 ? (double)nnz / (16.0 * (double)F.blocks4) : 0.0;
@@ -1418,6 +1454,33 @@ extern "C" spmv_status spmv_features_compute(const spmv_csr *A, spmv_features *o
     FeatureWork W;
     return validate_and_extract(*A, (hipStream_t)stream, *out, W, false, nullptr, nullptr);
 }
+
+namespace smat {
+size_t features_region_bytes(int64_t m, int64_t n) {
+    return FeatureArena::total(std::max<int64_t>(0, m), std::max<int64_t>(0, n));
+}
+
+spmv_status features_in_region(const spmv_csr *A, spmv_features *out, hipStream_t s,
+                               void *region, size_t bytes) {
+    SMAT_TRY(check_csr(A));
+    if (!out || !region) {
+        set_error("out or region is NULL");
+        return SPMV_EINVAL;
+    }
+    const size_t need = features_region_bytes(A->m, A->n);
+    if (need > bytes) {
+        set_error("matrix needs %zu bytes of feature scratch (m + n - 1 diagonal bins and "
+                  "n + 1 row-degree bins); the fixed region holds %zu",
+                  need, bytes);
+        return SPMV_EUNSUPPORTED;
+    }
+    FeatureWork W;
+    W.arena = static_cast<unsigned char *>(region);
+    W.arena_bytes = need;
+    W.arena_row_off = FeatureArena::row_offset(A->m, A->n);
+    return validate_and_extract(*A, s, *out, W, false, nullptr, nullptr);
+}
+}  // namespace smat
 
 namespace {
 __global__ void k_rebase_rows(int64_t m, const int32_t *__restrict__ rp, int32_t base,

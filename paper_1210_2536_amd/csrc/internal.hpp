@@ -203,6 +203,16 @@ spmv_status run_fill_zero(int elt, int64_t m, void *y, hipStream_t s);
 spmv_status run_mlp_infer(const float *params, int n_out, const float *mean, const float *stdv,
                           const float *raw, int64_t rows, float *scores, hipStream_t s);
 
+// ----------------------------------------------------------------- features
+// Feature extraction (validation included) with every device buffer taken
+// from `region` (`bytes` bytes of device memory the caller owns) and the
+// results read back through pageable host memory: no allocation.
+// features_region_bytes(m, n) is what an m x n matrix needs; a smaller
+// region gives SPMV_EUNSUPPORTED.  Synchronises `s`.
+size_t features_region_bytes(int64_t m, int64_t n);
+spmv_status features_in_region(const spmv_csr *A, spmv_features *out, hipStream_t s,
+                               void *region, size_t bytes);
+
 // ----------------------------------------------------------------- misc
 spmv_status run_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
 int64_t gather_probe_threads();

@@ -27,12 +27,13 @@ struct Dev {
     void *p = nullptr;
     size_t bytes = 0;
     spmv_allocator from{};
+    bool borrowed = false;   // memory owned elsewhere (see borrow), never freed
     Dev() = default;
     Dev(const Dev &) = delete;
     Dev &operator=(const Dev &) = delete;
     ~Dev() { release(); }
     void release() {
-        if (p) {
+        if (p && !borrowed) {
             if (from.free)
                 from.free(p, bytes, from.ctx);
             else
@@ -41,6 +42,14 @@ struct Dev {
         p = nullptr;
         bytes = 0;
         from = spmv_allocator{};
+        borrowed = false;
+    }
+    // Use `b` bytes at `q` (device memory someone else owns) as this buffer.
+    void borrow(void *q, size_t b) {
+        release();
+        p = q;
+        bytes = b;
+        borrowed = true;
     }
     spmv_status alloc(size_t b) {
         release();
