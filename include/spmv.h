@@ -147,10 +147,10 @@ typedef struct {
                                    rows per workgroup of 1024 threads;
                                    3 = tiles (both dtypes) for the rows
                                    longer than min(adaptive_wg_min, 1024):
-                                   x cut into 64 KB panels, one workgroup
+                                   x cut into 80 KB panels, one workgroup
                                    per (row block, panel) holding its panel
                                    in LDS, one float64 partial per (row,
-                                   panel), the partials added in panel
+                                   panel), the partials added in a fixed
                                    order by a second kernel; 2 = binned
                                    launch; 0 = default (tiles from 1024
                                    rows longer than 1024, else 2).  Tiles
@@ -161,6 +161,13 @@ typedef struct {
                                    keeps the 1e-12 bound; chunks fall back
                                    to 2 in float32 and for rows too long for
                                    the bound with 64 lanes per row          */
+    int32_t panel_direct_max;   /* CSR_PANEL: rows of at most this many
+                                   entries (rounded down to a length-bin
+                                   boundary) skip the column panels -- no
+                                   partial sums -- and are summed by the
+                                   length-binned kernel reading x through
+                                   the caches; -1 = every row in the panels;
+                                   0 = default (-1)                          */
 } spmv_params;
 
 typedef struct spmv_selector_s *spmv_selector_t;

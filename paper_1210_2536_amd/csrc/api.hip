@@ -385,6 +385,9 @@ spmv_params default_params(int kernel, const spmv_features &F) {
 }
 
 constexpr int kXcds = 8;  // gfx950: eight accelerator complex dies, one L2 each
+// Column panels: rows of at most this many entries are summed without panels
+// by default (-1: none).
+constexpr int kPanelDirectMaxDefault = -1;
 constexpr int64_t kDiaLdsMax = 64 * 1024;  // dynamic LDS of one DIA workgroup
 
 // Column-panel geometry: width w columns (a multiple of 64) and panel count P.
@@ -423,6 +426,7 @@ spmv_params resolve_params(int kernel, spmv_params p, const spmv_features &F, in
     // the chip many times over (measured: faster from about a million rows,
     // slower on smaller matrices)
     if (p.wide_loads == 0) p.wide_loads = F.m >= (1 << 20) ? 1 : 2;
+    if (p.panel_direct_max == 0) p.panel_direct_max = kPanelDirectMaxDefault;
     if (p.bcsr_lanes == 0) {
         const int64_t mb = std::max<int64_t>(1, (F.m + 3) / 4);
         const int64_t avg = (std::max<int64_t>(0, F.blocks4) + mb - 1) / mb;
@@ -454,6 +458,7 @@ void merge_params(spmv_params &p, const spmv_params &u) {
     if (u.wide_loads > 0) p.wide_loads = u.wide_loads;
     if (u.bcsr_lanes > 0) p.bcsr_lanes = u.bcsr_lanes;
     if (u.long_lds > 0) p.long_lds = u.long_lds;
+    if (u.panel_direct_max != 0) p.panel_direct_max = u.panel_direct_max;
 }
 
 spmv_status check_params(const spmv_params &p) {
@@ -501,6 +506,11 @@ spmv_status check_params(const spmv_params &p) {
         set_error("params.long_lds must be 0 (default), 1 (x chunks), 2 (off) or 3 (tiles)");
         return SPMV_EINVAL;
     }
+    if (p.panel_direct_max < -1 || p.panel_direct_max > (1 << 20)) {
+        set_error("params.panel_direct_max must be -1 (none), 0 (default) or a row length "
+                  "up to 2^20");
+        return SPMV_EINVAL;
+    }
     if (p.bcsr_lanes != 0 && !(pow2(p.bcsr_lanes) && p.bcsr_lanes <= 64)) {
         set_error("params.bcsr_lanes must be 0 (default) or a power of two <= 64");
         return SPMV_EINVAL;
@@ -523,6 +533,11 @@ constexpr int64_t kSplitSegment = 512 * 1024;   // entries per split segment (51
 constexpr int64_t kSplitMin = 256 * 4000;       // longer rows than this are split
 constexpr int kTileRowMin = 1024;       // tiles take rows longer than this (or wg_min)
 constexpr int64_t kTileRowsDefault = 1024;   // default: tiles from this many such rows
+// Tiles: lanes per row of a row block, the fewest (at least 2^kTileLanesLog2Min)
+// that give about kTileEntriesPerLane entries per lane of the block's mean
+// segment (raised further where the float64 chain bound needs it).
+constexpr int kTileLanesLog2Min = 3;
+constexpr double kTileEntriesPerLane = 16.0;
 
 // Kernels that can hold this matrix (zero-fill rule, storage cap) and, when
 // `accuracy` is set, also keep every float64 summation chain short enough for
@@ -657,6 +672,27 @@ void raw_features(const spmv_features &F, int dtype, float out[12]) {
 // when the grid would have under 2048 workgroups); a block's lanes per row
 // (8 to 64) give about 16 entries per lane of its mean segment, raised for
 // float64 until its longest segment keeps the chain bound.  Leaves
+// Launch geometry of the length bins blo..bhi of a binned row order (the
+// other bins get no workgroups): bin 7 a workgroup per row, bins 6..0
+// 256 >> max(0, b - shift) rows per workgroup.
+AdaptiveLaunch bins_launch(const unsigned bin_off[kAdaptiveBins + 1], int blo, int bhi,
+                           int shift) {
+    AdaptiveLaunch a{};
+    unsigned blocks = 0;
+    for (int q = 0; q < 8; ++q) {
+        const int b = 7 - q;
+        a.first[q] = blocks;
+        if (b < blo || b > bhi) continue;
+        const unsigned cnt = bin_off[b + 1] - bin_off[b];
+        const unsigned per = b == 7 ? 1u : (unsigned)(256 >> std::max(0, b - shift));
+        blocks += (cnt + per - 1) / per;
+    }
+    a.first[8] = blocks;
+    for (int b = 0; b < 9; ++b) a.row_begin[b] = bin_off[b];
+    a.lane_shift = shift;
+    return a;
+}
+
 // V.long_tiles false (nothing built) when the partials and segment starts
 // would cost over 1/20 of the long rows' own bytes per run, or no lane
 // count keeps the float64 bound.
@@ -671,6 +707,7 @@ spmv_status build_long_tiles(const spmv_plan_s &P, Variant &V, const std::vector
     const double extra = 16.0 * (double)NP * n7 + 8.0 * (double)(NP + 1) * n7;
     if (extra * 20 > (double)total * (P.elt + 4)) return SPMV_OK;
     const size_t nseg = (size_t)(n7 * (NP + 1));
+    SMAT_TRY(long_tiles_prepare());
     SMAT_TRY(V.tile_seg.alloc(sizeof(int32_t) * nseg));
     SMAT_TRY(launch_long_tile_seg(n7, NP, W, V.long_rows.as<int32_t>(), P.rp.as<int32_t>(),
                                   P.col.as<int32_t>(), V.tile_seg.as<int32_t>(), s));
@@ -690,8 +727,8 @@ spmv_status build_long_tiles(const spmv_plan_s &P, Variant &V, const std::vector
             for (int64_t r = r0; r < r1; ++r)
                 maxseg = std::max<int64_t>(maxseg, (int64_t)h[(p + 1) * n7 + r] - h[p * n7 + r]);
         const double mean = (double)acc / ((double)(r1 - r0) * (double)NP);
-        int lg = 3;
-        while (lg < 6 && 16.0 * (double)(1 << lg) < mean) ++lg;
+        int lg = kTileLanesLog2Min;
+        while (lg < 6 && kTileEntriesPerLane * (double)(1 << lg) < mean) ++lg;
         auto depth = [&](int l) { return (maxseg + (1 << l) - 1) / (1 << l) + l + NP; };
         if (P.dtype == SPMV_F64) {
             while (lg < 6 && depth(lg) > kFp64MaxDepth) ++lg;
@@ -1011,6 +1048,18 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
         }
         V.prm.long_lds = ll;
         V.bin_scratch.release();
+        if (panels && prm.panel_direct_max > 0) {
+            // the shortest bins leave the panels: their rows cost a panel
+            // row pointer and a partial written and read per panel, more
+            // than their few gathers from x save
+            int S = 0;
+            while (S < 6 && spec.upper[S] <= prm.panel_direct_max) ++S;
+            V.short_bins = S;
+            if (S > 0) {
+                V.ashort = bins_launch(V.bin_off, 0, S - 1, 0);
+                V.apanel = bins_launch(V.bin_off, S, V.long_tpr ? 6 : 7, shift);
+            }
+        }
         if (panels) {
             if (ns > 0) {
                 set_error("column panels cannot hold rows longer than %lld entries",
@@ -1086,12 +1135,19 @@ spmv_status run_variant(const spmv_plan_s &P, const Variant &V, const void *x, v
         return SPMV_OK;
     }
     case SPMV_K_CSR_PANEL: {
-        const int64_t lo = V.long_tpr ? V.alaunch.row_begin[7] : 0;
-        const int64_t hi = V.long_tpr ? V.alaunch.row_begin[8] : 0;
-        SMAT_TRY(run_csr_panels(elt, nt, V.long_tpr ? V.arest : V.alaunch,
-                                V.bin_rows.as<int32_t>(), V.P, m, V.prow.as<int32_t>(),
-                                V.pcol.as<int32_t>(), V.pval.p, x, y,
-                                V.prm.panel_xcd != 2 ? V.ppart.p : nullptr, lo, hi, s));
+        // binned positions [lo, hi) go through the panels: all rows but the
+        // short bins (summed directly) and the longest bin (long-row kernel)
+        const int64_t lo = V.bin_off[V.short_bins];
+        const int64_t hi = V.long_tpr ? V.bin_off[7] : m;
+        const AdaptiveLaunch &ap =
+            V.short_bins ? V.apanel : V.long_tpr ? V.arest : V.alaunch;
+        SMAT_TRY(run_csr_panels(elt, nt, ap, V.bin_rows.as<int32_t>(), V.P, m,
+                                V.prow.as<int32_t>(), V.pcol.as<int32_t>(), V.pval.p, x, y,
+                                V.prm.panel_xcd != 2 ? V.ppart.p : nullptr, lo, hi,
+                                V.short_bins > 0 || V.long_tpr != 0, s));
+        if (V.short_bins)
+            SMAT_TRY(run_csr_adaptive(elt, nt, true, V.ashort, V.bin_rows.as<int32_t>(),
+                                      P.rp.as<int32_t>(), P.col.as<int32_t>(), P.val.p, x, y, s));
         if (V.long_tpr) SMAT_TRY(run_long_rows(P, V, x, y, s));
         return SPMV_OK;
     }
@@ -1273,6 +1329,12 @@ std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_
                         add(p);
                     }
             }
+        // short rows without panels, the other parameters at their defaults
+        for (int d : {-1, 4, 16, 64}) {
+            spmv_params p = b;
+            p.panel_direct_max = d;
+            add(p);
+        }
         break;
     }
     case SPMV_K_COO:
@@ -1376,7 +1438,9 @@ spmv_status autotune_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork
 bool needs_csr(const Variant &V) {
     const int k = V.kernel;
     return k == SPMV_K_CSR_SCALAR || k == SPMV_K_CSR_VECTOR || k == SPMV_K_CSR_ADAPTIVE ||
-           k == SPMV_K_COO || (k == SPMV_K_CSR_PANEL && V.long_tpr);  // long rows read the CSR
+           k == SPMV_K_COO ||
+           // long rows and directly summed short rows read the CSR copy
+           (k == SPMV_K_CSR_PANEL && (V.long_tpr || V.short_bins));
 }
 
 }  // namespace

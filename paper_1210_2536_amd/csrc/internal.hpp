@@ -145,11 +145,13 @@ spmv_status run_csr_adaptive(int elt, bool nt, bool rest, const AdaptiveLaunch &
                              const void *val, const void *x, void *y, hipStream_t s);
 // Column panels; prow is P x (m+1) position-indexed segment starts.  With
 // `partial` (P x m values) all panels run in one launch, one per XCD, and a
-// second kernel adds the partials; without it, one launch per panel.
+// second kernel adds the partials of binned positions [red_lo, red_hi);
+// without it, one launch per panel.  `part`: the geometry leaves some bins
+// to other kernels (launched under the *_rest kernel names).
 spmv_status run_csr_panels(int elt, bool nt, const AdaptiveLaunch &a, const int32_t *rows, int P,
                            int64_t m, const int32_t *prow, const int32_t *pcol, const void *pval,
-                           const void *x, void *y, void *partial, int64_t skip_lo,
-                           int64_t skip_hi, hipStream_t s);
+                           const void *x, void *y, void *partial, int64_t red_lo,
+                           int64_t red_hi, bool part, hipStream_t s);
 // float64 long rows (the binned order's longest bin) with x streamed through
 // LDS; tpr (32 or 64) lanes per row.  prepare() raises the kernels' dynamic
 // LDS limit (call before the first launch, outside graph capture).
@@ -163,6 +165,9 @@ spmv_status run_long_rows_lds(int tpr, int64_t nrows, const int32_t *rows, const
 // triples (first row, end row, log2 lanes per row) over the rows' order;
 // part: P * n7 float64 partials.  y receives the rows rows[0 .. n7).
 int64_t long_tile_width(int elt);
+// Raises the tile kernels' dynamic LDS limit (before the first launch,
+// outside graph capture).
+spmv_status long_tiles_prepare();
 spmv_status launch_long_tile_seg(int64_t n7, int64_t P, int64_t W, const int32_t *rows,
                                  const int32_t *rp, const int32_t *col, int32_t *seg,
                                  hipStream_t s);

@@ -99,6 +99,10 @@ struct Variant {
     // CSR column panels
     Dev prow, pcol, pval, ppart;
     int P = 0;
+    // short rows summed directly (length bins 0 .. short_bins - 1) and the
+    // launch geometries of the two parts
+    int short_bins = 0;
+    AdaptiveLaunch apanel{}, ashort{};
     int64_t panel_w = 0;
     int64_t nsplit_rows = 0, nsplit_segs = 0;
     // float64 long rows through LDS: lanes per row (0: off), their count,
