@@ -79,6 +79,34 @@ def recorded_traffic(kernel, workload, algorithmic_bytes):
     return None
 
 
+def host_info():
+    """CPU model, logical CPUs usable by this process, and memory of the host."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    mem = None
+    try:
+        with open("/proc/meminfo") as fh:
+            for line in fh:
+                if line.startswith("MemTotal"):
+                    mem = round(int(line.split()[1]) / 1048576, 1)
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "usable_cpus": usable,
+            "mem_gib": mem}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -99,6 +127,11 @@ def parse():
                          "format and kernel (records and the step are per segment)")
     ap.add_argument("--no-cold", action="store_true",
                     help="skip the cold-cache runs (caches flushed before each SpMV)")
+    ap.add_argument("--no-side", action="store_true",
+                    help="skip the per-configuration records of the large workloads (the "
+                         "multilevel 27-point levels in float64, the n = 8M Zipf matrix in "
+                         "float32 and the 7-point 256^3 Laplacian in float64) that follow "
+                         "the headline workload")
     ap.add_argument("--no-batch", action="store_true",
                     help="time plain back-to-back runs only (no graph / persistent trial)")
     ap.add_argument("--no-staged", action="store_true",
@@ -121,7 +154,8 @@ def main():
 
     from paper_1210_2536_amd import capi, workloads
     from paper_1210_2536_amd import synth as S
-    from paper_1210_2536_amd.spmv import Plan, default_selector, gather_probe, stream_copy
+    from paper_1210_2536_amd.spmv import (Plan, default_selector, gather_probe, stream_copy,
+                                          stream_read)
 
     capi.lib()  # fails loudly if the HIP library is missing
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -262,7 +296,12 @@ def main():
         if rec.get("long_lanes"):
             long = (f" + k_long_tiles<{t}> + k_long_tiles_reduce<{t}>" if p.get("long_lds") == 3
                     else f" + k_long_rows_lds<{rec['long_lanes']}>")
-        rest = "_rest" if long else ""
+        # column panels that leave their shortest rows to the binned kernel
+        short = (k == "csr_panel" and
+                 p.get("panel_direct_max", -1) >= p["adaptive_rows_per_lane"])
+        rest = "_rest" if long or short else ""
+        if short:
+            long = f" + k_csr_adaptive_rest<{t}, {nt}>" + long
         if k == "csr_vector":
             return f"k_csr_vector<{t}, {p['vector_lanes']}, {nt}>"
         if k == "csr_adaptive":
@@ -411,7 +450,22 @@ def main():
         torch.cuda.synchronize()
         cps.append(e0.elapsed_time(e1))
     copy_gbs = 2.0 * cp_src.numel() * 4 / (float(np.median(cps[1:])) * 1e-3) / 1e9
-    del cp_src, cp_dst
+    del cp_dst
+    # read-dominant probe, the traffic shape of SpMV: 16-byte non-temporal
+    # loads of 1 GiB, one 16-byte word written per thread (256:1 here)
+    rd_out = None
+    rds = []
+    for _ in range(6):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        rd_out = stream_read(cp_src, out=rd_out)
+        e1.record()
+        torch.cuda.synchronize()
+        rds.append(e0.elapsed_time(e1))
+    read_bytes = cp_src.numel() * 4 + rd_out.numel()
+    read_gbs = read_bytes / (float(np.median(rds[1:])) * 1e-3) / 1e9
+    log(f"copy probe {copy_gbs:.0f} GB/s, read probe {read_gbs:.0f} GB/s")
+    del cp_src, rd_out
     # uniform random gathers: the CSR row loop's memory pattern (value and
     # index streams, one gather per entry) from a 1 MiB table, which every
     # XCD's L2 holds, with no two lanes sharing a cache line on purpose --
@@ -577,7 +631,31 @@ def main():
             n1 += 1
             if t1s >= a.cpu_seconds / 4:
                 break
+        # the same sample in float32 storage where the workload has
+        # float32-stored matrices (float64 sums, rows rounded once)
+        t32, f32s, n32 = 0.0, 0.0, 0
+        done32 = set()
+        for A, dt, xseed in items:
+            if dt != np.float32 or id(A) in done32 or A.name not in sampled:
+                continue
+            done32.add(id(A))
+            xv = S.uniform_vector(A.n, xseed).astype(np.float32)
+            rp64 = A.row_ptr.astype(np.int64)
+            v32 = A.val.astype(np.float32)
+            O.spmv_plain_f32(rp64, A.col, v32, xv, nthreads=threads)
+            ts = []
+            for _ in range(2):
+                t0c = time.perf_counter()
+                O.spmv_plain_f32(rp64, A.col, v32, xv, nthreads=threads)
+                ts.append(time.perf_counter() - t0c)
+            t32 += min(ts)
+            f32s += 2.0 * A.nnz
+            n32 += 1
+        host = host_info()
         cpu = {"value": round(fsum / tsum / 1e9, 3), "unit": "GFLOP/s", "cores": threads,
+               "value_f32_storage": round(f32s / t32 / 1e9, 3) if t32 else None,
+               "sample_f32_storage": f"the same {n32} matrices with float32 values and x",
+               "host": host,
                "value_1_thread": round(f1s / t1s / 1e9, 3) if t1s else None,
                "sample_1_thread": f"first {n1} sample matrices, one run each",
                "kind": "oracle",
@@ -586,6 +664,129 @@ def main():
                          f"nnz-balanced OpenMP rows), best of 2 runs each, "
                          f"{fsum / 2 / 1e6:.1f}M nnz"}
         log(f"cpu oracle: {cpu['value']} GFLOP/s on {threads} threads")
+
+    # ---- the large configurations, each timed on its own (records beside
+    # the headline): multilevel levels (one step of all levels, in the
+    # fastest of per-level launches, one persistent launch and one graph
+    # replay), the n = 8M Zipf matrix (float32) and the 7-point 256^3
+    # Laplacian (float64), with plain CSR on the same GPU and Equation 2
+    side = None
+    if not a.no_side and a.workload == "sweep":
+        side = {}
+        from paper_1210_2536_amd.spmv import Batch
+
+        def plan_of(A, dt, xseed):
+            rp = torch.from_numpy(A.row_ptr.astype(np.int32)).to(dev)
+            col = torch.from_numpy(A.col).to(dev)
+            val = torch.from_numpy(A.val.astype(dt)).to(dev)
+            x = torch.from_numpy(S.uniform_vector(A.n, xseed).astype(dt)).to(dev)
+            y = torch.empty(A.m, dtype=val.dtype, device=dev)
+            tuned = Plan(rp, col, val, n=A.n, selector=selector, model=model,
+                         autotune=not a.no_autotune)
+            plain = Plan(rp, col, val, n=A.n, selector="csr_scalar")
+            return tuned, plain, x, y
+
+        def one(A, dt, tuned, plain, x, y):
+            info = tuned.info()
+            t = time_run(tuned, x, y)
+            tp = time_run(plain, x, y)
+            b = workloads.plan_bytes(info)
+            return {"m": A.m, "nnz": A.nnz, "kernel": info["kernel_name"],
+                    "ms": round(t, 5), "gflops": round(2.0 * A.nnz / (t * 1e-3) / 1e9, 1),
+                    "alg_gbs": round(b / (t * 1e-3) / 1e9, 1),
+                    "frac": round(b / (t * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "bytes": int(b), "plain_ms": round(tp, 4),
+                    "tuned_vs_plain": round(tp / t, 2), "plan_ms": round(info["t_plan_ms"], 2),
+                    "break_even_calls": round(workloads.break_even_calls(
+                        info["t_plan_ms"], tp, t), 2)}
+
+        for A, dt, xseed in workloads.build("large"):
+            name = (f"{'zipf8M' if A.name.startswith('zipf') else 'lap7_256^3'}_"
+                    f"{'f32' if dt == np.float32 else 'f64'}")
+            log(f"side config {name}: planning")
+            tuned, plain, x, y = plan_of(A, dt, xseed)
+            side[name] = one(A, dt, tuned, plain, x, y)
+            log(f"side config {name}: {side[name]}")
+            tuned.close()
+            plain.close()
+            del tuned, plain, x, y
+        levels = workloads.build("multilevel")
+        lv = [(A, dt) + plan_of(A, dt, xs) for A, dt, xs in levels]
+        recs_ml = [one(A, dt, t, p, x, y) for A, dt, t, p, x, y in lv]
+        tuned_l = [r[2] for r in lv]
+        xs_l, ys_l = [r[4] for r in lv], [r[5] for r in lv]
+        modes = {}
+        bp = Batch(tuned_l, mode=0)
+        bp.tune(xs_l, ys_l)
+        bg = Batch(tuned_l, mode=1)
+        for mname, fn in (("separate", lambda: [t.run(x, y) for t, x, y in
+                                                zip(tuned_l, xs_l, ys_l)]),
+                          ("persistent", lambda: bp.run(xs_l, ys_l)),
+                          ("graph", lambda: bg.run(xs_l, ys_l))):
+            fn()
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(20)]
+            for e0, e1 in ev:
+                e0.record()
+                fn()
+                e1.record()
+            torch.cuda.synchronize()
+            modes[mname] = float(np.median([e0.elapsed_time(e1) for e0, e1 in ev]))
+        bp.close()
+        bg.close()
+        best_mode = min(modes, key=modes.get)
+        tot_nnz = sum(A.nnz for A, _ in [(r[0], r[1]) for r in lv])
+        tot_bytes = sum(r["bytes"] for r in recs_ml)
+        t_step = modes[best_mode]
+        side["multilevel_galerkin27_160^3_f64"] = {
+            "levels": len(lv), "nnz": tot_nnz, "step_ms": round(t_step, 5), "mode": best_mode,
+            "mode_ms": {k: round(v, 5) for k, v in modes.items()},
+            "gflops": round(2.0 * tot_nnz / (t_step * 1e-3) / 1e9, 1),
+            "alg_gbs": round(tot_bytes / (t_step * 1e-3) / 1e9, 1),
+            "frac": round(tot_bytes / (t_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "level0": recs_ml[0],
+            "levels_kernels": [r["kernel"] for r in recs_ml],
+            "plain_csr_ms": round(sum(r["plain_ms"] for r in recs_ml), 4)}
+        log(f"side config multilevel: {side['multilevel_galerkin27_160^3_f64']}")
+        for r in lv:
+            r[2].close()
+            r[3].close()
+        del lv, tuned_l, xs_l, ys_l
+
+    # per storage precision (the headline mixes float32- and float64-stored
+    # matrices; the paper reports single and double precision apart)
+    by_storage = {}
+    for dtn in ("float32", "float64"):
+        sel = [r["rec"] for r in recs if r["rec"]["dtype"] == dtn]
+        if sel:
+            ms = sum(x["tuned_ms"] for x in sel)
+            byt = sum(x["bytes"] for x in sel)
+            by_storage[dtn] = {
+                "matrices": len(sel),
+                "gflops": round(sum(2.0 * x["nnz"] for x in sel) / (ms * 1e-3) / 1e9, 1),
+                "alg_gbs": round(byt / (ms * 1e-3) / 1e9, 1),
+                "frac": round(byt / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "plain_csr_gflops": round(sum(2.0 * x["nnz"] for x in sel) /
+                                          (sum(x["plain_ms"] for x in sel) * 1e-3) / 1e9, 2)
+                if all(x.get("plain_ms") for x in sel) else None}
+    # Equation 2 per plan: calls to pay back the planning time against plain
+    # CSR, with (tuned) and without (selection only) the parameter search
+    be_t, be_u = [], []
+    for r in recs:
+        q = r["rec"]
+        if q.get("plain_ms") and q["plan_ms"] > 0:
+            be_t.append(workloads.break_even_calls(q["plan_ms"], q["plain_ms"], q["tuned_ms"]))
+            be_u.append(workloads.break_even_calls(q["plan_ms"] - q["tune_ms"], q["plain_ms"],
+                                                   q["tuned_ms"]))
+    break_even = None
+    if be_t:
+        break_even = {"median_calls_tuned_plans": round(float(np.median(be_t)), 2),
+                      "median_calls_selection_only": round(float(np.median(be_u)), 2),
+                      "p90_calls_tuned_plans": round(float(np.percentile(be_t, 90)), 2),
+                      "definition": "t_plan / (t_plain_csr - t_tuned) per plan (Equation 2); "
+                                    "selection only: t_plan - t_tune over the same run times",
+                      "paper": "n >= 29 calls from a plan cost of 19 CSR SpMVs and a 3x "
+                               "speedup (x86 CPUs)"}
 
     workload_name = {"sweep": "sweep200_f32_f64", "large": "zipf8M_f32+lap7_256^3_f64",
                      "mixed": "mixed_lap7_128^3+zipf_f64_f32",
@@ -645,6 +846,12 @@ def main():
         "hbm_frac_peak": round(hbm_gbs / HBM_PEAK_GBS, 4),
         "gbs_by_working_set": by_ws,
         "stream_copy_gbs": round(copy_gbs, 1),
+        "achievable_gbs": round(read_gbs, 1),
+        "achievable_probe": "16-byte non-temporal loads of 1 GiB, 16 bytes written per "
+                            "thread (read:write 256:1)",
+        "by_storage": by_storage,
+        "break_even": break_even,
+        "configs": side,
         "plain_csr_gflops": round(flops / (plain_ms_step * 1e-3) / 1e9, 3) if plain_ms_step else None,
         "tuned_vs_plain": round(speedup, 4) if speedup else None,
         "hit_rate": round(hit_rate, 4) if hit_rate is not None else None,

@@ -250,6 +250,14 @@ typedef struct {
                                    5% of the fastest); <= 0: default 0.98  */
     spmv_allocator allocator;   /* plan memory (see spmv_allocator); EINVAL
                                    unless both callbacks or neither are set */
+    int32_t time_baseline;      /* 1: after planning, time the chosen kernel
+                                   and the plain CSR kernel (one thread per
+                                   row, on the caller's CSR) and report the
+                                   break-even call count of Equation 2 in
+                                   spmv_plan_info (t_run_ms, t_plain_ms,
+                                   break_even_calls); 0: not timed         */
+    int32_t log;                /* 1: print a one-line plan summary on
+                                   stderr when the plan is created          */
 } spmv_plan_opts;
 
 /* Feature parameters of Table 3 (Section 4) plus the selector's extras.
@@ -312,6 +320,12 @@ typedef struct {
                                            64; tiles: the most of any row
                                            block, 8-64), else 0             */
     int64_t long_rows;                  /* rows taken by that kernel        */
+    /* opts.time_baseline = 1 (else -1): median time of one run of the plan
+     * and of the plain CSR kernel on the same matrix, and the break-even
+     * call count of Equation 2, t_plan_ms / (t_plain_ms - t_run_ms): the
+     * number of calls after which planning has paid for itself (+inf when
+     * the plan is not faster than plain CSR). */
+    double t_run_ms, t_plain_ms, break_even_calls;
 } spmv_plan_info;
 
 typedef struct spmv_plan_s *spmv_plan_t;
@@ -319,6 +333,20 @@ typedef struct spmv_batch_s *spmv_batch_t;
 
 /* Fill `opts` with defaults.  Always OK. */
 spmv_status spmv_plan_opts_default(spmv_plan_opts *opts);
+
+/* Environment overrides (an interface convention, not from the paper),
+ * applied by spmv_plan_create to its options and exported so that callers
+ * can see the options in effect.  Host only, no device work.
+ *   SPMV_SELECTOR  rules | mlp | exhaustive | a kernel name (forced), e.g.
+ *                  csr_adaptive (spmv_kernel_name); mlp is ignored, with a
+ *                  note on stderr, when opts->model is NULL
+ *   SPMV_TAU       confidence threshold (a float >= 0)
+ *   SPMV_LOG       1 / 0: opts->log
+ * Unset or empty variables leave the field alone; an unparsable value is
+ * ignored with a note on stderr.  The weights file and the autotune cache
+ * (SPMV_WEIGHTS, SPMV_AUTOTUNE_CACHE) belong to the Python layer.
+ * EINVAL if opts is NULL. */
+spmv_status spmv_plan_opts_apply_env(spmv_plan_opts *opts);
 
 /* Validate the CSR (Section 3 input), extract features (Section 4), choose a
  * kernel (Sections 5-6), convert into plan-owned device buffers and return
@@ -490,6 +518,15 @@ spmv_status spmv_batch_destroy(spmv_batch_t batch);
 /* Achievable-bandwidth probe: dst_dev[i] = src_dev[i] for `bytes` bytes
  * (multiple of 16, 16-byte aligned).  Asynchronous. */
 spmv_status spmv_stream_copy(void *dst_dev, const void *src_dev, size_t bytes, void *stream);
+
+/* Read-dominant bandwidth probe, the traffic shape of SpMV (the matrix is
+ * read, y is a small fraction written): streams `bytes` bytes of src_dev
+ * (multiple of 16, 16-byte aligned) with 16-byte non-temporal loads and
+ * writes one 16-byte word per thread of a fixed grid to out_dev (the
+ * 32-bit words of the thread's loads added, so no load can be dropped);
+ * out_dev must hold spmv_stream_read_out_bytes() bytes.  Asynchronous. */
+spmv_status spmv_stream_read(const void *src_dev, size_t bytes, void *out_dev, void *stream);
+size_t spmv_stream_read_out_bytes(void);
 
 /* Random-gather ceiling probe, the memory pattern of a CSR row loop (a
  * coalesced value stream, a coalesced index stream and one gather per

@@ -14,14 +14,16 @@
  * All arithmetic is IEEE binary64; float32 inputs are widened exactly by the
  * caller before the call.
  *
- * Two modes:
+ * Modes:
  *   accurate  error-free products (TwoProduct via fma) and Neumaier
  *             compensated summation in storage order, plus (|A||x|)_i; this
  *             is the value every parity test compares against.
  *   plain     a naive sequential sum per row, rows split over OpenMP threads
  *             so that each thread holds about the same number of nonzeros,
  *             rounded to whole rows (the paper's multithreaded scheme,
- *             Section 6).  It exists to time a straightforward CPU SpMV.
+ *             Section 6).  It exists to time a straightforward CPU SpMV;
+ *             plain_f32 is the same on float32 storage (binary64 sums,
+ *             each row rounded once).
  *
  * Build: gcc -O2 -ffp-contract=off -fopenmp -shared -fPIC (no fused
  * multiply-add is introduced behind the code's back; fma() below is
@@ -117,6 +119,29 @@ void ref_spmv_plain(int64_t m, const int64_t *row_ptr, const int32_t *col,
             for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
                 s += val[p] * x[col[p]];
             y[i] = s;
+        }
+    }
+}
+
+/* Plain mode on float32 storage (values and x in binary32, as the float32
+ * matrices the benchmark times): each product and the running sum in
+ * binary64, the row result rounded once to binary32.  For timing. */
+void ref_spmv_plain_f32(int64_t m, const int64_t *row_ptr, const int32_t *col,
+                        const float *val, const float *x, float *y, int nthreads)
+{
+    if (nthreads < 1)
+        nthreads = 1;
+    int64_t nnz = row_ptr[m];
+#pragma omp parallel num_threads(nthreads)
+    {
+        int t = omp_get_thread_num(), T = omp_get_num_threads();
+        int64_t r0 = t == 0 ? 0 : row_of(m, row_ptr, (nnz * t) / T);
+        int64_t r1 = t == T - 1 ? m : row_of(m, row_ptr, (nnz * (t + 1)) / T);
+        for (int64_t i = r0; i < r1; ++i) {
+            double s = 0.0;
+            for (int64_t p = row_ptr[i]; p < row_ptr[i + 1]; ++p)
+                s += (double)val[p] * (double)x[col[p]];
+            y[i] = (float)s;
         }
     }
 }

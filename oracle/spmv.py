@@ -32,6 +32,8 @@ def _load():
         lib.ref_spmv_rows.restype = None
         lib.ref_spmv_plain.argtypes = [i64, p, p, p, p, p, ctypes.c_int]
         lib.ref_spmv_plain.restype = None
+        lib.ref_spmv_plain_f32.argtypes = [i64, p, p, p, p, p, ctypes.c_int]
+        lib.ref_spmv_plain_f32.restype = None
         lib.ref_max_threads.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -77,6 +79,21 @@ def spmv_plain(row_ptr, col, val, x, nthreads=None, out=None):
     if nthreads is None:
         nthreads = max_threads()
     _load().ref_spmv_plain(m, _ptr(rp), _ptr(c), _ptr(v), _ptr(xx), _ptr(y), int(nthreads))
+    return y
+
+
+def spmv_plain_f32(row_ptr, col, val, x, nthreads=None, out=None):
+    """The plain mode on float32 values and x (float64 sums, rounded once
+    per row to float32): the CPU timing of float32-stored matrices."""
+    rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    c = np.ascontiguousarray(col, dtype=np.int32)
+    v = np.ascontiguousarray(val, dtype=np.float32)
+    xx = np.ascontiguousarray(x, dtype=np.float32)
+    m = rp.size - 1
+    y = out if out is not None else np.empty(m, dtype=np.float32)
+    if nthreads is None:
+        nthreads = max_threads()
+    _load().ref_spmv_plain_f32(m, _ptr(rp), _ptr(c), _ptr(v), _ptr(xx), _ptr(y), int(nthreads))
     return y
 
 

@@ -55,7 +55,8 @@ class spmv_plan_opts(ctypes.Structure):
                 ("measure_topk", i32), ("timing_reps", i32), ("disable_mask", u32),
                 ("mem_cap_bytes", u64), ("model", vp), ("autotune", i32), ("use_params", i32),
                 ("params", spmv_params), ("segments", i32), ("staged", i32),
-                ("stage_conf", f32), ("allocator", spmv_allocator)]
+                ("stage_conf", f32), ("allocator", spmv_allocator), ("time_baseline", i32),
+                ("log", i32)]
 
 
 class spmv_features(ctypes.Structure):
@@ -78,11 +79,13 @@ class spmv_plan_info(ctypes.Structure):
                 ("mlp_input", f32 * 12), ("rules_kernel", i32),
                 ("out_of_domain", i32), ("t_tune_ms", f64), ("bcsr_blocks", i64),
                 ("n_segments", i32), ("feature_stage", i32), ("stage_confidence", f32),
-                ("tune_rejected", i32), ("long_lanes", i32), ("long_rows", i64)]
+                ("tune_rejected", i32), ("long_lanes", i32), ("long_rows", i64),
+                ("t_run_ms", f64), ("t_plain_ms", f64), ("break_even_calls", f64)]
 
 
 _SIGS = {
     "spmv_plan_opts_default": (i32, [vp]),
+    "spmv_plan_opts_apply_env": (i32, [vp]),
     "spmv_plan_create": (i32, [vp, vp, vp, vp]),
     "spmv_run": (i32, [vp, vp, vp, vp]),
     "spmv_plan_info_get": (i32, [vp, vp]),
@@ -108,6 +111,8 @@ _SIGS = {
     "spmv_batch_tune": (i32, [vp, vp, vp, i32, vp, vp]),
     "spmv_batch_shape": (i32, [vp, vp, vp]),
     "spmv_stream_copy": (i32, [vp, vp, ctypes.c_size_t, vp]),
+    "spmv_stream_read": (i32, [vp, ctypes.c_size_t, vp, vp]),
+    "spmv_stream_read_out_bytes": (ctypes.c_size_t, []),
     "spmv_gather_probe": (i32, [vp, i64, vp, vp, i64, i32, vp, vp]),
     "spmv_gather_probe_threads": (i64, []),
     "spmv_status_string": (ctypes.c_char_p, [i32]),

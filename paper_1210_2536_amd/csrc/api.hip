@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <limits>
 #include <memory>
@@ -1182,20 +1183,20 @@ spmv_status run_variant(const spmv_plan_s &P, const Variant &V, const void *x, v
 constexpr double kTimeBatchMs = 0.05;
 constexpr int kTimeBatchMax = 64;
 
-spmv_status time_variant(const spmv_plan_s &P, const Variant &V, const void *x, void *y,
-                         int reps, hipStream_t s, double *ms) {
+template <typename Run>
+spmv_status time_calls(Run run, int reps, hipStream_t s, double *ms) {
     hipEvent_t a, b;
     SMAT_HIP(hipEventCreate(&a));
     SMAT_HIP(hipEventCreate(&b));
     auto batch = [&](int inner, float *f) -> spmv_status {
         (void)hipEventRecord(a, s);
-        for (int i = 0; i < inner; ++i) SMAT_TRY(run_variant(P, V, x, y, s));
+        for (int i = 0; i < inner; ++i) SMAT_TRY(run());
         (void)hipEventRecord(b, s);
         if (hipEventSynchronize(b) != hipSuccess) return hip_fail(hipGetLastError(), "timing");
         (void)hipEventElapsedTime(f, a, b);
         return SPMV_OK;
     };
-    spmv_status st = run_variant(P, V, x, y, s);
+    spmv_status st = run();
     float probe = 0;
     if (st == SPMV_OK) st = batch(1, &probe);
     int inner = 1;
@@ -1214,6 +1215,11 @@ spmv_status time_variant(const spmv_plan_s &P, const Variant &V, const void *x, 
     std::sort(t.begin(), t.end());
     *ms = t.empty() ? 0.0 : t[t.size() / 2];
     return SPMV_OK;
+}
+
+spmv_status time_variant(const spmv_plan_s &P, const Variant &V, const void *x, void *y,
+                         int reps, hipStream_t s, double *ms) {
+    return time_calls([&] { return run_variant(P, V, x, y, s); }, reps, s, ms);
 }
 
 // Parameter points tried by the autotuner for one kernel (the paper's offline
@@ -1481,6 +1487,54 @@ extern "C" spmv_status spmv_plan_opts_default(spmv_plan_opts *o) {
     return SPMV_OK;
 }
 
+extern "C" spmv_status spmv_plan_opts_apply_env(spmv_plan_opts *o) {
+    if (!o) {
+        set_error("opts is NULL");
+        return SPMV_EINVAL;
+    }
+    const char *v = std::getenv("SPMV_SELECTOR");
+    if (v && *v) {
+        int k = -1;
+        for (int i = 0; i < SPMV_K_COUNT; ++i)
+            if (!std::strcmp(v, spmv_kernel_name(i))) k = i;
+        if (!std::strcmp(v, "rules")) {
+            o->selector = SPMV_SELECT_RULES;
+        } else if (!std::strcmp(v, "mlp")) {
+            if (o->model)
+                o->selector = SPMV_SELECT_MLP;
+            else
+                std::fprintf(stderr, "[spmv] SPMV_SELECTOR=mlp ignored: no model given\n");
+        } else if (!std::strcmp(v, "exhaustive")) {
+            o->selector = SPMV_SELECT_EXHAUSTIVE;
+        } else if (k >= 0) {
+            o->selector = SPMV_SELECT_FORCED;
+            o->force_kernel = k;
+        } else {
+            std::fprintf(stderr, "[spmv] SPMV_SELECTOR=%s ignored: not rules, mlp, exhaustive "
+                                 "or a kernel name\n", v);
+        }
+    }
+    v = std::getenv("SPMV_TAU");
+    if (v && *v) {
+        char *end = nullptr;
+        const double t = std::strtod(v, &end);
+        if (end && *end == 0 && std::isfinite(t) && t >= 0)
+            o->confidence_tau = (float)t;
+        else
+            std::fprintf(stderr, "[spmv] SPMV_TAU=%s ignored: not a number >= 0\n", v);
+    }
+    v = std::getenv("SPMV_LOG");
+    if (v && *v) {
+        if (!std::strcmp(v, "1"))
+            o->log = 1;
+        else if (!std::strcmp(v, "0"))
+            o->log = 0;
+        else
+            std::fprintf(stderr, "[spmv] SPMV_LOG=%s ignored: 0 or 1\n", v);
+    }
+    return SPMV_OK;
+}
+
 static spmv_status check_csr(const spmv_csr *A) {
     if (!A) {
         set_error("csr is NULL");
@@ -1558,8 +1612,67 @@ __global__ void k_offset_rows(int64_t m, int32_t *__restrict__ rp, int32_t base)
 }
 }  // namespace
 
-extern "C" spmv_status spmv_plan_create(const spmv_csr *A, const spmv_plan_opts *opts,
-                                        void *stream, spmv_plan_t *out);
+static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opts_in,
+                                    hipStream_t s, spmv_plan_t *out);
+
+// Equation 2 of a finished plan (opts.time_baseline): the median time of one
+// run of the plan and of the plain CSR kernel (one thread per row) on the
+// caller's CSR, both on x = 1, and the calls after which the planning time
+// is paid back, t_plan / (t_plain - t_run).
+static spmv_status time_baseline(spmv_plan_s *P, const spmv_csr *A, int reps, hipStream_t s) {
+    spmv_plan_info &I = P->info;
+    Dev xs, ys;
+    SMAT_TRY(xs.alloc((size_t)P->elt * std::max<int64_t>(1, P->n)));
+    SMAT_TRY(ys.alloc((size_t)P->elt * std::max<int64_t>(1, P->m)));
+    if (P->n) k_fill_one<<<(unsigned)((P->n + 255) / 256), 256, 0, s>>>(P->n, P->elt, xs.p);
+    SMAT_LAUNCHED("fill_one");
+    double t_run = 0, t_plain = 0;
+    SMAT_TRY(time_calls([&] { return spmv_run(P, xs.p, ys.p, s); }, reps, s, &t_run));
+    SMAT_TRY(time_calls(
+        [&] {
+            return run_csr_scalar(P->elt, A->m, A->row_ptr_dev, A->col_dev, A->val_dev, xs.p,
+                                  ys.p, 256, s);
+        },
+        reps, s, &t_plain));
+    I.t_run_ms = t_run;
+    I.t_plain_ms = t_plain;
+    I.break_even_calls = t_plain > t_run ? I.t_plan_ms / (t_plain - t_run)
+                                         : std::numeric_limits<double>::infinity();
+    return SPMV_OK;
+}
+
+// One line per plan on stderr (opts.log, SPMV_LOG=1).
+static void log_plan(const spmv_plan_s &P) {
+    const spmv_plan_info &I = P.info;
+    static const char *sel[] = {"rules", "mlp", "exhaustive", "forced"};
+    const int su = I.selector_used >= 0 && I.selector_used <= 3 ? I.selector_used : 0;
+    char be[96] = "";
+    if (I.t_run_ms >= 0)
+        std::snprintf(be, sizeof(be), " run=%.4fms plain=%.4fms break_even=%.1f", I.t_run_ms,
+                      I.t_plain_ms, I.break_even_calls);
+    std::fprintf(stderr,
+                 "[spmv] plan m=%lld n=%lld nnz=%lld %s kernel=%s selector=%s conf=%.3f "
+                 "measured=%d stage=%d segments=%d long_rows=%lld plan=%.3fms tune=%.3fms "
+                 "device=%.1fMB%s\n",
+                 (long long)I.m, (long long)I.n, (long long)I.nnz,
+                 I.dtype == SPMV_F64 ? "f64" : "f32",
+                 I.n_segments ? "segmented" : spmv_kernel_name(I.kernel), sel[su],
+                 (double)I.confidence, I.n_measured, I.feature_stage, I.n_segments,
+                 (long long)I.long_rows, I.t_plan_ms, I.t_tune_ms,
+                 (double)I.device_bytes / 1048576.0, be);
+}
+
+// Options in effect for plan creation: the caller's (or the defaults)
+// with the environment overrides applied.
+static spmv_plan_opts effective_opts(const spmv_plan_opts *opts) {
+    spmv_plan_opts o;
+    if (opts)
+        o = *opts;
+    else
+        spmv_plan_opts_default(&o);
+    spmv_plan_opts_apply_env(&o);
+    return o;
+}
 
 // Segmented plan (Section 6: the matrix divided by rows into sub-matrices of
 // equal nonzero counts, each tuned on its own): rows cut where the running
@@ -1607,6 +1720,8 @@ static spmv_status plan_create_segments(const spmv_csr *A, const spmv_plan_opts 
     cut.push_back(A->m);
     spmv_plan_opts co = opts;
     co.segments = 0;
+    co.time_baseline = 0;   // reported for the whole plan
+    co.log = 0;
     Dev rb;
     SMAT_TRY(rb.alloc(sizeof(int32_t) * (size_t)(A->m + 1)));
     for (size_t k = 0; k + 1 < cut.size(); ++k) {
@@ -1624,7 +1739,7 @@ static spmv_status plan_create_segments(const spmv_csr *A, const spmv_plan_opts 
         c.val_dev = (const char *)A->val_dev + (size_t)P->elt * base;
         c.dtype = A->dtype;
         spmv_plan_t child = nullptr;
-        SMAT_TRY(spmv_plan_create(&c, &co, s, &child));
+        SMAT_TRY(plan_create_impl(&c, &co, s, &child));
         P->seg.push_back(child);
         P->seg_row0.push_back(r0);
         I.device_bytes += child->info.device_bytes;
@@ -1635,6 +1750,9 @@ static spmv_status plan_create_segments(const spmv_csr *A, const spmv_plan_opts 
     I.n_segments = (int32_t)P->seg.size();
     I.t_plan_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() -
                                                             t_start).count();
+    I.t_run_ms = I.t_plain_ms = I.break_even_calls = -1.0;
+    if (opts.time_baseline) SMAT_TRY(time_baseline(P.get(), A, opts.timing_reps, s));
+    if (opts.log) log_plan(*P);
     *out = P.release();
     return SPMV_OK;
 }
@@ -1956,6 +2074,9 @@ static spmv_status plan_create_impl(const spmv_csr *A, const spmv_plan_opts *opt
     I.t_select_ms = std::chrono::duration<double, std::milli>(t_conv0 - t_sel0).count();
     I.t_convert_ms = std::chrono::duration<double, std::milli>(t_end - t_conv0).count();
     I.t_plan_ms = std::chrono::duration<double, std::milli>(t_end - t_start).count();
+    I.t_run_ms = I.t_plain_ms = I.break_even_calls = -1.0;
+    if (opts.time_baseline) SMAT_TRY(time_baseline(P.get(), A, opts.timing_reps, s));
+    if (opts.log) log_plan(*P);
     *out = P.release();
     return SPMV_OK;
 }
@@ -1968,7 +2089,8 @@ extern "C" spmv_status spmv_plan_create(const spmv_csr *A, const spmv_plan_opts 
     }
     *out = nullptr;
     try {
-        return plan_create_impl(A, opts, (hipStream_t)stream, out);
+        const spmv_plan_opts o = effective_opts(opts);
+        return plan_create_impl(A, &o, (hipStream_t)stream, out);
     } catch (const std::bad_alloc &) {
         set_error("host allocation failed");
         return SPMV_ENOMEM;
@@ -2293,6 +2415,16 @@ extern "C" spmv_status spmv_gather_probe(const void *table, int64_t table_len, c
         return SPMV_EINVAL;
     }
     return run_gather_probe(table, idx, val, count, elt, out, (hipStream_t)stream);
+}
+
+extern "C" size_t spmv_stream_read_out_bytes(void) { return stream_read_out_bytes(); }
+
+extern "C" spmv_status spmv_stream_read(const void *src, size_t bytes, void *out, void *stream) {
+    if (!src || !out || bytes % 16 || (uintptr_t)src % 16 || (uintptr_t)out % 16) {
+        set_error("stream_read needs 16-byte aligned buffers and a multiple of 16 bytes");
+        return SPMV_EINVAL;
+    }
+    return run_stream_read(src, bytes, out, (hipStream_t)stream);
 }
 
 extern "C" spmv_status spmv_stream_copy(void *dst, const void *src, size_t bytes, void *stream) {

@@ -160,6 +160,28 @@ __global__ __launch_bounds__(256) void k_stream_copy(const v4u *__restrict__ src
     for (; i < n; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
+// Read-dominant bandwidth probe: a fixed grid streams the source with
+// 16-byte non-temporal loads, four in flight per thread, and each thread
+// writes the word-wise sum of what it loaded (so no load can be dropped).
+constexpr int kReadProbeBlocks = 256 * 8, kReadProbeThreads = 256;
+
+__global__ __launch_bounds__(kReadProbeThreads) void k_stream_read(const v4u *__restrict__ src,
+                                                                   int64_t n,
+                                                                   v4u *__restrict__ out) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    v4u acc = {0u, 0u, 0u, 0u};
+    for (; i + 3 * stride < n; i += 4 * stride) {
+        v4u a = __builtin_nontemporal_load(src + i);
+        v4u b = __builtin_nontemporal_load(src + i + stride);
+        v4u c = __builtin_nontemporal_load(src + i + 2 * stride);
+        v4u d = __builtin_nontemporal_load(src + i + 3 * stride);
+        acc += a + b + c + d;
+    }
+    for (; i < n; i += stride) acc += __builtin_nontemporal_load(src + i);
+    out[blockIdx.x * (int64_t)blockDim.x + threadIdx.x] = acc;
+}
+
 // Random-gather probe: thread t adds val[i] * table[idx[i]] over i = t,
 // t + G, t + 2 G, ... (G threads in the grid) in that order, four entries per
 // trip -- the memory pattern of a CSR row loop (two coalesced streams and
@@ -199,6 +221,16 @@ spmv_status run_gather_probe(const void *table, const int32_t *idx, const void *
         k_gather_probe<float><<<g, 256, 0, s>>>((const float *)table, idx, (const float *)val,
                                                 count, (float *)out);
     SMAT_LAUNCHED("gather_probe");
+    return SPMV_OK;
+}
+
+size_t stream_read_out_bytes() { return (size_t)kReadProbeBlocks * kReadProbeThreads * 16; }
+
+spmv_status run_stream_read(const void *src, size_t bytes, void *out, hipStream_t s) {
+    k_stream_read<<<kReadProbeBlocks, kReadProbeThreads, 0, s>>>((const v4u *)src,
+                                                                  (int64_t)(bytes / 16),
+                                                                  (v4u *)out);
+    SMAT_LAUNCHED("stream_read");
     return SPMV_OK;
 }
 

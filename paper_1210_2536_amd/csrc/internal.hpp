@@ -220,6 +220,8 @@ spmv_status features_in_region(const spmv_csr *A, spmv_features *out, hipStream_
 
 // ----------------------------------------------------------------- misc
 spmv_status run_stream_copy(void *dst, const void *src, size_t bytes, hipStream_t s);
+size_t stream_read_out_bytes();
+spmv_status run_stream_read(const void *src, size_t bytes, void *out, hipStream_t s);
 int64_t gather_probe_threads();
 spmv_status run_gather_probe(const void *table, const int32_t *idx, const void *val,
                              int64_t count, int elt, void *out, hipStream_t s);

@@ -158,15 +158,23 @@ DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weig
                                "selector_gfx950.json")
 
 
+def weights_path():
+    """The selector weights file: $SPMV_WEIGHTS when set (non-empty), else the
+    shipped one."""
+    return os.environ.get("SPMV_WEIGHTS") or DEFAULT_WEIGHTS
+
+
 def default_selector():
-    """The shipped trained selector, or None if absent or trained for another kernel set."""
-    if not os.path.exists(DEFAULT_WEIGHTS):
+    """The trained selector of weights_path(), or None if the file is absent
+    or was trained for another kernel set."""
+    path = weights_path()
+    if not os.path.exists(path):
         return None
-    with open(DEFAULT_WEIGHTS) as fh:
+    with open(path) as fh:
         meta = json.load(fh)
     if meta.get("n_out") != C.K_COUNT or list(meta.get("kernels", [])) != list(C.KERNELS):
         return None
-    return Selector.load(DEFAULT_WEIGHTS)
+    return Selector.load(path)
 
 
 class TorchAllocator:
@@ -238,7 +246,7 @@ class Plan:
     def __init__(self, row_ptr, col, val, n=None, selector="rules", model=None,
                  tau=None, topk=None, reps=None, disable=(), mem_cap=0, params=None,
                  autotune=False, segments=0, staged=True, stage_conf=None,
-                 allocator="torch", stream=None):
+                 allocator="torch", stream=None, time_baseline=False, log=False):
         torch = _torch()
         m = row_ptr.numel() - 1
         n = m if n is None else int(n)
@@ -269,6 +277,8 @@ class Plan:
         o.disable_mask = mask
         o.mem_cap_bytes = int(mem_cap)
         o.autotune = 1 if autotune else 0
+        o.time_baseline = 1 if time_baseline else 0
+        o.log = 1 if log else 0
         o.segments = int(segments)
         o.staged = 1 if staged else 0
         if stage_conf is not None:
@@ -419,7 +429,10 @@ class TuneCache:
     KEY_FEATURES = ("m", "n", "nnz", "sum_rd", "sum_rd2", "max_rd", "min_rd", "ndiags",
                     "ntdiags", "bandwidth", "blocks4")
 
-    def __init__(self, path):
+    def __init__(self, path=None):
+        path = path or os.environ.get("SPMV_AUTOTUNE_CACHE")
+        if not path:
+            raise ValueError("TuneCache needs a path (or $SPMV_AUTOTUNE_CACHE)")
         self.path = path
         self.entries = {}
         if os.path.exists(path):
@@ -503,6 +516,19 @@ class Batch:
 
     def __del__(self):
         self.close()
+
+
+def stream_read(src, out=None, stream=None):
+    """spmv_stream_read over a device tensor (16-byte multiple); returns the
+    per-thread word sums (uint8 tensor of spmv_stream_read_out_bytes())."""
+    torch = _torch()
+    nbytes = src.numel() * src.element_size()
+    if out is None:
+        out = torch.empty(int(C.lib().spmv_stream_read_out_bytes()), dtype=torch.uint8,
+                          device=src.device)
+    C.check(C.lib().spmv_stream_read(_ptr(src), nbytes, _ptr(out), _stream_handle(stream)),
+            "spmv_stream_read")
+    return out
 
 
 def stream_copy(dst, src, stream=None):

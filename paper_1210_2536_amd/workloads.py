@@ -40,6 +40,14 @@ def algorithmic_bytes(fmt, m, n, nnz, s, K=0, D=0, blocks=0):
     raise ValueError(fmt)
 
 
+def break_even_calls(t_plan_ms, t_plain_ms, t_tuned_ms):
+    """Equation 2: calls after which a plan that took t_plan_ms to build has
+    paid for itself against plain CSR, t_plan / (t_plain - t_tuned) (inf
+    when the tuned SpMV is not faster)."""
+    gain = t_plain_ms - t_tuned_ms
+    return t_plan_ms / gain if gain > 0 else float("inf")
+
+
 def plan_bytes(info):
     """Algorithmic bytes of one run of a plan, from its report."""
     s = 8 if info["dtype"] == 1 else 4

@@ -196,3 +196,29 @@ def test_rows_subset_matches_full():
     rows = np.array([0, 17, 4999, 2500])
     ys, as_ = O.spmv_rows(A.row_ptr, A.col, A.val, x, rows)
     assert np.array_equal(ys, y[rows]) and np.array_equal(as_, a[rows])
+
+
+def test_plain_f32_mode_rounds_the_float64_sum_once():
+    """The float32-storage plain mode: float32 values and x, float64 sums,
+    each row rounded once.  Pinned by the exact product on the same widened
+    data (error <= 2^-24 |y| + the float64 chain's, far below 2e-6 (|A||x|)),
+    by exact integer stencils (bitwise) and by thread-count independence."""
+    A = S.zipf_g2(np.random.default_rng([9, 32]), 20_000)
+    x = S.uniform_vector(A.n, 5).astype(np.float32)
+    v32 = A.val.astype(np.float32)
+    y_acc, absax = O.spmv_accurate(A.row_ptr, A.col, v32.astype(np.float64), x.astype(np.float64))
+    y1 = O.spmv_plain_f32(A.row_ptr, A.col, v32, x, nthreads=1)
+    y3 = O.spmv_plain_f32(A.row_ptr, A.col, v32, x, nthreads=3)
+    assert y1.dtype == np.float32 and np.array_equal(y1, y3)
+    kmax = int(np.diff(A.row_ptr).max())
+    err = np.abs(y1.astype(np.float64) - y_acc)
+    assert np.all(err <= 2.0 ** -24 * np.abs(y_acc) + (kmax + 1) * 1.2e-16 * absax + 1e-300)
+    # 7-point stencil on i^2 + j^2 + k^2: integers, exact in float32 storage
+    g = 12
+    B = S.stencil_7pt(g)
+    r = np.arange(B.n)
+    i, j, k = r // (g * g), (r // g) % g, r % g
+    xp = (i * i + j * j + k * k).astype(np.float32)
+    yb = O.spmv_plain_f32(B.row_ptr, B.col, B.val.astype(np.float32), xp)
+    ref, _ = O.spmv_accurate(B.row_ptr, B.col, B.val, xp.astype(np.float64))
+    assert np.array_equal(yb.astype(np.float64), ref)
