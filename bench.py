@@ -451,21 +451,24 @@ def main():
         cps.append(e0.elapsed_time(e1))
     copy_gbs = 2.0 * cp_src.numel() * 4 / (float(np.median(cps[1:])) * 1e-3) / 1e9
     del cp_dst
+    del cp_src
     # read-dominant probe, the traffic shape of SpMV: 16-byte non-temporal
-    # loads of 1 GiB, one 16-byte word written per thread (256:1 here)
+    # loads of 8 GiB (long enough that the launch's ramp and tail do not
+    # count), one 16-byte word written per thread
+    rd_src = torch.zeros(1 << 31, dtype=torch.float32, device=dev)
     rd_out = None
     rds = []
     for _ in range(6):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        rd_out = stream_read(cp_src, out=rd_out)
+        rd_out = stream_read(rd_src, out=rd_out)
         e1.record()
         torch.cuda.synchronize()
         rds.append(e0.elapsed_time(e1))
-    read_bytes = cp_src.numel() * 4 + rd_out.numel()
+    read_bytes = rd_src.numel() * 4 + rd_out.numel()
     read_gbs = read_bytes / (float(np.median(rds[1:])) * 1e-3) / 1e9
     log(f"copy probe {copy_gbs:.0f} GB/s, read probe {read_gbs:.0f} GB/s")
-    del cp_src, rd_out
+    del rd_src, rd_out
     # uniform random gathers: the CSR row loop's memory pattern (value and
     # index streams, one gather per entry) from a 1 MiB table, which every
     # XCD's L2 holds, with no two lanes sharing a cache line on purpose --
@@ -847,8 +850,8 @@ def main():
         "gbs_by_working_set": by_ws,
         "stream_copy_gbs": round(copy_gbs, 1),
         "achievable_gbs": round(read_gbs, 1),
-        "achievable_probe": "16-byte non-temporal loads of 1 GiB, 16 bytes written per "
-                            "thread (read:write 256:1)",
+        "achievable_probe": "16-byte non-temporal loads of 8 GiB, 16 bytes written per "
+                            "thread (read:write 1024:1)",
         "by_storage": by_storage,
         "break_even": break_even,
         "configs": side,

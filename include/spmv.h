@@ -489,10 +489,11 @@ spmv_status spmv_mlp_adam(float *params_dev, const float *grad_dev, float *adam_
  * plans in one launch (mode 0, persistent work-queue kernel) or as one
  * captured HIP graph (mode 1).  Plans stay owned by the caller and must
  * outlive the batch.  Persistent mode covers CSR_SCALAR, CSR_VECTOR,
- * CSR_ADAPTIVE (unless rows were split into segments), ELL, DIA and
- * DIA_DIRECT levels, each with its plan's tile shape; levels with other
- * kernels are launched separately on the same stream, after the persistent
- * kernel.  Mode 0 takes 1..16 plans of one dtype; mode 1 takes 1..4096
+ * CSR_ADAPTIVE (unless rows were split into segments or long rows use
+ * their own kernel), ELL, DIA, DIA_DIRECT and BCSR levels, each with its
+ * plan's tile shape, in a kernel compiled for just the level kinds present;
+ * levels with other kernels are launched separately on the same stream,
+ * after the persistent kernel.  Mode 0 takes 1..16 plans of one dtype; mode 1 takes 1..4096
  * plans of any dtypes and kernels (every spmv_run of the batch, in order,
  * captured on the first run and again whenever the vectors change).
  * EINVAL otherwise. */

@@ -24,16 +24,17 @@ constexpr int kPBlock = 256;   // persistent workgroup size
 constexpr int kPDiaRpt = 4;    // rows per thread of a DIA tile
 
 enum LevelKind {
-    LK_SCALAR = 0, LK_VECTOR = 1, LK_ADAPTIVE = 2, LK_ELL = 3, LK_DIA = 4, LK_DIA_DIRECT = 5
+    LK_SCALAR = 0, LK_VECTOR = 1, LK_ADAPTIVE = 2, LK_ELL = 3, LK_DIA = 4, LK_DIA_DIRECT = 5,
+    LK_BCSR = 6
 };
 
 // One level: its kernel kind, the tile shape of its plan (wide: a lane owns
 // 16 bytes of consecutive rows in DIA / ELL) and its arrays.
 struct LevelDesc {
     int kind, lanes, K, D, nwin, nt, wide;
-    int64_t m, n, m_pad, tile_rows, tile_begin;
-    const int32_t *rp, *col, *ecol, *offs, *rows;
-    const void *val, *eval, *data;
+    int64_t m, n, m_pad, tile_rows, tile_begin, mb;
+    const int32_t *rp, *col, *ecol, *offs, *rows, *brp, *bcol;
+    const void *val, *eval, *data, *bval;
     const DiaWindow *win;
     AdaptiveLaunch alaunch;
 };
@@ -53,19 +54,48 @@ __device__ __forceinline__ void vector_tile(const LevelDesc &d, int64_t tile, co
     }
 }
 
+// Level-kind sets the persistent kernel is compiled for (bit k: LevelKind
+// k).  A launch takes the smallest set that holds the kinds of its levels:
+// a kernel carrying only CSR code needs far fewer registers than one that
+// also carries the wide DIA tiles, so more of its waves fit a CU.
+constexpr unsigned kKindsRow = (1u << LK_SCALAR) | (1u << LK_VECTOR);
+constexpr unsigned kKindsCsr = kKindsRow | (1u << LK_ADAPTIVE);
+constexpr unsigned kKindsEll = 1u << LK_ELL;
+constexpr unsigned kKindsDia = (1u << LK_DIA) | (1u << LK_DIA_DIRECT);
+constexpr unsigned kKindsBcsr = 1u << LK_BCSR;
+constexpr unsigned kKindsAll = kKindsCsr | kKindsEll | kKindsDia | kKindsBcsr;
+
+// A tile of a BCSR level: kPBlock / L block rows, L lanes each.
+template <typename T, int L, bool NT>
+__device__ __forceinline__ void bcsr_tile(const LevelDesc &d, int64_t tile, const T *x, T *y) {
+    const int64_t R = tile * (kPBlock / L) + threadIdx.x / L;
+    if constexpr (sizeof(T) == 8) {
+        if constexpr (L >= 8)
+            bcsr_row_coop<L, NT>(R, threadIdx.x & (L - 1), d.mb, d.m, d.n, d.brp, d.bcol,
+                                 (const double *)d.bval, x, y);
+    } else {
+        bcsr_row_lanes<T, L, NT>(R, threadIdx.x & (L - 1), d.mb, d.m, d.n, d.brp, d.bcol,
+                                 (const T *)d.bval, x, y);
+    }
+}
+
 // One (level, tile) work item; the same device functions as the stand-alone
-// kernels, so each row is computed exactly as by the level's own run.
-template <typename T, bool NT>
+// kernels, so each row is computed exactly as by the level's own run.  Only
+// the kinds in KINDS are compiled in (the launch guarantees the levels'
+// kinds are among them).
+template <typename T, bool NT, unsigned KINDS>
 __device__ __forceinline__ void batch_item(const LevelDesc &d, int64_t tile, const T *x, T *y,
                                            T *xs, double *part) {
     constexpr int W = 16 / (int)sizeof(T);
     switch (d.kind) {
     case LK_SCALAR: {
+        if constexpr (!(KINDS & (1u << LK_SCALAR))) break;
         int64_t i = tile * kPBlock + threadIdx.x;
         if (i < d.m) y[i] = (T)csr_row_seq<T>(i, d.rp, d.col, (const T *)d.val, x);
         break;
     }
     case LK_VECTOR:
+        if constexpr (!(KINDS & (1u << LK_VECTOR))) break;
         switch (d.lanes) {
         case 1: vector_tile<T, 1, NT>(d, tile, x, y); break;
         case 2: vector_tile<T, 2, NT>(d, tile, x, y); break;
@@ -77,10 +107,12 @@ __device__ __forceinline__ void batch_item(const LevelDesc &d, int64_t tile, con
         }
         break;
     case LK_ADAPTIVE:
+        if constexpr (!(KINDS & (1u << LK_ADAPTIVE))) break;
         adaptive_block<T, NT>(d.alaunch, (unsigned)tile, d.rows, d.rp, d.col, (const T *)d.val,
                               x, y, part);
         break;
     case LK_ELL:
+        if constexpr (!(KINDS & (1u << LK_ELL))) break;
         if (d.wide) {
             int64_t i0 = (tile * kPBlock + threadIdx.x) * W;
             if (i0 < d.m) {
@@ -97,6 +129,7 @@ __device__ __forceinline__ void batch_item(const LevelDesc &d, int64_t tile, con
         }
         break;
     case LK_DIA:
+        if constexpr (!(KINDS & (1u << LK_DIA))) break;
         if (d.wide)
             dia_tile_lds<T, kPDiaRpt, NT, W>(tile * d.tile_rows, d.m, d.n, d.m_pad, d.offs,
                                              d.nwin, d.win, (const T *)d.data, x, y, xs);
@@ -104,7 +137,20 @@ __device__ __forceinline__ void batch_item(const LevelDesc &d, int64_t tile, con
             dia_tile_lds<T, kPDiaRpt, NT>(tile * d.tile_rows, d.m, d.n, d.m_pad, d.offs, d.nwin,
                                           d.win, (const T *)d.data, x, y, xs);
         break;
+    case LK_BCSR:
+        if constexpr (!(KINDS & (1u << LK_BCSR))) break;
+        switch (d.lanes) {
+        case 1: bcsr_tile<T, 1, NT>(d, tile, x, y); break;
+        case 2: bcsr_tile<T, 2, NT>(d, tile, x, y); break;
+        case 4: bcsr_tile<T, 4, NT>(d, tile, x, y); break;
+        case 8: bcsr_tile<T, 8, NT>(d, tile, x, y); break;
+        case 16: bcsr_tile<T, 16, NT>(d, tile, x, y); break;
+        case 32: bcsr_tile<T, 32, NT>(d, tile, x, y); break;
+        default: bcsr_tile<T, 64, NT>(d, tile, x, y); break;
+        }
+        break;
     default:
+        if constexpr (!(KINDS & (1u << LK_DIA_DIRECT))) break;
         if (d.wide)
             dia_tile_direct<T, kPDiaRpt, NT, W>(tile * d.tile_rows, d.m, d.n, d.m_pad, d.D,
                                                 d.offs, (const T *)d.data, x, y);
@@ -117,7 +163,7 @@ __device__ __forceinline__ void batch_item(const LevelDesc &d, int64_t tile, con
 
 // Work items base .. total-1 (items below `base` belong to levels launched
 // on their own before this kernel), strided over the grid.
-template <typename T>
+template <typename T, unsigned KINDS>
 __global__ __launch_bounds__(kPBlock) void k_batch_persistent(const LevelDesc *__restrict__ L,
                                                               int nlev, int64_t base,
                                                               int64_t total, Ptrs P) {
@@ -132,9 +178,9 @@ __global__ __launch_bounds__(kPBlock) void k_batch_persistent(const LevelDesc *_
         const T *x = (const T *)P.x[l];
         T *y = (T *)P.y[l];
         if (d.nt)
-            batch_item<T, true>(d, tile, x, y, xs, part);
+            batch_item<T, true, KINDS>(d, tile, x, y, xs, part);
         else
-            batch_item<T, false>(d, tile, x, y, xs, part);
+            batch_item<T, false, KINDS>(d, tile, x, y, xs, part);
         __syncthreads();  // LDS reuse by the next item
     }
 }
@@ -161,7 +207,7 @@ __global__ __launch_bounds__(256) void k_stream_copy(const v4u *__restrict__ src
 }
 
 // Read-dominant bandwidth probe: a fixed grid streams the source with
-// 16-byte non-temporal loads, four in flight per thread, and each thread
+// 16-byte non-temporal loads, eight in flight per thread, and each thread
 // writes the word-wise sum of what it loaded (so no load can be dropped).
 constexpr int kReadProbeBlocks = 256 * 8, kReadProbeThreads = 256;
 
@@ -171,12 +217,16 @@ __global__ __launch_bounds__(kReadProbeThreads) void k_stream_read(const v4u *__
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     v4u acc = {0u, 0u, 0u, 0u};
-    for (; i + 3 * stride < n; i += 4 * stride) {
+    for (; i + 7 * stride < n; i += 8 * stride) {
         v4u a = __builtin_nontemporal_load(src + i);
         v4u b = __builtin_nontemporal_load(src + i + stride);
         v4u c = __builtin_nontemporal_load(src + i + 2 * stride);
         v4u d = __builtin_nontemporal_load(src + i + 3 * stride);
-        acc += a + b + c + d;
+        v4u e = __builtin_nontemporal_load(src + i + 4 * stride);
+        v4u f = __builtin_nontemporal_load(src + i + 5 * stride);
+        v4u g = __builtin_nontemporal_load(src + i + 6 * stride);
+        v4u h = __builtin_nontemporal_load(src + i + 7 * stride);
+        acc += a + b + c + d + e + f + g + h;
     }
     for (; i < n; i += stride) acc += __builtin_nontemporal_load(src + i);
     out[blockIdx.x * (int64_t)blockDim.x + threadIdx.x] = acc;
@@ -257,6 +307,7 @@ struct spmv_batch_s {
     std::vector<spmv_plan_t> plans;
     std::vector<int> persistent_levels;  // indices handled inside the persistent kernel
     std::vector<int64_t> tile_begin;     // first work item of each of them
+    std::vector<int> kinds;              // and their LevelKind
     std::vector<int> extra_levels;       // launched separately
     int split = 0;  // leading persistent levels launched as their own kernels instead
     smat::Dev desc;
@@ -359,6 +410,17 @@ extern "C" spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplan
                                         (size_t)(d.tile_rows + V.max_span) * (size_t)P.elt);
             if (V.D == 0) d.kind = -1;
             break;
+        case SPMV_K_BCSR:
+            // the level's own lane count (float64: at least the 8 lanes of
+            // one block), kPBlock / lanes block rows per work item
+            d.kind = LK_BCSR;
+            d.lanes = P.elt == 8 ? std::max(8, V.prm.bcsr_lanes) : V.prm.bcsr_lanes;
+            d.mb = (P.m + 3) / 4;
+            d.brp = V.brp.as<int32_t>();
+            d.bcol = V.bcol.as<int32_t>();
+            d.bval = V.bval.p;
+            d.tile_rows = 4 * (kPBlock / d.lanes);
+            break;
         default:
             d.kind = -1;
         }
@@ -370,6 +432,7 @@ extern "C" spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplan
         B->tile_begin.push_back(tiles);
         tiles += ntiles >= 0 ? ntiles : (P.m + d.tile_rows - 1) / d.tile_rows;
         B->persistent_levels.push_back(l);
+        B->kinds.push_back(d.kind);
         descs.push_back(d);
     }
     B->total_tiles = tiles;
@@ -440,14 +503,36 @@ extern "C" spmv_status spmv_batch_run(spmv_batch_t B, const void *const *xs, voi
                                                               : B->total_tiles;
     if (B->total_tiles > base) {
         const int grid = (int)std::min<int64_t>(B->grid, B->total_tiles - base);
+        unsigned kinds = 0;
+        for (size_t i = (size_t)B->split; i < B->kinds.size(); ++i) kinds |= 1u << B->kinds[i];
+        const LevelDesc *L = B->desc.as<LevelDesc>();
+        const int nl = (int)B->persistent_levels.size();
+        const int64_t tot = B->total_tiles;
+#define SMAT_PERSISTENT(T, K)                                                                \
+    k_batch_persistent<T, K><<<grid, kPBlock, B->lds_bytes, s>>>(L, nl, base, tot, P)
+#define SMAT_PERSISTENT_SET(T)                                                               \
+    do {                                                                                     \
+        if ((kinds & ~kKindsRow) == 0)                                                       \
+            SMAT_PERSISTENT(T, kKindsRow);                                                   \
+        else if ((kinds & ~(kKindsRow | kKindsBcsr)) == 0)                                   \
+            SMAT_PERSISTENT(T, (kKindsRow | kKindsBcsr));                                    \
+        else if ((kinds & ~kKindsCsr) == 0)                                                  \
+            SMAT_PERSISTENT(T, kKindsCsr);                                                   \
+        else if ((kinds & ~kKindsEll) == 0)                                                  \
+            SMAT_PERSISTENT(T, kKindsEll);                                                   \
+        else if ((kinds & ~kKindsDia) == 0)                                                  \
+            SMAT_PERSISTENT(T, kKindsDia);                                                   \
+        else if ((kinds & ~(kKindsCsr | kKindsEll | kKindsBcsr)) == 0)                       \
+            SMAT_PERSISTENT(T, (kKindsCsr | kKindsEll | kKindsBcsr));                        \
+        else                                                                                 \
+            SMAT_PERSISTENT(T, kKindsAll);                                                   \
+    } while (0)
         if (B->elt == 8)
-            k_batch_persistent<double><<<grid, kPBlock, B->lds_bytes, s>>>(
-                B->desc.as<LevelDesc>(), (int)B->persistent_levels.size(), base,
-                B->total_tiles, P);
+            SMAT_PERSISTENT_SET(double);
         else
-            k_batch_persistent<float><<<grid, kPBlock, B->lds_bytes, s>>>(
-                B->desc.as<LevelDesc>(), (int)B->persistent_levels.size(), base,
-                B->total_tiles, P);
+            SMAT_PERSISTENT_SET(float);
+#undef SMAT_PERSISTENT_SET
+#undef SMAT_PERSISTENT
         SMAT_LAUNCHED("batch_persistent");
     }
     for (int l : B->extra_levels) {

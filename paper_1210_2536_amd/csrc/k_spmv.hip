@@ -616,50 +616,8 @@ __global__ __launch_bounds__(256) void k_bcsr(int64_t mb, int64_t m, int64_t n,
                                               const int32_t *__restrict__ bcol,
                                               const T *__restrict__ bval,
                                               const T *__restrict__ x, T *__restrict__ y) {
-    constexpr int V = 16 / (int)sizeof(T);   // values per 16-byte load
-    typedef T vec __attribute__((ext_vector_type(V)));
-    typedef T vec4 __attribute__((ext_vector_type(4)));
     const int64_t R = (int64_t)blockIdx.x * (blockDim.x / L) + threadIdx.x / L;
-    const int lane = threadIdx.x & (L - 1);
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    if (R < mb) {
-        const int32_t kb = brp[R], ke = brp[R + 1];
-        for (int32_t k = kb + lane; k < ke; k += L) {
-            T v[16];
-            const vec *src = reinterpret_cast<const vec *>(bval + (int64_t)k * 16);
-#pragma unroll
-            for (int q = 0; q < 16 / V; ++q) {
-                vec w = ld<NT>(src + q);
-#pragma unroll
-                for (int e = 0; e < V; ++e) v[q * V + e] = w[e];
-            }
-            const int64_t c0 = (int64_t)ld<NT>(bcol + k) * 4;
-            T xv[4];
-            if (c0 + 4 <= n) {
-                vec4 t;
-                __builtin_memcpy(&t, x + c0, sizeof(t));
-#pragma unroll
-                for (int cc = 0; cc < 4; ++cc) xv[cc] = t[cc];
-            } else {
-#pragma unroll
-                for (int cc = 0; cc < 4; ++cc) xv[cc] = c0 + cc < n ? x[c0 + cc] : T(0);
-            }
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-                for (int cc = 0; cc < 4; ++cc)
-                    acc[rr] = fma((double)v[rr * 4 + cc], (double)xv[cc], acc[rr]);
-        }
-    }
-#pragma unroll
-    for (int rr = 0; rr < 4; ++rr)
-#pragma unroll
-        for (int off = L / 2; off > 0; off >>= 1) acc[rr] += __shfl_xor(acc[rr], off, L);
-    if (R < mb && lane == 0) {
-#pragma unroll
-        for (int rr = 0; rr < 4; ++rr)
-            if (4 * R + rr < m) y[4 * R + rr] = (T)acc[rr];
-    }
+    bcsr_row_lanes<T, L, NT>(R, threadIdx.x & (L - 1), mb, m, n, brp, bcol, bval, x, y);
 }
 
 template <int L, bool NT>
@@ -669,39 +627,8 @@ __global__ __launch_bounds__(256) void k_bcsr_coop(int64_t mb, int64_t m, int64_
                                                    const double *__restrict__ bval,
                                                    const double *__restrict__ x,
                                                    double *__restrict__ y) {
-    constexpr int S = 8;                    // lanes per block, 2 values each
-    constexpr int G = L / S;                // blocks of a row in flight
-    static_assert(L >= S && L <= 64 && (L & (L - 1)) == 0, "lanes per block row");
-    typedef double vec2 __attribute__((ext_vector_type(2)));
     const int64_t R = (int64_t)blockIdx.x * (blockDim.x / L) + threadIdx.x / L;
-    const int lane = threadIdx.x & (L - 1);
-    const int g = lane / S, j = lane % S;
-    const int row = j / 2;                  // block row of this lane's piece
-    const int cc0 = 2 * (j % 2);            // first column of the piece
-    double acc = 0.0;
-    if (R < mb) {
-        const int32_t kb = brp[R], ke = brp[R + 1];
-        for (int32_t k = kb + g; k < ke; k += G) {
-            const vec2 w = ld<NT>(reinterpret_cast<const vec2 *>(bval + (int64_t)k * 16) + j);
-            const int64_t c0 = (int64_t)ld<NT>(bcol + k) * 4 + cc0;
-            double x0, x1;
-            if (c0 + 2 <= n) {
-                vec2 t;
-                __builtin_memcpy(&t, x + c0, sizeof(t));
-                x0 = t[0];
-                x1 = t[1];
-            } else {
-                x0 = c0 < n ? x[c0] : 0.0;
-                x1 = c0 + 1 < n ? x[c0 + 1] : 0.0;
-            }
-            acc = fma(w[0], x0, acc);
-            acc = fma(w[1], x1, acc);
-        }
-    }
-    acc += __shfl_xor(acc, 1, L);   // the two halves of a block row
-#pragma unroll
-    for (int off = S; off < L; off <<= 1) acc += __shfl_xor(acc, off, L);
-    if (R < mb && g == 0 && cc0 == 0 && 4 * R + row < m) y[4 * R + row] = acc;
+    bcsr_row_coop<L, NT>(R, threadIdx.x & (L - 1), mb, m, n, brp, bcol, bval, x, y);
 }
 
 // ---------------------------------------------------------------- COO

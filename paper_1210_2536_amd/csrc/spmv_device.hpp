@@ -320,4 +320,108 @@ __device__ __forceinline__ void dia_tile_direct(int64_t r0, int64_t m, int64_t n
     }
 }
 
+// ---------------------------------------------------------------- BCSR 4x4
+// Block row R (rows 4R .. 4R+3) by L lanes; every lane of the wave must
+// call (the lane sums are added by shuffles), R >= mb contributing nothing.
+//
+// bcsr_row_lanes (float32 form): lane l takes blocks l, l + L, ... of its
+// block row; a block's 16 values (row-major) arrive in 16-byte loads, its 4
+// x values in one (element-aligned) load away from the last column block;
+// one running sum per row, the L lanes' sums added by xor shuffles.
+template <typename T, int L, bool NT>
+__device__ __forceinline__ void bcsr_row_lanes(int64_t R, int lane, int64_t mb, int64_t m,
+                                               int64_t n, const int32_t *__restrict__ brp,
+                                               const int32_t *__restrict__ bcol,
+                                               const T *__restrict__ bval,
+                                               const T *__restrict__ x, T *__restrict__ y) {
+    constexpr int V = 16 / (int)sizeof(T);   // values per 16-byte load
+    typedef T vec __attribute__((ext_vector_type(V)));
+    typedef T vec4 __attribute__((ext_vector_type(4)));
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    if (R < mb) {
+        const int32_t kb = brp[R], ke = brp[R + 1];
+        for (int32_t k = kb + lane; k < ke; k += L) {
+            T v[16];
+            const vec *src = reinterpret_cast<const vec *>(bval + (int64_t)k * 16);
+#pragma unroll
+            for (int q = 0; q < 16 / V; ++q) {
+                vec w = ld<NT>(src + q);
+#pragma unroll
+                for (int e = 0; e < V; ++e) v[q * V + e] = w[e];
+            }
+            const int64_t c0 = (int64_t)ld<NT>(bcol + k) * 4;
+            T xv[4];
+            if (c0 + 4 <= n) {
+                vec4 t;
+                __builtin_memcpy(&t, x + c0, sizeof(t));
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) xv[cc] = t[cc];
+            } else {
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc) xv[cc] = c0 + cc < n ? x[c0 + cc] : T(0);
+            }
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                for (int cc = 0; cc < 4; ++cc)
+                    acc[rr] = fma((double)v[rr * 4 + cc], (double)xv[cc], acc[rr]);
+        }
+    }
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) acc[rr] += __shfl_xor(acc[rr], off, L);
+    if (R < mb && lane == 0) {
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr)
+            if (4 * R + rr < m) y[4 * R + rr] = (T)acc[rr];
+    }
+}
+
+// bcsr_row_coop (float64 form, 8 <= L <= 64): a block's 128 bytes are read
+// by 8 lanes together, 16 bytes (half a row) each, so a wave's loads are
+// contiguous; G = L / 8 groups, group g taking blocks g, g + G, ...; a lane
+// reads the 2 x values under its piece in one load and keeps one running
+// sum for its row; the lanes of a row (the pair inside a block, then the G
+// groups) are added by xor shuffles in a fixed order.
+template <int L, bool NT>
+__device__ __forceinline__ void bcsr_row_coop(int64_t R, int lane, int64_t mb, int64_t m,
+                                              int64_t n, const int32_t *__restrict__ brp,
+                                              const int32_t *__restrict__ bcol,
+                                              const double *__restrict__ bval,
+                                              const double *__restrict__ x,
+                                              double *__restrict__ y) {
+    constexpr int S = 8;                    // lanes per block, 2 values each
+    constexpr int G = L / S;                // blocks of a row in flight
+    static_assert(L >= S && L <= 64 && (L & (L - 1)) == 0, "lanes per block row");
+    typedef double vec2 __attribute__((ext_vector_type(2)));
+    const int g = lane / S, j = lane % S;
+    const int row = j / 2;                  // block row of this lane's piece
+    const int cc0 = 2 * (j % 2);            // first column of the piece
+    double acc = 0.0;
+    if (R < mb) {
+        const int32_t kb = brp[R], ke = brp[R + 1];
+        for (int32_t k = kb + g; k < ke; k += G) {
+            const vec2 w = ld<NT>(reinterpret_cast<const vec2 *>(bval + (int64_t)k * 16) + j);
+            const int64_t c0 = (int64_t)ld<NT>(bcol + k) * 4 + cc0;
+            double x0, x1;
+            if (c0 + 2 <= n) {
+                vec2 t;
+                __builtin_memcpy(&t, x + c0, sizeof(t));
+                x0 = t[0];
+                x1 = t[1];
+            } else {
+                x0 = c0 < n ? x[c0] : 0.0;
+                x1 = c0 + 1 < n ? x[c0 + 1] : 0.0;
+            }
+            acc = fma(w[0], x0, acc);
+            acc = fma(w[1], x1, acc);
+        }
+    }
+    acc += __shfl_xor(acc, 1, L);   // the two halves of a block row
+#pragma unroll
+    for (int off = S; off < L; off <<= 1) acc += __shfl_xor(acc, off, L);
+    if (R < mb && g == 0 && cc0 == 0 && 4 * R + row < m) y[4 * R + row] = acc;
+}
+
 }  // namespace smat

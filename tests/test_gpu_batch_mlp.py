@@ -17,8 +17,9 @@ def _levels():
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32], ids=["f64", "f32"])
 @pytest.mark.parametrize("kernel", ["dia", "dia_direct", "ell", "csr_vector", "csr_scalar",
-                                    "csr_adaptive", "mixed", "dia/wide", "dia_direct/wide",
-                                    "ell/wide", "mixed/wide"])
+                                    "csr_adaptive", "bcsr", "mixed", "mixed2", "dia/wide",
+                                    "dia_direct/wide", "ell/wide", "mixed/wide", "bcsr/l2",
+                                    "bcsr/l32"])
 def test_batch_equals_per_level_runs(kernel, dtype):
     """Persistent launch and graph replay give each level's own result bit
     for bit, for every level kind the persistent kernel takes in (adaptive
@@ -26,10 +27,13 @@ def test_batch_equals_per_level_runs(kernel, dtype):
     import torch
     from paper_1210_2536_amd.spmv import Batch, Plan
     levels = _levels()
-    kernel, _, wide = kernel.partition("/")
-    prm = {"wide_loads": 1 if wide else 2}
-    kinds = (["dia", "ell", "csr_vector", "coo", "csr_adaptive"] if kernel == "mixed"
-             else [kernel] * len(levels))
+    kernel, _, opt = kernel.partition("/")
+    prm = {"wide_loads": 1 if opt == "wide" else 2}
+    if opt.startswith("l"):   # BCSR lanes per block row (float64: at least 8)
+        prm["bcsr_lanes"] = int(opt[1:])
+    kinds = {"mixed": ["dia", "ell", "csr_vector", "coo", "csr_adaptive"],
+             "mixed2": ["bcsr", "ell", "csr_scalar", "dia_direct", "bcsr"]}.get(
+                 kernel, [kernel] * len(levels))
     plans, xs, ys_ref = [], [], []
     for l, (A, k) in enumerate(zip(levels, kinds)):
         rp, col, val = dev(A, dtype)
