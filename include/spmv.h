@@ -146,7 +146,8 @@ typedef struct {
                                    through LDS in column chunks, 16-32 such
                                    rows per workgroup of 1024 threads;
                                    3 = tiles (both dtypes) for the rows
-                                   longer than min(adaptive_wg_min, 1024):
+                                   longer than min(adaptive_wg_min,
+                                   tile_row_min):
                                    x cut into 80 KB panels, one workgroup
                                    per (row block, panel) holding its panel
                                    in LDS, one float64 partial per (row,
@@ -156,11 +157,15 @@ typedef struct {
                                    rows longer than 1024, else 2).  Tiles
                                    fall back to chunks
                                    (float64) or 2 where their partials and
-                                   segment starts would exceed 1/20 of the
+                                   segment starts would exceed 1/5 of the
                                    long rows' bytes per run or no lane count
                                    keeps the 1e-12 bound; chunks fall back
                                    to 2 in float32 and for rows too long for
                                    the bound with 64 lanes per row          */
+    int32_t tile_row_min;       /* CSR_ADAPTIVE and CSR_PANEL with long-row
+                                   tiles: the rows longer than this many
+                                   entries go to the tiles (0 = default
+                                   1024; at least 64)                      */
     int32_t panel_direct_max;   /* CSR_PANEL: rows of at most this many
                                    entries (rounded down to a length-bin
                                    boundary) skip the column panels -- no

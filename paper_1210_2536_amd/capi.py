@@ -39,7 +39,7 @@ class spmv_params(ctypes.Structure):
                 ("adaptive_wg_min", i32), ("dia_rows_per_thread", i32), ("dia_span", i32),
                 ("coo_chunk", i32), ("ell_unroll", i32), ("stream_nt", i32),
                 ("panel_kib", i32), ("panel_xcd", i32), ("wide_loads", i32), ("bcsr_lanes", i32), ("long_lds", i32),
-                ("panel_direct_max", i32)]
+                ("tile_row_min", i32), ("panel_direct_max", i32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(vp, ctypes.c_size_t, vp)

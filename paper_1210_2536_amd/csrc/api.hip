@@ -389,6 +389,8 @@ constexpr int kXcds = 8;  // gfx950: eight accelerator complex dies, one L2 each
 // Column panels: rows of at most this many entries are summed without panels
 // by default (-1: none).
 constexpr int kPanelDirectMaxDefault = -1;
+// Long-row tiles take the rows longer than this by default (params.tile_row_min).
+constexpr int kTileRowMin = 1024;
 constexpr int64_t kDiaLdsMax = 64 * 1024;  // dynamic LDS of one DIA workgroup
 
 // Column-panel geometry: width w columns (a multiple of 64) and panel count P.
@@ -428,6 +430,7 @@ spmv_params resolve_params(int kernel, spmv_params p, const spmv_features &F, in
     // slower on smaller matrices)
     if (p.wide_loads == 0) p.wide_loads = F.m >= (1 << 20) ? 1 : 2;
     if (p.panel_direct_max == 0) p.panel_direct_max = kPanelDirectMaxDefault;
+    if (p.tile_row_min == 0) p.tile_row_min = kTileRowMin;
     if (p.bcsr_lanes == 0) {
         const int64_t mb = std::max<int64_t>(1, (F.m + 3) / 4);
         const int64_t avg = (std::max<int64_t>(0, F.blocks4) + mb - 1) / mb;
@@ -459,6 +462,7 @@ void merge_params(spmv_params &p, const spmv_params &u) {
     if (u.wide_loads > 0) p.wide_loads = u.wide_loads;
     if (u.bcsr_lanes > 0) p.bcsr_lanes = u.bcsr_lanes;
     if (u.long_lds > 0) p.long_lds = u.long_lds;
+    if (u.tile_row_min > 0) p.tile_row_min = u.tile_row_min;
     if (u.panel_direct_max != 0) p.panel_direct_max = u.panel_direct_max;
 }
 
@@ -507,6 +511,10 @@ spmv_status check_params(const spmv_params &p) {
         set_error("params.long_lds must be 0 (default), 1 (x chunks), 2 (off) or 3 (tiles)");
         return SPMV_EINVAL;
     }
+    if (p.tile_row_min != 0 && (p.tile_row_min < 64 || p.tile_row_min > (1 << 20))) {
+        set_error("params.tile_row_min must be 0 (default) or in [64, 2^20]");
+        return SPMV_EINVAL;
+    }
     if (p.panel_direct_max < -1 || p.panel_direct_max > (1 << 20)) {
         set_error("params.panel_direct_max must be -1 (none), 0 (default) or a row length "
                   "up to 2^20");
@@ -532,12 +540,14 @@ int64_t bcsr_f64_depth(int64_t max_rd, int L) {
 constexpr int64_t kCooMaxChunksPerRow = 3000;
 constexpr int64_t kSplitSegment = 512 * 1024;   // entries per split segment (512 threads)
 constexpr int64_t kSplitMin = 256 * 4000;       // longer rows than this are split
-constexpr int kTileRowMin = 1024;       // tiles take rows longer than this (or wg_min)
 constexpr int64_t kTileRowsDefault = 1024;   // default: tiles from this many such rows
 // Tiles: lanes per row of a row block, the fewest (at least 2^kTileLanesLog2Min)
 // that give about kTileEntriesPerLane entries per lane of the block's mean
 // segment (raised further where the float64 chain bound needs it).
 constexpr int kTileLanesLog2Min = 3;
+// Tiles are built only when their partial sums and segment starts cost at
+// most 1/kTileExtraShare of the long rows' own bytes per run.
+constexpr double kTileExtraShare = 5.0;
 constexpr double kTileEntriesPerLane = 16.0;
 
 // Kernels that can hold this matrix (zero-fill rule, storage cap) and, when
@@ -706,7 +716,7 @@ spmv_status build_long_tiles(const spmv_plan_s &P, Variant &V, const std::vector
     int64_t total = 0;
     for (int64_t l : len) total += l;
     const double extra = 16.0 * (double)NP * n7 + 8.0 * (double)(NP + 1) * n7;
-    if (extra * 20 > (double)total * (P.elt + 4)) return SPMV_OK;
+    if (extra * kTileExtraShare > (double)total * (P.elt + 4)) return SPMV_OK;
     const size_t nseg = (size_t)(n7 * (NP + 1));
     SMAT_TRY(long_tiles_prepare());
     SMAT_TRY(V.tile_seg.alloc(sizeof(int32_t) * nseg));
@@ -928,10 +938,10 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
             return SPMV_OK;
         };
         // tiles (asked for, or the default's candidate) take the rows longer
-        // than kTileRowMin as well; the binned launch's own threshold is
+        // than params.tile_row_min as well; the binned launch's own threshold is
         // restored below when they are not used
         const bool try_tiles = prm.long_lds == 0 || prm.long_lds == 3;
-        int wg = try_tiles ? std::min(prm.adaptive_wg_min, kTileRowMin) : prm.adaptive_wg_min;
+        int wg = try_tiles ? std::min(prm.adaptive_wg_min, prm.tile_row_min) : prm.adaptive_wg_min;
         SMAT_TRY(bin(wg));
         // split rows: segment table on the host from their row_ptr entries
         int64_t ns = V.bin_off[9] - V.bin_off[8];
@@ -975,7 +985,7 @@ spmv_status build_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork &W
         // for a kernel that keeps x in LDS: x chunks streamed through each
         // workgroup of rows (long_lds 1, float64) or one x panel per (row
         // block, panel) workgroup (long_lds 3).  Default: tiles from
-        // kTileRowsDefault rows longer than kTileRowMin.  Tiles that do not
+        // kTileRowsDefault rows longer than tile_row_min.  Tiles that do not
         // suit the matrix fall back to chunks where those keep the float64
         // chain bound, else to the binned launch.
         int ll = prm.long_lds;
@@ -1264,6 +1274,14 @@ std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_
                     p.long_lds = ll;
                     add(p);
                 }
+        // tiles for only the longer rows, the other parameters at their defaults
+        for (int r : {4096, 16384}) {
+            spmv_params p = b;
+            p.long_lds = 3;
+            p.tile_row_min = r;
+            p.adaptive_wg_min = std::max(b.adaptive_wg_min, r);
+            add(p);
+        }
         break;
     case SPMV_K_ELL:
         for (int u : {2, 4})
@@ -1335,10 +1353,18 @@ std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_
                         add(p);
                     }
             }
-        // short rows without panels, the other parameters at their defaults
+        // short rows without panels, and tiles for only the longer rows, the
+        // other parameters at their defaults
         for (int d : {-1, 4, 16, 64}) {
             spmv_params p = b;
             p.panel_direct_max = d;
+            add(p);
+        }
+        for (int r : {4096, 16384}) {
+            spmv_params p = b;
+            p.long_lds = 3;
+            p.tile_row_min = r;
+            p.adaptive_wg_min = std::max(b.adaptive_wg_min, r);
             add(p);
         }
         break;

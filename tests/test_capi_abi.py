@@ -75,7 +75,7 @@ int main(void) {
   O(spmv_plan_info, mlp_input) O(spmv_plan_info, rules_kernel) O(spmv_plan_info, out_of_domain) O(spmv_plan_info, t_tune_ms) O(spmv_plan_info, bcsr_blocks) O(spmv_plan_info, n_segments) O(spmv_plan_opts, segments)
   O(spmv_plan_opts, staged) O(spmv_plan_opts, stage_conf) O(spmv_plan_info, feature_stage) O(spmv_plan_info, stage_confidence) O(spmv_plan_info, tune_rejected) O(spmv_plan_info, long_lanes) O(spmv_plan_info, long_rows) O(spmv_params, long_lds) O(spmv_plan_opts, allocator) S(spmv_allocator)
   O(spmv_features, dia_feasible)
-  O(spmv_params, panel_direct_max) O(spmv_plan_opts, time_baseline) O(spmv_plan_opts, log)
+  O(spmv_params, panel_direct_max) O(spmv_params, tile_row_min) O(spmv_plan_opts, time_baseline) O(spmv_plan_opts, log)
   O(spmv_plan_info, t_run_ms) O(spmv_plan_info, break_even_calls)
   return 0;
 }
