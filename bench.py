@@ -37,18 +37,11 @@ def log(msg):
 
 
 def kernel_sources_sha256():
-    """Digest of the HIP sources and the C header: a counter record taken on
-    other sources no longer describes the kernels being timed."""
-    import hashlib
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1210_2536_amd", "csrc")
-    files = sorted(os.path.join(csrc, f) for f in os.listdir(csrc)
-                   if f.endswith((".hip", ".hpp", ".h")))
-    for f in files + [os.path.join(ROOT, "include", "spmv.h")]:
-        h.update(os.path.basename(f).encode())
-        with open(f, "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+    """Digest of the HIP sources and the C header, comments and layout
+    removed: a counter record taken on other code no longer describes the
+    kernels being timed."""
+    from paper_1210_2536_amd.build import all_sources_digest
+    return all_sources_digest()
 
 
 def recorded_traffic(kernel, workload, algorithmic_bytes):
@@ -674,7 +667,7 @@ def main():
     # replay), the n = 8M Zipf matrix (float32) and the 7-point 256^3
     # Laplacian (float64), with plain CSR on the same GPU and Equation 2
     side = None
-    if not a.no_side and a.workload == "sweep":
+    if not a.no_side and a.workload == "sweep" and not a.replay:
         side = {}
         from paper_1210_2536_amd.spmv import Batch
 

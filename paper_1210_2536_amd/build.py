@@ -27,6 +27,62 @@ FLAGS = [
 ]
 
 
+# The sources that decide what the SpMV kernels cost: the kernels, their
+# launch parameters and plan set-up, the formats they read, the interface.
+TIMING_SOURCES = ["csrc/k_spmv.hip", "csrc/spmv_device.hpp", "csrc/api.hip", "csrc/k_convert.hip",
+                  "csrc/internal.hpp", "csrc/plan.hpp", "../include/spmv.h"]
+
+
+def _strip_comments(text: str) -> str:
+    """C/C++ source without comments and with whitespace runs collapsed
+    (string and character literals kept as written)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
+def sources_digest(rel_paths) -> str:
+    """SHA-256 of the given sources (relative to the package) with comments
+    and layout removed."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in rel_paths:
+        with open(os.path.join(HERE, rel)) as fh:
+            h.update(os.path.basename(rel).encode())
+            h.update(_strip_comments(fh.read()).encode())
+    return h.hexdigest()
+
+
+def timing_sources_digest() -> str:
+    """Digest of TIMING_SOURCES: timing tables and the models fitted to them
+    describe the kernels these sources build, and no others."""
+    return sources_digest(TIMING_SOURCES)
+
+
+def all_sources_digest() -> str:
+    """Digest of every HIP source and header of the library and the C
+    interface: a counter record describes the kernels these build."""
+    names = sorted(f for f in os.listdir(CSRC) if f.endswith((".hip", ".hpp", ".h")))
+    return sources_digest([os.path.join("csrc", f) for f in names] + ["../include/spmv.h"])
+
+
 def _hipcc():
     for cand in (os.environ.get("HIPCC"), "/opt/rocm/bin/hipcc", shutil.which("hipcc")):
         if cand and os.path.exists(cand):

@@ -8,7 +8,7 @@ feasible kernel is timed (brute force, the paper's Table 6 comparison), and
 the model is a 12-64-64-C perceptron trained by the library's own HIP
 forward / backward / Adam kernels.
 
-  python -m paper_1210_2536_amd.selector collect --start 0 --stop 5000 --out train.npz
+  python -m paper_1210_2536_amd.selector collect --start 0 --stop 5000 --out train.npz [--resume --budget S]
   python -m paper_1210_2536_amd.selector collect --heldout --start 0 --stop 500 --out held.npz
   python -m paper_1210_2536_amd.selector train --data train*.npz --out weights.json
   python -m paper_1210_2536_amd.selector eval --weights weights.json --data held.npz
@@ -57,41 +57,77 @@ def _measure(A, dtype, reps, dev):
     return np.array(info["mlp_input"], dtype=np.float32), times, info["rules_kernel"]
 
 
-def collect(start, stop, heldout, out, reps=7, threads=8, nnz_cap=30_000_000):
-    """Time every feasible kernel on selector matrices [start, stop) x {f32, f64}."""
+def _save_table(out, cols, heldout, digest):
+    tmp = out + ".tmp.npz"
+    np.savez(tmp, **{k: np.array(v) for k, v in cols.items()}, heldout=np.array(bool(heldout)),
+             sources=np.array(digest))
+    os.replace(tmp, out)
+
+
+def collect(start, stop, heldout, out, reps=7, threads=8, nnz_cap=30_000_000, resume=False,
+            budget_s=None):
+    """Time every feasible kernel on selector matrices [start, stop) x {f32, f64}.
+
+    The table is written to `out` every 50 matrices and at the end, keyed by
+    matrix index; with `resume`, rows already in `out` are kept and the
+    collection continues after its last matrix.  `budget_s`: stop (and
+    write) once this many seconds have passed.  The table records the digest
+    of the kernel sources it was measured on (build.timing_sources_digest)."""
     import torch
+    from .build import timing_sources_digest
     dev = torch.device("cuda:0")
-    raw, times, rules, idx, dts, nnz = [], [], [], [], [], []
+    digest = timing_sources_digest()
+    keys = ("raw", "times", "rules", "idx", "dtype", "nnz")
+    cols = {k: [] for k in keys}
+    if resume and os.path.exists(out):
+        old = np.load(out)
+        if bool(old["heldout"]) != bool(heldout) or str(old["sources"]) != digest:
+            raise RuntimeError(f"{out}: other matrices or other kernel sources, not resumed")
+        for k in keys:
+            cols[k] = list(old[k])
+        if len(cols["idx"]):
+            start = max(start, int(max(cols["idx"])) + 1)
+        log(f"resuming {out} at matrix {start} ({len(cols['idx'])} rows kept)")
     t0 = time.time()
+    done = 0
     gen = lambda i: S.selector_matrix(i, heldout=heldout, nnz_cap=nnz_cap)  # noqa: E731
     with cf.ThreadPoolExecutor(threads) as ex:
         futs = {i: ex.submit(gen, i) for i in range(start, min(stop, start + 2 * threads))}
         nxt = start + len(futs)
         for i in range(start, stop):
+            if budget_s is not None and time.time() - t0 > budget_s:
+                log(f"time budget reached before matrix {i}")
+                break
             A = futs.pop(i).result()
             if nxt < stop:
                 futs[nxt] = ex.submit(gen, nxt)
                 nxt += 1
             for code, dt in ((0, np.float32), (1, np.float64)):
                 r, t, rk = _measure(A, dt, reps, dev)
-                raw.append(r)
-                times.append(t)
-                rules.append(rk)
-                idx.append(i)
-                dts.append(code)
-                nnz.append(A.nnz)
-            if (i - start) % 100 == 99:
-                log(f"{i + 1 - start}/{stop - start} matrices, {time.time() - t0:.0f}s")
-    np.savez(out, raw=np.array(raw), times=np.array(times), rules=np.array(rules),
-             idx=np.array(idx), dtype=np.array(dts), nnz=np.array(nnz),
-             heldout=np.array(bool(heldout)))
-    log(f"wrote {out}: {len(raw)} rows in {time.time() - t0:.0f}s")
+                for k, v in zip(keys, (r, t, rk, i, code, A.nnz)):
+                    cols[k].append(v)
+            done += 1
+            if done % 20 == 0:
+                log(f"matrix {i + 1} of [{start}, {stop}), {time.time() - t0:.0f}s")
+            if done % 50 == 0:
+                _save_table(out, cols, heldout, digest)
+        for f in futs.values():
+            f.cancel()
+    _save_table(out, cols, heldout, digest)
+    log(f"wrote {out}: {len(cols['idx'])} rows, {done} matrices in {time.time() - t0:.0f}s")
 
 
 def load(paths):
     parts = [np.load(p) for p in paths]
     keys = ("raw", "times", "rules", "idx", "dtype", "nnz")
     return {k: np.concatenate([p[k] for p in parts]) for k in keys}
+
+
+def sources_of(paths):
+    """The kernel-source digest the timing tables were measured on (one for
+    all of them), or None if they disagree or predate the digest."""
+    ds = {str(np.load(p)["sources"]) if "sources" in np.load(p).files else None for p in paths}
+    return ds.pop() if len(ds) == 1 else None
 
 
 # ----------------------------------------------------------------- training
@@ -345,6 +381,8 @@ def main(argv=None):
     c.add_argument("--out", required=True)
     c.add_argument("--reps", type=int, default=7)
     c.add_argument("--threads", type=int, default=8)
+    c.add_argument("--resume", action="store_true")
+    c.add_argument("--budget", type=float, default=None, help="stop after this many seconds")
     t = sub.add_parser("train")
     t.add_argument("--data", nargs="+", required=True)
     t.add_argument("--heldout", nargs="*", default=[])
@@ -366,7 +404,8 @@ def main(argv=None):
     e.add_argument("--data", nargs="+", required=True)
     a = ap.parse_args(argv)
     if a.cmd == "collect":
-        collect(a.start, a.stop, a.heldout, a.out, reps=a.reps, threads=a.threads)
+        collect(a.start, a.stop, a.heldout, a.out, reps=a.reps, threads=a.threads,
+                resume=a.resume, budget_s=a.budget)
     elif a.cmd == "train":
         ds = load(a.data)
         n = len(ds["raw"])
@@ -380,7 +419,8 @@ def main(argv=None):
         va = {k: v[val] for k, v in ds.items()}
         params, mean, std, curve = train(tr, epochs=a.epochs)
         tau, vr = pick_tau(params, mean, std, va)
-        meta = {"train_rows": int((~val).sum()), "val_rows": int(val.sum()), "tau": tau,
+        meta = {"kernel_sources_sha256": sources_of(a.data + list(a.heldout)),
+                "train_rows": int((~val).sum()), "val_rows": int(val.sum()), "tau": tau,
                 "val_hit_rate_tau": vr["hit_rate"], "loss_curve": curve,
                 "val_rules": {k: v for k, v in evaluate_rules(va).items() if k != "choice"}}
         if a.heldout:

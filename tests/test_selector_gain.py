@@ -51,10 +51,33 @@ def test_network_beats_rules_on_heldout_tables():
           f"geomean slowdown {slow_mlp:.4f} vs {slow_rules:.4f}")
 
 
+def _time_pair(plans, x, y, reps=3):
+    """Median time of one run of each plan, the two timed in alternation
+    (the same session, the same conditions)."""
+    import torch
+    ts = [[] for _ in plans]
+    for _ in range(reps):
+        for k, p in enumerate(plans):
+            p.run(x, y)
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(5)]
+            for a, b in ev:
+                a.record()
+                for _ in range(8):
+                    p.run(x, y)
+                b.record()
+            torch.cuda.synchronize()
+            ts[k].append(np.median([a.elapsed_time(b) for a, b in ev]) / 8)
+    return [float(np.median(t)) for t in ts]
+
+
 @pytest.mark.gpu
 def test_live_selection_network_vs_rules():
+    """Prediction only (no measurement), judged against exhaustive timing in
+    the same session; a choice outside 5% of the table's best but within
+    1.5x is timed again beside the best kernel (table noise)."""
     import torch
-    from paper_1210_2536_amd import capi, synth
+    from paper_1210_2536_amd import synth
     from paper_1210_2536_amd.spmv import Plan, Selector
     sel = Selector.load(WEIGHTS)
     hits_mlp = hits_rules = total = 0
@@ -65,18 +88,30 @@ def test_live_selection_network_vs_rules():
             rp = torch.from_numpy(A.row_ptr.astype(np.int32)).cuda()
             col = torch.from_numpy(A.col).cuda()
             val = torch.from_numpy(A.val.astype(dt)).cuda()
+            x = torch.ones(A.n, dtype=val.dtype, device="cuda")
+            y = torch.empty(A.m, dtype=val.dtype, device="cuda")
             ex = Plan(rp, col, val, n=A.n, selector="exhaustive", reps=9).info()
             nm = ex["n_measured"]
             table = dict(zip(ex["measured_kernel"][:nm], ex["measured_ms"][:nm]))
             best = min(table.values())
+            best_k = min(table, key=table.get)
             pm = Plan(rp, col, val, n=A.n, selector="mlp", model=sel, tau=0.0,
                       staged=False).info()
-            hits_mlp += table[pm["kernel"]] <= 1.05 * best
-            hits_rules += table[ex["rules_kernel"]] <= 1.05 * best
+
+            def hit(k):
+                if table[k] <= 1.05 * best:
+                    return True
+                if table[k] > 1.5 * best:
+                    return False
+                tk, tb = _time_pair([Plan(rp, col, val, n=A.n, selector=int(k)),
+                                     Plan(rp, col, val, n=A.n, selector=int(best_k))], x, y)
+                return tk <= 1.05 * tb
+            hits_mlp += hit(pm["kernel"])
+            hits_rules += hit(ex["rules_kernel"])
             total += 1
     print(f"live hit rate: network {hits_mlp / total:.3f}, rules {hits_rules / total:.3f}")
     assert hits_mlp >= hits_rules
-    assert hits_mlp / total >= 0.7
+    assert hits_mlp / total >= 0.9
 
 
 @pytest.mark.gpu
