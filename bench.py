@@ -487,6 +487,12 @@ def main():
         del table, idx, vals, outp
     log(f"gather probe: {gather}")
     ms_step = (t1 - t0) * 1e3 / a.steps
+    # the single plan taking the most time per step, with its own rate
+    big = max(recs, key=lambda r: r["rec"]["tuned_ms"])["rec"]
+    largest = {"plan": f"{big['name']}/{big['dtype']}", "kernel": big["symbol"],
+               "ms": round(big["tuned_ms"], 5),
+               "alg_gbs": round(big["bytes"] / (big["tuned_ms"] * 1e-3) / 1e9, 1),
+               "frac": round(big["bytes"] / (big["tuned_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     flops = sum(2.0 * r["rec"]["nnz"] for r in recs)
     nbytes = sum(float(r["rec"]["bytes"]) for r in recs)
     gflops = flops / (ms_step * 1e-3) / 1e9
@@ -866,7 +872,10 @@ def main():
                                                  int(np.mean(dom_bytes))),
                      "avg_launch_ms": round(dom_avg_ms, 5),
                      "bytes_per_launch": int(np.mean(dom_bytes)),
-                     "entry_rate_G_per_s": round(dom_entries_per_s / 1e9, 2)},
+                     "entry_rate_G_per_s": round(dom_entries_per_s / 1e9, 2),
+                     "plans": sorted({f"{r['rec']['name']}/{r['rec']['dtype']}" for r in recs
+                                      if r["rec"]["symbol"] == dominant}),
+                     "largest_plan": largest},
         "gather_probe": {(k.replace("entries_per_s", "G_entries_per_s")):
                          (round(v / 1e9, 2) if k.endswith("per_s") else v)
                          for k, v in gather.items()},
