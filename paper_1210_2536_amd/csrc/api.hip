@@ -548,6 +548,7 @@ constexpr int kTileLanesLog2Min = 3;
 // Tiles are built only when their partial sums and segment starts cost at
 // most 1/kTileExtraShare of the long rows' own bytes per run.
 constexpr double kTileExtraShare = 5.0;
+constexpr int64_t kTileMinEntries = 16384;   // per tile workgroup, at least
 constexpr double kTileEntriesPerLane = 16.0;
 
 // Kernels that can hold this matrix (zero-fill rule, storage cap) and, when
@@ -726,8 +727,14 @@ spmv_status build_long_tiles(const spmv_plan_s &P, Variant &V, const std::vector
     SMAT_HIP(hipMemcpyAsync(h.data(), V.tile_seg.p, sizeof(int32_t) * nseg,
                             hipMemcpyDeviceToHost, s));
     SMAT_HIP(hipStreamSynchronize(s));
-    const int64_t target =
-        std::max<int64_t>(1, std::min<int64_t>(4 * W * NP, total * NP / 2048));
+    // entries per row block (over all its panels): about four panels' worth,
+    // fewer so that the grid has about 2048 workgroups, but no fewer than
+    // kTileMinEntries per workgroup -- each workgroup reads a whole x panel,
+    // which small blocks would not repay (measured: 5-14% faster than 2048
+    // workgroups on Zipf matrices of 1.1-2.6e7 long-row entries)
+    const int64_t target = std::max<int64_t>(
+        1, std::min<int64_t>(4 * W * NP,
+                             std::max<int64_t>(total * NP / 2048, kTileMinEntries * NP)));
     std::vector<int32_t> blocks;
     int max_tpr = 0;
     for (int64_t r0 = 0; r0 < n7;) {
@@ -1274,8 +1281,9 @@ std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_
                     p.long_lds = ll;
                     add(p);
                 }
-        // tiles for only the longer rows, the other parameters at their defaults
-        for (int r : {4096, 16384}) {
+        // tiles for more or only the longer rows, the other parameters at
+        // their defaults
+        for (int r : {256, 4096, 16384}) {
             spmv_params p = b;
             p.long_lds = 3;
             p.tile_row_min = r;
@@ -1353,14 +1361,14 @@ std::vector<spmv_params> tune_grid(int kernel, const spmv_params &b, const spmv_
                         add(p);
                     }
             }
-        // short rows without panels, and tiles for only the longer rows, the
-        // other parameters at their defaults
+        // short rows without panels, and tiles for more or only the longer
+        // rows, the other parameters at their defaults
         for (int d : {-1, 4, 16, 64}) {
             spmv_params p = b;
             p.panel_direct_max = d;
             add(p);
         }
-        for (int r : {4096, 16384}) {
+        for (int r : {256, 4096, 16384}) {
             spmv_params p = b;
             p.long_lds = 3;
             p.tile_row_min = r;
