@@ -765,6 +765,9 @@ spmv_status build_long_tiles(const spmv_plan_s &P, Variant &V, const std::vector
     SMAT_HIP(hipMemcpyAsync(V.tile_blocks.p, blocks.data(), sizeof(int32_t) * blocks.size(),
                             hipMemcpyHostToDevice, s));
     SMAT_TRY(V.tile_part.alloc(sizeof(double) * (size_t)(NP * n7)));
+    SMAT_TRY(V.tile_off.alloc(sizeof(uint16_t) * (size_t)std::max<int64_t>(1, P.nnz)));
+    SMAT_TRY(launch_long_tile_off(n7, W, V.long_rows.as<int32_t>(), P.rp.as<int32_t>(),
+                                  P.col.as<int32_t>(), V.tile_off.as<uint16_t>(), s));
     SMAT_HIP(hipStreamSynchronize(s));
     V.tile_P = NP;
     V.tile_nb = (int64_t)blocks.size() / 3;
@@ -1120,8 +1123,8 @@ spmv_status run_long_rows(const spmv_plan_s &P, const Variant &V, const void *x,
     if (V.long_tiles)
         return run_long_tiles(P.elt, V.n_long, V.tile_P, V.tile_nb, V.tile_blocks.as<int32_t>(),
                               V.tile_seg.as<int32_t>(), V.long_rows.as<int32_t>(),
-                              P.col.as<int32_t>(), P.val.p, x, P.n, V.tile_part.as<double>(), y,
-                              s);
+                              V.tile_off.as<uint16_t>(), P.val.p, x, P.n,
+                              V.tile_part.as<double>(), y, s);
     return run_long_rows_lds(V.long_tpr, V.n_long, V.long_rows.as<int32_t>(), P.rp.as<int32_t>(),
                              P.col.as<int32_t>(), P.val.as<double>(), (const double *)x, P.n,
                              (double *)y, s);

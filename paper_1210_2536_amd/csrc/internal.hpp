@@ -161,9 +161,11 @@ spmv_status run_long_rows_lds(int tpr, int64_t nrows, const int32_t *rows, const
                               double *y, hipStream_t s);
 // Long rows by tiles: x panels of long_tile_width(elt) values, workgroup
 // (row block, panel).  seg: (P + 1) * n7 segment starts, filled by
-// launch_long_tile_seg from the rows (ascending columns); blocks: nblocks
-// triples (first row, end row, log2 lanes per row) over the rows' order;
-// part: P * n7 float64 partials.  y receives the rows rows[0 .. n7).
+// launch_long_tile_seg from the rows (ascending columns); off: nnz 16-bit
+// panel offsets of the columns, filled for the long rows' entries by
+// launch_long_tile_off; blocks: nblocks triples (first row, end row, log2
+// lanes per row) over the rows' order; part: P * n7 float64 partials.  y
+// receives the rows rows[0 .. n7).
 int64_t long_tile_width(int elt);
 // Raises the tile kernels' dynamic LDS limit (before the first launch,
 // outside graph capture).
@@ -171,9 +173,11 @@ spmv_status long_tiles_prepare();
 spmv_status launch_long_tile_seg(int64_t n7, int64_t P, int64_t W, const int32_t *rows,
                                  const int32_t *rp, const int32_t *col, int32_t *seg,
                                  hipStream_t s);
+spmv_status launch_long_tile_off(int64_t n7, int64_t W, const int32_t *rows, const int32_t *rp,
+                                 const int32_t *col, uint16_t *off, hipStream_t s);
 spmv_status run_long_tiles(int elt, int64_t n7, int64_t P, int64_t nblocks,
                            const int32_t *blocks, const int32_t *seg, const int32_t *rows,
-                           const int32_t *col, const void *val, const void *x, int64_t n,
+                           const uint16_t *off, const void *val, const void *x, int64_t n,
                            double *part, void *y, hipStream_t s);
 // Build column panels of width w from a CSR matrix whose rows are visited in
 // the binned order `rows`.  cnt: P*(m+1) ints; prow: P*(m+1)+1 ints; inv: m

@@ -441,9 +441,15 @@ __global__ __launch_bounds__(kLongThreads) void k_long_rows_lds(
 // float64 partial per (row, panel), and k_long_tiles_reduce adds a row's
 // partials in panel order and rounds once.  A row's float64 chain is at most
 // (longest segment) / TPR + log2 TPR + panels long.
+//
+// The columns are read as 16-bit offsets into the entry's panel (off[e] =
+// col[e] mod W, written once by k_long_tile_off): a panel holds at most
+// 20480 values, and the entry stream shrinks from 4 + sizeof(T) to
+// 2 + sizeof(T) bytes per entry.
 constexpr int kTileThreads = 1024;
 constexpr int kTileBytes = 81920;   // x per workgroup: two workgroups fill a CU's LDS
 constexpr int kTileUnroll = 4;      // entries per lane loaded ahead
+static_assert(kTileBytes / 4 <= 65536, "panel offsets must fit 16 bits");
 
 //
 // Dispatch order: panels fastest (workgroup w serves panel w mod P of row
@@ -456,8 +462,8 @@ constexpr int kTileUnroll = 4;      // entries per lane loaded ahead
 template <typename T>
 __global__ __launch_bounds__(kTileThreads) void k_long_tiles(
     int64_t n7, int64_t W, int64_t P, const int32_t *__restrict__ blocks,
-    const int32_t *__restrict__ seg, const int32_t *__restrict__ col, const T *__restrict__ val,
-    const T *__restrict__ x, int64_t n, double *__restrict__ part) {
+    const int32_t *__restrict__ seg, const uint16_t *__restrict__ off,
+    const T *__restrict__ val, const T *__restrict__ x, int64_t n, double *__restrict__ part) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int V = 16 / (int)sizeof(T);      // values per 16-byte piece
     typedef T vec __attribute__((ext_vector_type(V)));
@@ -508,27 +514,27 @@ __global__ __launch_bounds__(kTileThreads) void k_long_tiles(
         // segment's end are skipped and whose products there are left out
         // (the same additions, in the same order, as one entry at a time)
         for (; q + (kTileUnroll - 1) * tpr < e; q += kTileUnroll * tpr) {
-            int32_t cc[kTileUnroll];
+            uint32_t cc[kTileUnroll];
             T vv[kTileUnroll];
 #pragma unroll
-            for (int u = 0; u < kTileUnroll; ++u) cc[u] = col[q + u * tpr];
+            for (int u = 0; u < kTileUnroll; ++u) cc[u] = off[q + u * tpr];
 #pragma unroll
             for (int u = 0; u < kTileUnroll; ++u) vv[u] = val[q + u * tpr];
 #pragma unroll
             for (int u = 0; u < kTileUnroll; ++u)
-                acc = fma((double)vv[u], (double)xs[cc[u] - c0], acc);
+                acc = fma((double)vv[u], (double)xs[cc[u]], acc);
         }
         if (q < e) {
             const int k = (int)((e - q + tpr - 1) / tpr);   // 1 .. kTileUnroll - 1
-            int32_t cc[kTileUnroll - 1];
+            uint32_t cc[kTileUnroll - 1];
             T vv[kTileUnroll - 1];
 #pragma unroll
-            for (int u = 0; u < kTileUnroll - 1; ++u) cc[u] = u < k ? col[q + u * tpr] : c0;
+            for (int u = 0; u < kTileUnroll - 1; ++u) cc[u] = u < k ? off[q + u * tpr] : 0u;
 #pragma unroll
             for (int u = 0; u < kTileUnroll - 1; ++u) vv[u] = u < k ? val[q + u * tpr] : T(0);
 #pragma unroll
             for (int u = 0; u < kTileUnroll - 1; ++u) {
-                const double v = fma((double)vv[u], (double)xs[cc[u] - c0], acc);
+                const double v = fma((double)vv[u], (double)xs[cc[u]], acc);
                 acc = u < k ? v : acc;
             }
         }
@@ -590,6 +596,22 @@ __global__ __launch_bounds__(256) void k_long_tile_seg(int64_t n7, int64_t P, in
             hi = mid;
     }
     seg[i] = (int32_t)lo;
+}
+
+// Panel offsets of the long rows' entries: off[e] = col[e] mod W for every
+// entry e of the rows rows[0 .. n7); the other entries of off are not
+// written.  Workgroups take rows in turn, threads the row's entries.
+__global__ __launch_bounds__(256) void k_long_tile_off(int64_t n7, int32_t W,
+                                                       const int32_t *__restrict__ rows,
+                                                       const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ col,
+                                                       uint16_t *__restrict__ off) {
+    for (int64_t r = blockIdx.x; r < n7; r += gridDim.x) {
+        const int32_t row = rows[r];
+        const int64_t e = rp[row + 1];
+        for (int64_t q = rp[row] + threadIdx.x; q < e; q += blockDim.x)
+            off[q] = (uint16_t)(col[q] % W);
+    }
 }
 
 // ---------------------------------------------------------------- BCSR 4x4
@@ -1090,9 +1112,22 @@ spmv_status launch_long_tile_seg(int64_t n7, int64_t P, int64_t W, const int32_t
     return SPMV_OK;
 }
 
+spmv_status launch_long_tile_off(int64_t n7, int64_t W, const int32_t *rows, const int32_t *rp,
+                                 const int32_t *col, uint16_t *off, hipStream_t s) {
+    if (n7 == 0) return SPMV_OK;
+    if (W < 1 || W > 65536) {
+        set_error("long-row tiles: panel width %lld beyond 16-bit offsets", (long long)W);
+        return SPMV_EINVAL;
+    }
+    const unsigned grid = (unsigned)std::min<int64_t>(n7, 4096);
+    k_long_tile_off<<<grid, 256, 0, s>>>(n7, (int32_t)W, rows, rp, col, off);
+    SMAT_LAUNCHED("long_tile_off");
+    return SPMV_OK;
+}
+
 spmv_status run_long_tiles(int elt, int64_t n7, int64_t P, int64_t nblocks,
                            const int32_t *blocks, const int32_t *seg, const int32_t *rows,
-                           const int32_t *col, const void *val, const void *x, int64_t n,
+                           const uint16_t *off, const void *val, const void *x, int64_t n,
                            double *part, void *y, hipStream_t s) {
     if (n7 == 0) return SPMV_OK;
     if (P < 1 || P > 65535 || nblocks < 1 || nblocks > INT_MAX || (elt != 4 && elt != 8)) {
@@ -1109,13 +1144,13 @@ spmv_status run_long_tiles(int elt, int64_t n7, int64_t P, int64_t nblocks,
     const unsigned rg = (unsigned)((n7 + kReduceRows - 1) / kReduceRows);
     if (elt == 8) {
         k_long_tiles<double><<<grid, kTileThreads, kTileBytes, s>>>(
-            n7, W, P, blocks, seg, col, (const double *)val, (const double *)x, n, part);
+            n7, W, P, blocks, seg, off, (const double *)val, (const double *)x, n, part);
         SMAT_LAUNCHED("long_tiles");
         k_long_tiles_reduce<double><<<rg, kReduceRows * kReduceGroups, 0, s>>>(n7, P, rows, part,
                                                                               (double *)y);
     } else {
         k_long_tiles<float><<<grid, kTileThreads, kTileBytes, s>>>(
-            n7, W, P, blocks, seg, col, (const float *)val, (const float *)x, n, part);
+            n7, W, P, blocks, seg, off, (const float *)val, (const float *)x, n, part);
         SMAT_LAUNCHED("long_tiles");
         k_long_tiles_reduce<float><<<rg, kReduceRows * kReduceGroups, 0, s>>>(n7, P, rows, part,
                                                                              (float *)y);
