@@ -123,3 +123,54 @@ def test_galerkin_levels_tensor_vectors_bitwise():
         assert np.array_equal(ref, closed.astype(np.float64)), l
         A.name = f"galerkin27_{g0}^3_level{l}"
         _all_kernels_bitwise(A, x, ref)
+
+
+def test_long_tiles_panel_boundaries_bitwise():
+    """Long rows by x-panel tiles on integer data: every row holds the
+    columns on both sides of every panel boundary (80 KB panels: 10240
+    float64 or 20480 float32 values) plus random ones, so each tile entry's
+    16-bit panel offset takes its extreme values 0 and W - 1.  The products
+    and sums are integers far below 2^24, so y must equal the exact integer
+    product bit for bit, in both dtypes, for the binned CSR kernel and the
+    column panels, and for tiles from rows of 256, 1024 and 4096 entries."""
+    from paper_1210_2536_amd.spmv import Plan
+    rng = np.random.default_rng(1210)
+    n = 30 * 20480 + 777         # many panels of either width, a partial last one, and
+                                 # x above the 2 MiB the column panels need
+    edges = np.unique(np.concatenate([np.arange(w, n, w) + d for w in (10240, 20480)
+                                      for d in (-1, 0)]))
+    edges = edges[(edges >= 0) & (edges < n)]
+    lens = np.concatenate([rng.integers(300, 5000, 1200), rng.integers(1, 30, 4000)])
+    rng.shuffle(lens)
+    rows = []
+    for k in lens:
+        if k >= 300:
+            extra = rng.choice(n, int(k), replace=False)
+            c = np.union1d(np.concatenate([edges, [0, n - 1]]), extra)
+        else:
+            c = np.sort(rng.choice(n, int(k), replace=False))
+        rows.append(c)
+    rp = np.concatenate([[0], np.cumsum([len(c) for c in rows])]).astype(np.int64)
+    col = np.concatenate(rows).astype(np.int32)
+    val = rng.integers(-3, 4, col.size).astype(np.float64)
+    A = S.CSR(len(rows), n, rp, col, val, "tile_edges")
+    x = rng.integers(-4, 5, n).astype(np.float64)
+    ref = np.zeros(A.m)
+    for i in range(A.m):   # exact: integers well inside float64's 2^53
+        ref[i] = float(np.dot(val[rp[i]:rp[i + 1]].astype(np.int64),
+                              x[col[rp[i]:rp[i + 1]]].astype(np.int64)))
+    assert np.abs(ref).max() < 2 ** 24
+    for dt in DTYPES:
+        rp_d, col_d, val_d = dev(A, dt)
+        xd = vec(x, dt)
+        for k in ("csr_adaptive", "csr_panel"):
+            for trm in (256, 1024, 4096):
+                note(f"[exact tiles] {np.dtype(dt).name} {k} tile_row_min={trm}")
+                p = Plan(rp_d, col_d, val_d, n=A.n, selector=k,
+                         params={"long_lds": 3, "tile_row_min": trm})
+                assert p.info()["params"]["long_lds"] == 3
+                assert p.info()["long_rows"] > 0
+                y = p.run(xd).cpu().numpy().astype(np.float64)
+                bad = np.nonzero(y != ref)[0]
+                assert bad.size == 0, (np.dtype(dt).name, k, trm, bad[:5], y[bad[:5]], ref[bad[:5]])
+                p.close()
