@@ -1199,12 +1199,14 @@ spmv_status run_variant(const spmv_plan_s &P, const Variant &V, const void *x, v
 // as many as make about kTimeBatchMs of work (at most kTimeBatchMax), so that
 // launch overhead and timer resolution do not decide between kernels of a
 // few microseconds, and the figure is the steady rate of repeated calls.
-// The median over `reps` such batches is reported, per launch.
+// The median over `reps` such batches is reported, per launch.  With
+// abandon_ms > 0 a candidate whose first batch already takes longer than
+// that per launch is not timed further: that batch's figure is reported.
 constexpr double kTimeBatchMs = 0.05;
 constexpr int kTimeBatchMax = 64;
 
 template <typename Run>
-spmv_status time_calls(Run run, int reps, hipStream_t s, double *ms) {
+spmv_status time_calls(Run run, int reps, hipStream_t s, double *ms, double abandon_ms = 0.0) {
     hipEvent_t a, b;
     SMAT_HIP(hipEventCreate(&a));
     SMAT_HIP(hipEventCreate(&b));
@@ -1228,6 +1230,7 @@ spmv_status time_calls(Run run, int reps, hipStream_t s, double *ms) {
         float f = 0;
         st = batch(inner, &f);
         t.push_back((double)f / inner);
+        if (r == 0 && abandon_ms > 0.0 && t[0] > abandon_ms) break;
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
@@ -1238,8 +1241,8 @@ spmv_status time_calls(Run run, int reps, hipStream_t s, double *ms) {
 }
 
 spmv_status time_variant(const spmv_plan_s &P, const Variant &V, const void *x, void *y,
-                         int reps, hipStream_t s, double *ms) {
-    return time_calls([&] { return run_variant(P, V, x, y, s); }, reps, s, ms);
+                         int reps, hipStream_t s, double *ms, double abandon_ms = 0.0) {
+    return time_calls([&] { return run_variant(P, V, x, y, s); }, reps, s, ms, abandon_ms);
 }
 
 // Parameter points tried by the autotuner for one kernel (the paper's offline
@@ -1406,6 +1409,9 @@ bool same_params(const spmv_params &a, const spmv_params &b) {
 // differences inside run-to-run timing noise would otherwise flip plans of
 // the same matrix between equivalent choices from one process to the next.
 constexpr double kSwitchMargin = 0.03;
+// A point whose first timed batch is this much slower than the best so far
+// is not timed further (it cannot come within kSwitchMargin of winning).
+constexpr double kAbandonRatio = 1.25;
 
 // Time the grid for the chosen kernel and keep the fastest variant.  Every
 // visited point must also reproduce the starting variant's output on the
@@ -1452,7 +1458,7 @@ spmv_status autotune_variant(spmv_plan_s &P, const spmv_features &F, FeatureWork
             continue;
         visited.push_back(V->prm);
         double ms = 0;
-        SMAT_TRY(time_variant(P, *V, xs.p, ys.p, reps, s, &ms));
+        SMAT_TRY(time_variant(P, *V, xs.p, ys.p, reps, s, &ms, best_ms * kAbandonRatio));
         if (m) {
             unsigned h = 0;
             SMAT_HIP(hipMemsetAsync(bad.p, 0, sizeof(unsigned), s));
