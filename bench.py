@@ -480,12 +480,24 @@ def main():
     evs = steps("tuned", a.steps, events=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # the last timed step's outputs, checked below against back-to-back runs
+    step_out = [r["y"].clone() for r in recs] if step_mode != "separate" else None
     if not evs:
         # batch steps: the dominant level kernel is timed launch by launch
         # right after the timed steps, still inside the marked trace region
         evs = per_plan("tuned", a.steps, events=True)
         torch.cuda.synchronize()
     stream_copy(mark_dst, mark_src)
+    step_check = None
+    if step_out is not None:
+        for r in recs:
+            r["tuned"].run(r["x"], r["y"])
+        torch.cuda.synchronize()
+        same = all(torch.equal(o.view(torch.uint8), r["y"].view(torch.uint8))
+                   for o, r in zip(step_out, recs))
+        step_check = {"mode": step_mode, "bitwise_equal_to_back_to_back": same}
+        log(f"step check: {step_check}")
+        del step_out
     # achievable-bandwidth probe: copy 1 GiB (2 GiB of traffic), median of 5
     cp_src = torch.zeros(1 << 28, dtype=torch.float32, device=dev)
     cp_dst = torch.empty_like(cp_src)
@@ -898,6 +910,7 @@ def main():
                    "matrices": len(items), "nnz_per_step": int(flops / 2), "selector": selector,
                    "step": step_mode, "segments": a.segments, "staged": not a.no_staged},
         "step_trial": ml,
+        "step_check": step_check,
         "cold": cold,
         "hbm_gbs": round(hbm_gbs, 1),
         "hbm_frac_peak": round(hbm_gbs / HBM_PEAK_GBS, 4),

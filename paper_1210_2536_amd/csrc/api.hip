@@ -706,8 +706,8 @@ AdaptiveLaunch bins_launch(const unsigned bin_off[kAdaptiveBins + 1], int blo, i
 }
 
 // V.long_tiles false (nothing built) when the partials and segment starts
-// would cost over 1/20 of the long rows' own bytes per run, or no lane
-// count keeps the float64 bound.
+// would cost over 1/kTileExtraShare of the long rows' own bytes per run, or
+// no lane count keeps the float64 bound.
 spmv_status build_long_tiles(const spmv_plan_s &P, Variant &V, const std::vector<int64_t> &len,
                              hipStream_t s) {
     const int64_t n7 = (int64_t)len.size();
@@ -765,10 +765,49 @@ spmv_status build_long_tiles(const spmv_plan_s &P, Variant &V, const std::vector
     SMAT_HIP(hipMemcpyAsync(V.tile_blocks.p, blocks.data(), sizeof(int32_t) * blocks.size(),
                             hipMemcpyHostToDevice, s));
     SMAT_TRY(V.tile_part.alloc(sizeof(double) * (size_t)(NP * n7)));
-    SMAT_TRY(V.tile_off.alloc(sizeof(uint16_t) * (size_t)std::max<int64_t>(1, P.nnz)));
-    SMAT_TRY(launch_long_tile_off(n7, W, V.long_rows.as<int32_t>(), P.rp.as<int32_t>(),
-                                  P.col.as<int32_t>(), V.tile_off.as<uint16_t>(), s));
-    SMAT_HIP(hipStreamSynchronize(s));
+    // The long rows' entries packed in workgroup order -- row block, panel,
+    // row -- so that each workgroup streams one contiguous range: pk[k] is
+    // the first packed entry of row r in panel p, k = NP r0 + p (r1 - r0) +
+    // (r - r0) for the block [r0, r1) holding r, and pk[k + 1] its end.
+    // NP n7 stays below total / 10 (the partials' share above), so int32.
+    std::vector<int32_t> pk((size_t)(NP * n7 + 1)), kb(2 * (size_t)n7);
+    int64_t pos = 0;
+    for (size_t bi = 0; bi < blocks.size(); bi += 3) {
+        const int64_t r0 = blocks[bi], r1 = blocks[bi + 1];
+        for (int64_t p = 0; p < NP; ++p)
+            for (int64_t r = r0; r < r1; ++r) {
+                pk[(size_t)(NP * r0 + p * (r1 - r0) + (r - r0))] = (int32_t)pos;
+                pos += (int64_t)h[(p + 1) * n7 + r] - h[p * n7 + r];
+            }
+        for (int64_t r = r0; r < r1; ++r) {
+            kb[2 * r] = (int32_t)(NP * r0 + (r - r0));
+            kb[2 * r + 1] = (int32_t)(r1 - r0);
+        }
+    }
+    pk[(size_t)(NP * n7)] = (int32_t)pos;
+    if (pos != total) {
+        set_error("long-row tiles: %lld packed entries for %lld", (long long)pos,
+                  (long long)total);
+        return SPMV_EINVAL;
+    }
+    {
+        Dev kbd;
+        SMAT_TRY(kbd.alloc(sizeof(int32_t) * kb.size()));
+        SMAT_TRY(V.tile_pk.alloc(sizeof(int32_t) * pk.size()));
+        SMAT_TRY(V.tile_off.alloc(sizeof(uint16_t) * (size_t)std::max<int64_t>(1, total)));
+        SMAT_TRY(V.tile_val.alloc((size_t)P.elt * (size_t)std::max<int64_t>(1, total)));
+        SMAT_HIP(hipMemcpyAsync(kbd.p, kb.data(), sizeof(int32_t) * kb.size(),
+                                hipMemcpyHostToDevice, s));
+        SMAT_HIP(hipMemcpyAsync(V.tile_pk.p, pk.data(), sizeof(int32_t) * pk.size(),
+                                hipMemcpyHostToDevice, s));
+        SMAT_TRY(launch_long_tile_pack(n7, NP, W, V.long_rows.as<int32_t>(), P.rp.as<int32_t>(),
+                                       P.col.as<int32_t>(), P.val.p, P.elt,
+                                       V.tile_seg.as<int32_t>(), kbd.as<int32_t>(),
+                                       V.tile_pk.as<int32_t>(), V.tile_off.as<uint16_t>(),
+                                       V.tile_val.p, s));
+        SMAT_HIP(hipStreamSynchronize(s));
+    }
+    V.tile_seg.release();   // the CSR-position segment starts are not needed to run
     V.tile_P = NP;
     V.tile_nb = (int64_t)blocks.size() / 3;
     V.long_tiles = true;
@@ -1122,8 +1161,8 @@ spmv_status run_long_rows(const spmv_plan_s &P, const Variant &V, const void *x,
                           hipStream_t s) {
     if (V.long_tiles)
         return run_long_tiles(P.elt, V.n_long, V.tile_P, V.tile_nb, V.tile_blocks.as<int32_t>(),
-                              V.tile_seg.as<int32_t>(), V.long_rows.as<int32_t>(),
-                              V.tile_off.as<uint16_t>(), P.val.p, x, P.n,
+                              V.tile_pk.as<int32_t>(), V.long_rows.as<int32_t>(),
+                              V.tile_off.as<uint16_t>(), V.tile_val.p, x, P.n,
                               V.tile_part.as<double>(), y, s);
     return run_long_rows_lds(V.long_tpr, V.n_long, V.long_rows.as<int32_t>(), P.rp.as<int32_t>(),
                              P.col.as<int32_t>(), P.val.as<double>(), (const double *)x, P.n,

@@ -160,12 +160,15 @@ spmv_status run_long_rows_lds(int tpr, int64_t nrows, const int32_t *rows, const
                               const int32_t *col, const double *val, const double *x, int64_t n,
                               double *y, hipStream_t s);
 // Long rows by tiles: x panels of long_tile_width(elt) values, workgroup
-// (row block, panel).  seg: (P + 1) * n7 segment starts, filled by
-// launch_long_tile_seg from the rows (ascending columns); off: nnz 16-bit
-// panel offsets of the columns, filled for the long rows' entries by
-// launch_long_tile_off; blocks: nblocks triples (first row, end row, log2
-// lanes per row) over the rows' order; part: P * n7 float64 partials.  y
-// receives the rows rows[0 .. n7).
+// (row block, panel).  seg: (P + 1) * n7 segment starts in CSR positions,
+// filled by launch_long_tile_seg from the rows (ascending columns); blocks:
+// nblocks triples (first row, end row, log2 lanes per row) over the rows'
+// order.  The entries are packed by launch_long_tile_pack in (row block,
+// panel, row) order: pk[k], k = P r0 + p (r1 - r0) + (r - r0) for the block
+// [r0, r1) holding r, is row r's first entry in panel p and pk[k + 1] its
+// end (P n7 + 1 ints); off (16-bit column - p W) and val hold the packed
+// entries, kb two ints per row (k at p = 0, r1 - r0).  part: P * n7 float64
+// partials.  y receives the rows rows[0 .. n7).
 int64_t long_tile_width(int elt);
 // Raises the tile kernels' dynamic LDS limit (before the first launch,
 // outside graph capture).
@@ -173,10 +176,12 @@ spmv_status long_tiles_prepare();
 spmv_status launch_long_tile_seg(int64_t n7, int64_t P, int64_t W, const int32_t *rows,
                                  const int32_t *rp, const int32_t *col, int32_t *seg,
                                  hipStream_t s);
-spmv_status launch_long_tile_off(int64_t n7, int64_t W, const int32_t *rows, const int32_t *rp,
-                                 const int32_t *col, uint16_t *off, hipStream_t s);
+spmv_status launch_long_tile_pack(int64_t n7, int64_t P, int64_t W, const int32_t *rows,
+                                  const int32_t *rp, const int32_t *col, const void *val, int elt,
+                                  const int32_t *seg, const int32_t *kb, const int32_t *pk,
+                                  uint16_t *off, void *pval, hipStream_t s);
 spmv_status run_long_tiles(int elt, int64_t n7, int64_t P, int64_t nblocks,
-                           const int32_t *blocks, const int32_t *seg, const int32_t *rows,
+                           const int32_t *blocks, const int32_t *pk, const int32_t *rows,
                            const uint16_t *off, const void *val, const void *x, int64_t n,
                            double *part, void *y, hipStream_t s);
 // Build column panels of width w from a CSR matrix whose rows are visited in

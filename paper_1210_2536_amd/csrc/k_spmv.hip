@@ -442,9 +442,10 @@ __global__ __launch_bounds__(kLongThreads) void k_long_rows_lds(
 // partials in panel order and rounds once.  A row's float64 chain is at most
 // (longest segment) / TPR + log2 TPR + panels long.
 //
-// The columns are read as 16-bit offsets into the entry's panel (off[e] =
-// col[e] mod W, written once by k_long_tile_off): a panel holds at most
-// 20480 values, and the entry stream shrinks from 4 + sizeof(T) to
+// The entries come packed in workgroup order (row block, panel, row; see
+// k_long_tile_pack), so a workgroup streams one contiguous range, and their
+// columns as 16-bit offsets into the panel (col - p W): a panel holds at
+// most 20480 values, and the entry stream shrinks from 4 + sizeof(T) to
 // 2 + sizeof(T) bytes per entry.
 constexpr int kTileThreads = 1024;
 constexpr int kTileBytes = 81920;   // x per workgroup: two workgroups fill a CU's LDS
@@ -462,7 +463,7 @@ static_assert(kTileBytes / 4 <= 65536, "panel offsets must fit 16 bits");
 template <typename T>
 __global__ __launch_bounds__(kTileThreads) void k_long_tiles(
     int64_t n7, int64_t W, int64_t P, const int32_t *__restrict__ blocks,
-    const int32_t *__restrict__ seg, const uint16_t *__restrict__ off,
+    const int32_t *__restrict__ pk, const uint16_t *__restrict__ off,
     const T *__restrict__ val, const T *__restrict__ x, int64_t n, double *__restrict__ part) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int V = 16 / (int)sizeof(T);      // values per 16-byte piece
@@ -494,7 +495,8 @@ __global__ __launch_bounds__(kTileThreads) void k_long_tiles(
     const int t = threadIdx.x & (tpr - 1);
     const int grp = threadIdx.x >> lg;
     const int G = kTileThreads >> lg;
-    const int32_t *sb = seg + p * n7, *se = seg + (p + 1) * n7;
+    // row r's packed range in panel p: [sb[r], se[r])
+    const int32_t *sb = pk + (P * r0 + p * (r1 - r0) - r0), *se = sb + 1;
     double *pp = part + p * n7;
     // every lane of a wave runs the same iterations (the shuffles need them);
     // the next group's segment bounds are loaded before the current group's
@@ -598,19 +600,27 @@ __global__ __launch_bounds__(256) void k_long_tile_seg(int64_t n7, int64_t P, in
     seg[i] = (int32_t)lo;
 }
 
-// Panel offsets of the long rows' entries: off[e] = col[e] mod W for every
-// entry e of the rows rows[0 .. n7); the other entries of off are not
-// written.  Workgroups take rows in turn, threads the row's entries.
-__global__ __launch_bounds__(256) void k_long_tile_off(int64_t n7, int32_t W,
-                                                       const int32_t *__restrict__ rows,
-                                                       const int32_t *__restrict__ rp,
-                                                       const int32_t *__restrict__ col,
-                                                       uint16_t *__restrict__ off) {
+// Packing of the long rows' entries for the tiles: entry e of row rows[r],
+// in panel p = col / W, goes to pk[kb[2r] + p kb[2r+1]] + (e - seg[p n7 +
+// r]) with its column as col - p W (16 bits) and its value's bits.
+// Workgroups take rows in turn, threads the row's entries.
+template <typename U>
+__global__ __launch_bounds__(256) void k_long_tile_pack(
+    int64_t n7, int32_t W, const int32_t *__restrict__ rows, const int32_t *__restrict__ rp,
+    const int32_t *__restrict__ col, const U *__restrict__ val, const int32_t *__restrict__ seg,
+    const int32_t *__restrict__ kb, const int32_t *__restrict__ pk, uint16_t *__restrict__ off,
+    U *__restrict__ pval) {
     for (int64_t r = blockIdx.x; r < n7; r += gridDim.x) {
         const int32_t row = rows[r];
-        const int64_t e = rp[row + 1];
-        for (int64_t q = rp[row] + threadIdx.x; q < e; q += blockDim.x)
-            off[q] = (uint16_t)(col[q] % W);
+        const int64_t k0 = kb[2 * r], ks = kb[2 * r + 1];
+        const int64_t e1 = rp[row + 1];
+        for (int64_t e = rp[row] + threadIdx.x; e < e1; e += blockDim.x) {
+            const int32_t c = col[e];
+            const int64_t p = c / W;
+            const int64_t dst = (int64_t)pk[k0 + p * ks] + (e - seg[p * n7 + r]);
+            off[dst] = (uint16_t)(c - p * W);
+            pval[dst] = val[e];
+        }
     }
 }
 
@@ -1112,21 +1122,30 @@ spmv_status launch_long_tile_seg(int64_t n7, int64_t P, int64_t W, const int32_t
     return SPMV_OK;
 }
 
-spmv_status launch_long_tile_off(int64_t n7, int64_t W, const int32_t *rows, const int32_t *rp,
-                                 const int32_t *col, uint16_t *off, hipStream_t s) {
+spmv_status launch_long_tile_pack(int64_t n7, int64_t P, int64_t W, const int32_t *rows,
+                                  const int32_t *rp, const int32_t *col, const void *val, int elt,
+                                  const int32_t *seg, const int32_t *kb, const int32_t *pk,
+                                  uint16_t *off, void *pval, hipStream_t s) {
     if (n7 == 0) return SPMV_OK;
-    if (W < 1 || W > 65536) {
+    if (W < 1 || W > 65536 || P < 1 || (elt != 4 && elt != 8)) {
         set_error("long-row tiles: panel width %lld beyond 16-bit offsets", (long long)W);
         return SPMV_EINVAL;
     }
     const unsigned grid = (unsigned)std::min<int64_t>(n7, 4096);
-    k_long_tile_off<<<grid, 256, 0, s>>>(n7, (int32_t)W, rows, rp, col, off);
-    SMAT_LAUNCHED("long_tile_off");
+    if (elt == 8)
+        k_long_tile_pack<uint64_t><<<grid, 256, 0, s>>>(n7, (int32_t)W, rows, rp, col,
+                                                        (const uint64_t *)val, seg, kb, pk, off,
+                                                        (uint64_t *)pval);
+    else
+        k_long_tile_pack<uint32_t><<<grid, 256, 0, s>>>(n7, (int32_t)W, rows, rp, col,
+                                                        (const uint32_t *)val, seg, kb, pk, off,
+                                                        (uint32_t *)pval);
+    SMAT_LAUNCHED("long_tile_pack");
     return SPMV_OK;
 }
 
 spmv_status run_long_tiles(int elt, int64_t n7, int64_t P, int64_t nblocks,
-                           const int32_t *blocks, const int32_t *seg, const int32_t *rows,
+                           const int32_t *blocks, const int32_t *pk, const int32_t *rows,
                            const uint16_t *off, const void *val, const void *x, int64_t n,
                            double *part, void *y, hipStream_t s) {
     if (n7 == 0) return SPMV_OK;
@@ -1144,13 +1163,13 @@ spmv_status run_long_tiles(int elt, int64_t n7, int64_t P, int64_t nblocks,
     const unsigned rg = (unsigned)((n7 + kReduceRows - 1) / kReduceRows);
     if (elt == 8) {
         k_long_tiles<double><<<grid, kTileThreads, kTileBytes, s>>>(
-            n7, W, P, blocks, seg, off, (const double *)val, (const double *)x, n, part);
+            n7, W, P, blocks, pk, off, (const double *)val, (const double *)x, n, part);
         SMAT_LAUNCHED("long_tiles");
         k_long_tiles_reduce<double><<<rg, kReduceRows * kReduceGroups, 0, s>>>(n7, P, rows, part,
                                                                               (double *)y);
     } else {
         k_long_tiles<float><<<grid, kTileThreads, kTileBytes, s>>>(
-            n7, W, P, blocks, seg, off, (const float *)val, (const float *)x, n, part);
+            n7, W, P, blocks, pk, off, (const float *)val, (const float *)x, n, part);
         SMAT_LAUNCHED("long_tiles");
         k_long_tiles_reduce<float><<<rg, kReduceRows * kReduceGroups, 0, s>>>(n7, P, rows, part,
                                                                              (float *)y);

@@ -114,7 +114,7 @@ struct Variant {
     // long rows by tiles (x panel per workgroup) instead of x chunks
     bool long_tiles = false;
     int64_t tile_P = 0, tile_nb = 0;
-    Dev tile_seg, tile_blocks, tile_part, tile_off;
+    Dev tile_seg, tile_blocks, tile_part, tile_off, tile_pk, tile_val;
     // BCSR 4x4
     Dev brp, bcol, bval, bpres;
     int64_t nblocks = 0;
@@ -124,7 +124,8 @@ struct Variant {
                bin_rows.bytes + bin_scratch.bytes + split_segs.bytes + split_partials.bytes +
                split_begin.bytes + split_rows.bytes + prow.bytes + pcol.bytes + pval.bytes +
                ppart.bytes + brp.bytes + bcol.bytes + bval.bytes + bpres.bytes + long_rows.bytes +
-               tile_seg.bytes + tile_blocks.bytes + tile_part.bytes + tile_off.bytes;
+               tile_seg.bytes + tile_blocks.bytes + tile_part.bytes + tile_off.bytes +
+               tile_pk.bytes + tile_val.bytes;
     }
 };
 
