@@ -298,11 +298,11 @@ def main():
                  p.get("panel_direct_max", -1) >= p["adaptive_rows_per_lane"])
         rest = "_rest" if long or short else ""
         if short:
-            long = f" + k_csr_adaptive_rest<{t}, {nt}>" + long
+            long = f" + k_csr_adaptive_rest<{t}, {nt}, false>" + long
         if k == "csr_vector":
             return f"k_csr_vector<{t}, {p['vector_lanes']}, {nt}>"
-        if k == "csr_adaptive":
-            return f"k_csr_adaptive{rest}<{t}, {nt}>{long}"
+        if k == "csr_adaptive":   # rows read from the plan's copy in binned order
+            return f"k_csr_adaptive{rest}<{t}, {nt}, true>{long}"
         v = (16 // (8 if t == "double" else 4)) if p["wide_loads"] == 1 else 1
         if k == "ell":
             return f"k_ell<{t}, {p['ell_unroll']}, {nt}, {v}>"

@@ -140,9 +140,21 @@ struct AdaptiveLaunch {
 };
 // rest: the launch geometry leaves out the longest bin (another kernel
 // takes those rows); launched under its own kernel name.
+// pk: rp / col / val are the copy in binned order (launch_pack_binned),
+// indexed by binned position, instead of the plan's CSR indexed by row.
 spmv_status run_csr_adaptive(int elt, bool nt, bool rest, const AdaptiveLaunch &a,
                              const int32_t *rows, const int32_t *rp, const int32_t *col,
-                             const void *val, const void *x, void *y, hipStream_t s);
+                             const void *val, const void *x, void *y, hipStream_t s,
+                             bool pk = false);
+// Copy of the entries of the rows at binned positions [0, hi) in that order:
+// launch_binned_scan fills brp (hi + 1 ints: each position's first entry,
+// then the total; len hi ints and scan hi / 4096 + 2 unsigned of scratch),
+// launch_pack_binned the entries bcol / bval (brp[hi] of them).
+spmv_status launch_binned_scan(int64_t hi, const int32_t *rows, const int32_t *rp, int32_t *len,
+                               unsigned *scan, int32_t *brp, hipStream_t s);
+spmv_status launch_pack_binned(int64_t hi, const int32_t *rows, const int32_t *rp,
+                               const int32_t *col, const void *val, int elt, const int32_t *brp,
+                               int32_t *bcol, void *bval, hipStream_t s);
 // Column panels; prow is P x (m+1) position-indexed segment starts.  With
 // `partial` (P x m values) all panels run in one launch, one per XCD, and a
 // second kernel adds the partials of binned positions [red_lo, red_hi);

@@ -58,9 +58,12 @@ __global__ __launch_bounds__(1024) void k_csr_vector(int64_t nrows,
 // Rows binned by length, all bins in one launch.  Workgroups are handed out
 // longest bin first: launch position q serves bin 7 - q, where bin 7 gives a
 // whole 256-thread workgroup to each row and bins 6..0 give 64..1 lanes.
+// PK: the row pointers, columns and values are the plan's copy in binned
+// row order (k_pack_binned), indexed by binned position, so that the rows
+// of a bin read their entries from one contiguous range.
 constexpr int kRowBlock = 512;     // split-row segments
 
-template <typename T, bool NT>
+template <typename T, bool NT, bool PK>
 __global__ __launch_bounds__(kAdaptBlock) void k_csr_adaptive(AdaptiveLaunch a,
                                                               const int32_t *__restrict__ rows,
                                                               const int32_t *__restrict__ rp,
@@ -69,19 +72,51 @@ __global__ __launch_bounds__(kAdaptBlock) void k_csr_adaptive(AdaptiveLaunch a,
                                                               const T *__restrict__ x,
                                                               T *__restrict__ y) {
     __shared__ double part[kAdaptBlock / kWave];
-    adaptive_block<T, NT>(a, blockIdx.x, rows, rp, col, val, x, y, part);
+    adaptive_block<T, NT, PK>(a, blockIdx.x, rows, rp, col, val, x, y, part);
 }
 
 // The same launch without the longest bin, whose rows another kernel takes
 // (the launch geometry has it empty); its own name keeps the two launch
 // forms apart in kernel traces.  Likewise the *_rest panel kernels below.
-template <typename T, bool NT>
+template <typename T, bool NT, bool PK>
 __global__ __launch_bounds__(kAdaptBlock) void k_csr_adaptive_rest(
     AdaptiveLaunch a, const int32_t *__restrict__ rows, const int32_t *__restrict__ rp,
     const int32_t *__restrict__ col, const T *__restrict__ val, const T *__restrict__ x,
     T *__restrict__ y) {
     __shared__ double part[kAdaptBlock / kWave];
-    adaptive_block<T, NT>(a, blockIdx.x, rows, rp, col, val, x, y, part);
+    adaptive_block<T, NT, PK>(a, blockIdx.x, rows, rp, col, val, x, y, part);
+}
+
+// The entries of the rows at binned positions [0, hi) copied in that order:
+// brp (hi + 1 entries, filled by an exclusive scan of the row lengths) gives
+// position pos's range in bcol / bval.  One wave per position, lanes
+// striding the row; values are copied as bits.
+template <typename U>
+__global__ __launch_bounds__(256) void k_pack_binned(int64_t hi, const int32_t *__restrict__ rows,
+                                                     const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ col,
+                                                     const U *__restrict__ val,
+                                                     const int32_t *__restrict__ brp,
+                                                     int32_t *__restrict__ bcol,
+                                                     U *__restrict__ bval) {
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / 64);
+    const int lane = threadIdx.x & 63;
+    for (int64_t pos = blockIdx.x * (int64_t)(blockDim.x / 64) + threadIdx.x / 64; pos < hi;
+         pos += waves) {
+        const int32_t row = rows[pos];
+        const int64_t b = rp[row], e = rp[row + 1], d = (int64_t)brp[pos] - b;
+        for (int64_t q = b + lane; q < e; q += 64) {
+            bcol[q + d] = col[q];
+            bval[q + d] = val[q];
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_binned_lengths(int64_t hi, const int32_t *__restrict__ rows,
+                                                        const int32_t *__restrict__ rp,
+                                                        int32_t *__restrict__ len) {
+    const int64_t pos = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (pos < hi) len[pos] = rp[rows[pos] + 1] - rp[rows[pos]];
 }
 
 // ---------------------------------------------------------------- CSR panels
@@ -900,22 +935,30 @@ spmv_status coo_dispatch(int64_t m, int64_t nnz, const int32_t *ri, const int32_
     return SPMV_OK;
 }
 
+template <typename T, bool NT, bool PK>
+void adaptive_launch(bool rest, unsigned nblk, const AdaptiveLaunch &a, const int32_t *rows,
+                     const int32_t *rp, const int32_t *col, const T *val, const T *x, T *y,
+                     hipStream_t s) {
+    if (rest)
+        k_csr_adaptive_rest<T, NT, PK><<<nblk, kAdaptBlock, 0, s>>>(a, rows, rp, col, val, x, y);
+    else
+        k_csr_adaptive<T, NT, PK><<<nblk, kAdaptBlock, 0, s>>>(a, rows, rp, col, val, x, y);
+}
+
 template <typename T>
-spmv_status adaptive_dispatch(bool nt, bool rest, const AdaptiveLaunch &a, const int32_t *rows,
-                              const int32_t *rp, const int32_t *col, const T *val, const T *x,
-                              T *y, hipStream_t s) {
+spmv_status adaptive_dispatch(bool nt, bool rest, bool pk, const AdaptiveLaunch &a,
+                              const int32_t *rows, const int32_t *rp, const int32_t *col,
+                              const T *val, const T *x, T *y, hipStream_t s) {
     const unsigned nblk = a.first[8];
     if (nblk == 0) return SPMV_OK;
-    if (rest) {
-        if (nt)
-            k_csr_adaptive_rest<T, true><<<nblk, kAdaptBlock, 0, s>>>(a, rows, rp, col, val, x, y);
-        else
-            k_csr_adaptive_rest<T, false><<<nblk, kAdaptBlock, 0, s>>>(a, rows, rp, col, val, x, y);
-    } else if (nt) {
-        k_csr_adaptive<T, true><<<nblk, kAdaptBlock, 0, s>>>(a, rows, rp, col, val, x, y);
-    } else {
-        k_csr_adaptive<T, false><<<nblk, kAdaptBlock, 0, s>>>(a, rows, rp, col, val, x, y);
-    }
+    if (nt && pk)
+        adaptive_launch<T, true, true>(rest, nblk, a, rows, rp, col, val, x, y, s);
+    else if (nt)
+        adaptive_launch<T, true, false>(rest, nblk, a, rows, rp, col, val, x, y, s);
+    else if (pk)
+        adaptive_launch<T, false, true>(rest, nblk, a, rows, rp, col, val, x, y, s);
+    else
+        adaptive_launch<T, false, false>(rest, nblk, a, rows, rp, col, val, x, y, s);
     SMAT_LAUNCHED("csr_adaptive");
     return SPMV_OK;
 }
@@ -1066,12 +1109,38 @@ spmv_status run_csr_vector(int elt, bool nt, int lanes, int64_t nrows, const int
 
 spmv_status run_csr_adaptive(int elt, bool nt, bool rest, const AdaptiveLaunch &a,
                              const int32_t *rows, const int32_t *rp, const int32_t *col,
-                             const void *val, const void *x, void *y, hipStream_t s) {
+                             const void *val, const void *x, void *y, hipStream_t s, bool pk) {
     if (elt == 8)
-        return adaptive_dispatch<double>(nt, rest, a, rows, rp, col, (const double *)val,
+        return adaptive_dispatch<double>(nt, rest, pk, a, rows, rp, col, (const double *)val,
                                          (const double *)x, (double *)y, s);
-    return adaptive_dispatch<float>(nt, rest, a, rows, rp, col, (const float *)val,
+    return adaptive_dispatch<float>(nt, rest, pk, a, rows, rp, col, (const float *)val,
                                     (const float *)x, (float *)y, s);
+}
+
+spmv_status launch_binned_scan(int64_t hi, const int32_t *rows, const int32_t *rp, int32_t *len,
+                               unsigned *scan, int32_t *brp, hipStream_t s) {
+    if (hi <= 0) {
+        SMAT_HIP(hipMemsetAsync(brp, 0, sizeof(int32_t), s));
+        return SPMV_OK;
+    }
+    k_binned_lengths<<<(unsigned)((hi + 255) / 256), 256, 0, s>>>(hi, rows, rp, len);
+    SMAT_LAUNCHED("binned_lengths");
+    return launch_exclusive_scan_rows(hi, len, brp, scan, s);
+}
+
+spmv_status launch_pack_binned(int64_t hi, const int32_t *rows, const int32_t *rp,
+                               const int32_t *col, const void *val, int elt, const int32_t *brp,
+                               int32_t *bcol, void *bval, hipStream_t s) {
+    if (hi <= 0) return SPMV_OK;
+    const unsigned grid = (unsigned)std::min<int64_t>((hi + 3) / 4, 65536);
+    if (elt == 8)
+        k_pack_binned<uint64_t><<<grid, 256, 0, s>>>(hi, rows, rp, col, (const uint64_t *)val, brp,
+                                                     bcol, (uint64_t *)bval);
+    else
+        k_pack_binned<uint32_t><<<grid, 256, 0, s>>>(hi, rows, rp, col, (const uint32_t *)val, brp,
+                                                     bcol, (uint32_t *)bval);
+    SMAT_LAUNCHED("pack_binned");
+    return SPMV_OK;
 }
 
 spmv_status long_rows_lds_prepare() {

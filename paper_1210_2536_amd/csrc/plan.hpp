@@ -91,8 +91,10 @@ struct Variant {
     // DIA
     Dev dia_off, dia_data, dia_present, dia_win;
     int D = 0, nwin = 0, max_span = 0;
-    // CSR adaptive
+    // CSR adaptive; binned_*: the entries of the launch's rows in
+    // binned order (the launch reads them, the plan's CSR serves the rest)
     Dev bin_rows, bin_scratch, split_segs, split_partials, split_begin, split_rows;
+    Dev binned_rp, binned_col, binned_val;
     unsigned bin_off[kAdaptiveBins + 1] = {};
     int bin_lanes[kAdaptiveBins] = {};
     AdaptiveLaunch alaunch{};
@@ -125,7 +127,8 @@ struct Variant {
                split_begin.bytes + split_rows.bytes + prow.bytes + pcol.bytes + pval.bytes +
                ppart.bytes + brp.bytes + bcol.bytes + bval.bytes + bpres.bytes + long_rows.bytes +
                tile_seg.bytes + tile_blocks.bytes + tile_part.bytes + tile_off.bytes +
-               tile_pk.bytes + tile_val.bytes;
+               tile_pk.bytes + tile_val.bytes + binned_rp.bytes + binned_col.bytes +
+               binned_val.bytes;
     }
 };
 

@@ -91,7 +91,7 @@ __device__ __forceinline__ double csr_row_block(int64_t row, const int32_t *__re
 // row; 6..0: 64..1 lanes per row) and its rows in the binned order `rows`.
 constexpr int kAdaptBlock = 256;
 
-template <typename T, int L, bool NT>
+template <typename T, int L, bool NT, bool PK = false>
 __device__ __forceinline__ void adaptive_lanes(unsigned local, unsigned rbeg, unsigned rend,
                                                const int32_t *__restrict__ rows,
                                                const int32_t *__restrict__ rp,
@@ -102,14 +102,14 @@ __device__ __forceinline__ void adaptive_lanes(unsigned local, unsigned rbeg, un
     int lane = threadIdx.x & (L - 1);
     if (r < rend) {
         int64_t row = rows[r];
-        double acc = csr_row_lanes<T, L, NT>(row, lane, rp, col, val, x);
+        double acc = csr_row_lanes<T, L, NT>(PK ? r : row, lane, rp, col, val, x);
         if (lane == 0) y[row] = (T)acc;
     }
 }
 
 // Every thread of the (kAdaptBlock-thread) workgroup must call it; `part` is
 // LDS scratch of kAdaptBlock / 64 doubles.
-template <typename T, bool NT>
+template <typename T, bool NT, bool PK = false>
 __device__ __forceinline__ void adaptive_block(const AdaptiveLaunch &a, unsigned bid,
                                                const int32_t *__restrict__ rows,
                                                const int32_t *__restrict__ rp,
@@ -124,17 +124,18 @@ __device__ __forceinline__ void adaptive_block(const AdaptiveLaunch &a, unsigned
     switch (b) {
     case 7: {
         int64_t row = rows[rb + local];
-        double s = csr_row_block<T, kAdaptBlock, NT>(row, rp, col, val, x, part);
+        double s = csr_row_block<T, kAdaptBlock, NT>(PK ? (int64_t)(rb + local) : row, rp, col,
+                                                     val, x, part);
         if (threadIdx.x == 0) y[row] = (T)s;
         break;
     }
-    case 6: adaptive_lanes<T, 64, NT>(local, rb, re, rows, rp, col, val, x, y); break;
-    case 5: adaptive_lanes<T, 32, NT>(local, rb, re, rows, rp, col, val, x, y); break;
-    case 4: adaptive_lanes<T, 16, NT>(local, rb, re, rows, rp, col, val, x, y); break;
-    case 3: adaptive_lanes<T, 8, NT>(local, rb, re, rows, rp, col, val, x, y); break;
-    case 2: adaptive_lanes<T, 4, NT>(local, rb, re, rows, rp, col, val, x, y); break;
-    case 1: adaptive_lanes<T, 2, NT>(local, rb, re, rows, rp, col, val, x, y); break;
-    default: adaptive_lanes<T, 1, NT>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 6: adaptive_lanes<T, 64, NT, PK>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 5: adaptive_lanes<T, 32, NT, PK>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 4: adaptive_lanes<T, 16, NT, PK>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 3: adaptive_lanes<T, 8, NT, PK>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 2: adaptive_lanes<T, 4, NT, PK>(local, rb, re, rows, rp, col, val, x, y); break;
+    case 1: adaptive_lanes<T, 2, NT, PK>(local, rb, re, rows, rp, col, val, x, y); break;
+    default: adaptive_lanes<T, 1, NT, PK>(local, rb, re, rows, rp, col, val, x, y); break;
     }
 }
 
