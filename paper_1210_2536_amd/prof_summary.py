@@ -1,6 +1,6 @@
 """Summary of rocprofv3 CSV output for a bench.py run.
 
-usage: python -m paper_1210_2536_amd.prof_summary TRACE_CSV BENCH_LOG [FETCH_CSV WRITE_CSV]
+usage: python -m paper_1210_2536_amd.prof_summary TRACE_CSV BENCH_LOG [FETCH_CSV [WRITE_CSV]]
 
 TRACE_CSV is the kernel trace (--kernel-trace -f csv) of the bench command,
 BENCH_LOG that run's output (its last JSON line names the dominant kernel;
@@ -108,6 +108,15 @@ def main(argv=None):
               f"algorithmic {B['roofline']['bytes_per_launch']} bytes per launch")
         print(json.dumps({"traffic_bytes_per_launch": int(fb + wb), "fetch_factor": ff,
                           "write_factor": fw}))
+    elif fetch_csv:
+        # reads only: no traffic figure (that needs both counters)
+        cf, nf, tf = pmc(fetch_csv, dom)
+        ff = (1 << 30) / (cf * 1024.0)
+        fb = tf / nf * ff * 1024.0
+        print(f"copy calibration: the 1 GiB copy reads FETCH_SIZE {cf:.0f} KiB (factor {ff:.4f})")
+        print(f"dominant kernel reads: {nf} launches in the counter run's timed region, "
+              f"{fb:.0f} bytes fetched per launch (no WRITE_SIZE run); algorithmic "
+              f"{B['roofline']['bytes_per_launch']} bytes per launch")
 
 
 if __name__ == "__main__":
