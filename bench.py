@@ -365,6 +365,41 @@ def main():
         for ev in join_evs:
             main.wait_event(ev)
 
+    # ---- batched step: the dominant kernel's plans first, alone (as above);
+    # then the SpMVs under SMALL_MS in one persistent launch per value type
+    # (spmv_batch mode 0; the kinds it does not hold run right after it on
+    # the same stream), each on a side stream or all on the current one,
+    # beside the larger SpMVs back to back on the current stream.
+    small_batches = []
+    if small_recs and not a.no_batch:
+        from paper_1210_2536_amd.spmv import Batch as _Batch
+        by_dtype = {}
+        for r in small_recs:
+            by_dtype.setdefault(r["tuned"].dtype, []).append(r)
+        for rs in by_dtype.values():
+            b = _Batch([r["tuned"] for r in rs], mode=0)
+            bx, by = [r["x"] for r in rs], [r["y"] for r in rs]
+            b.tune(bx, by)
+            small_batches.append((b, bx, by))
+    batch_evs = [torch.cuda.Event() for _ in small_batches]
+
+    def batched_rest(on_side):
+        main = torch.cuda.current_stream()
+        if on_side:
+            fork_ev.record(main)
+            for st, (b, bx, by), ev in zip(side, small_batches, batch_evs):
+                st.wait_event(fork_ev)
+                b.run(bx, by, stream=st)
+                ev.record(st)
+        else:
+            for b, bx, by in small_batches:
+                b.run(bx, by)
+        for r in rest_recs:
+            r["tuned"].run(r["x"], r["y"])
+        if on_side:
+            for ev in batch_evs:
+                main.wait_event(ev)
+
     # ---- the step as one captured graph of every plan's launches (and, for
     # the multilevel workloads, as one persistent launch); a short trial
     # against plain back-to-back runs picks the mode
@@ -409,6 +444,13 @@ def main():
             ml["trial_ms"]["streams"] = trial(streams)
             ml["streams"] = {"side_streams": len(side), "small_ms": SMALL_MS,
                              "small_plans": len(small_recs)}
+        if small_batches:
+            for name, on_side in (("batched", False), ("batched_streams", True)):
+                def bstep(on_side=on_side):
+                    for r in dom_recs:
+                        r["tuned"].run(r["x"], r["y"])
+                    batched_rest(on_side)
+                ml["trial_ms"][name] = trial(bstep)
         ml["mode"] = min(ml["trial_ms"], key=ml["trial_ms"].get)
         if replay_step:
             ml["mode"] = replay_step  # profile the recorded run's step, not this trial's pick
@@ -418,11 +460,14 @@ def main():
     # ---- timed region: K steps of every tuned SpMV
     def steps(which, K, events=False):
         evs = []
-        if which == "tuned" and step_mode == "streams":
+        if which == "tuned" and step_mode in ("streams", "batched", "batched_streams"):
             pairs = event_pairs(K * len(dom_recs)) if events else None
             for _ in range(K):
                 evs += per_plan(which, 1, events, dom_recs, pairs)
-                concurrent_rest()
+                if step_mode == "streams":
+                    concurrent_rest()
+                else:
+                    batched_rest(step_mode == "batched_streams")
             return evs
         if which == "tuned" and step_mode != "separate":
             # a batch launch hides the levels' kernels from stream events

@@ -490,17 +490,19 @@ spmv_status spmv_mlp_adam(float *params_dev, const float *grad_dev, float *adam_
                           float *adam_v_dev, int64_t n_params, int32_t step, float lr,
                           float beta1, float beta2, float eps, void *stream);
 
-/* Multilevel batch (the AMG setting of Section 1): run y_l = A_l x_l for all
- * plans in one launch (mode 0, persistent work-queue kernel) or as one
- * captured HIP graph (mode 1).  Plans stay owned by the caller and must
- * outlive the batch.  Persistent mode covers CSR_SCALAR, CSR_VECTOR,
- * CSR_ADAPTIVE (unless rows were split into segments or long rows use
- * their own kernel), ELL, DIA, DIA_DIRECT and BCSR levels, each with its
- * plan's tile shape, in a kernel compiled for just the level kinds present;
- * levels with other kernels are launched separately on the same stream,
- * after the persistent kernel.  Mode 0 takes 1..16 plans of one dtype; mode 1 takes 1..4096
- * plans of any dtypes and kernels (every spmv_run of the batch, in order,
- * captured on the first run and again whenever the vectors change).
+/* Multilevel batch (the AMG setting of Section 1), or any set of independent
+ * SpMVs: run y_l = A_l x_l for all plans in one launch (mode 0, persistent
+ * work-queue kernel) or as one captured HIP graph (mode 1).  Plans stay
+ * owned by the caller and must outlive the batch.  Persistent mode covers
+ * CSR_SCALAR, CSR_VECTOR, CSR_ADAPTIVE (unless rows were split into
+ * segments or long rows use their own kernel), ELL, DIA, DIA_DIRECT and
+ * BCSR levels, each with its plan's tile shape, in a kernel compiled for
+ * just the level kinds present; levels with other kernels are launched
+ * separately on the same stream, after the persistent kernel.  Mode 0 takes
+ * 1..4096 plans of one dtype (a run whose vectors differ from the previous
+ * run's uploads the new pointers and waits for that copy); mode 1 takes
+ * 1..4096 plans of any dtypes and kernels (every spmv_run of the batch, in
+ * order, captured on the first run and again whenever the vectors change).
  * EINVAL otherwise. */
 spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplans, int32_t mode,
                               spmv_batch_t *out);

@@ -1,7 +1,8 @@
 // K11 multilevel batch: y_l = A_l x_l for every level of an AMG-style
 // hierarchy (the paper's motivation, Section 1: AMG spends most of its time
-// in SpMV over a series of diverse level matrices).  Coarse levels are far
-// too small to fill the GPU on their own, so
+// in SpMV over a series of diverse level matrices), or for any set of
+// independent SpMVs of one value type (up to kMaxLevels plans).  Small
+// matrices are far too small to fill the GPU on their own, so
 //   mode 0: one persistent launch; workgroup w takes the (level, tile) work
 //           items w, w + grid, w + 2 grid, ... of the list that runs through
 //           the levels in order (largest first), so consecutive workgroups
@@ -18,7 +19,7 @@
 namespace smat {
 namespace {
 
-constexpr int kMaxLevels = 16;        // persistent mode
+constexpr int kMaxLevels = 4096;      // persistent mode
 constexpr int kMaxGraphPlans = 4096;  // graph mode
 constexpr int kPBlock = 256;   // persistent workgroup size
 constexpr int kPDiaRpt = 4;    // rows per thread of a DIA tile
@@ -37,11 +38,6 @@ struct LevelDesc {
     const void *val, *eval, *data, *bval;
     const DiaWindow *win;
     AdaptiveLaunch alaunch;
-};
-
-struct Ptrs {
-    const void *x[kMaxLevels];
-    void *y[kMaxLevels];
 };
 
 template <typename T, int L, bool NT>
@@ -108,8 +104,8 @@ __device__ __forceinline__ void batch_item(const LevelDesc &d, int64_t tile, con
         break;
     case LK_ADAPTIVE:
         if constexpr (!(KINDS & (1u << LK_ADAPTIVE))) break;
-        adaptive_block<T, NT>(d.alaunch, (unsigned)tile, d.rows, d.rp, d.col, (const T *)d.val,
-                              x, y, part);
+        adaptive_block<T, NT, true>(d.alaunch, (unsigned)tile, d.rows, d.rp, d.col,
+                                    (const T *)d.val, x, y, part);
         break;
     case LK_ELL:
         if constexpr (!(KINDS & (1u << LK_ELL))) break;
@@ -162,21 +158,30 @@ __device__ __forceinline__ void batch_item(const LevelDesc &d, int64_t tile, con
 }
 
 // Work items base .. total-1 (items below `base` belong to levels launched
-// on their own before this kernel), strided over the grid.
+// on their own before this kernel), strided over the grid; an item's level
+// is found by binary search over the levels' first items.  xy: the levels'
+// x pointers, then their y pointers.
 template <typename T, unsigned KINDS>
 __global__ __launch_bounds__(kPBlock) void k_batch_persistent(const LevelDesc *__restrict__ L,
                                                               int nlev, int64_t base,
-                                                              int64_t total, Ptrs P) {
+                                                              int64_t total,
+                                                              const void *const *__restrict__ xy) {
     extern __shared__ unsigned char smem_raw[];
     T *xs = reinterpret_cast<T *>(smem_raw);
     __shared__ double part[kPBlock / kWave];
     for (int64_t t = base + blockIdx.x; t < total; t += gridDim.x) {
-        int l = 0;
-        while (l + 1 < nlev && t >= L[l + 1].tile_begin) ++l;
-        const LevelDesc &d = L[l];
+        int lo = 0, hi = nlev - 1;   // the last level whose first item is <= t
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (L[mid].tile_begin <= t)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const LevelDesc &d = L[lo];
         const int64_t tile = t - d.tile_begin;
-        const T *x = (const T *)P.x[l];
-        T *y = (T *)P.y[l];
+        const T *x = (const T *)xy[lo];
+        T *y = (T *)const_cast<void *>(xy[nlev + lo]);
         if (d.nt)
             batch_item<T, true, KINDS>(d, tile, x, y, xs, part);
         else
@@ -311,6 +316,8 @@ struct spmv_batch_s {
     std::vector<int> extra_levels;       // launched separately
     int split = 0;  // leading persistent levels launched as their own kernels instead
     smat::Dev desc;
+    smat::Dev xy;                        // x then y pointers of the persistent levels
+    std::vector<const void *> xy_host;   // what xy holds
     int64_t total_tiles = 0;
     size_t lds_bytes = 0;
     int grid = 0;
@@ -383,9 +390,13 @@ extern "C" spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplan
             // one work item per workgroup of the level's binned launch; rows
             // split into segments or long rows through LDS need their own
             // kernels
-            d.kind = (V.nsplit_rows > 0 || V.long_tpr) ? -1 : LK_ADAPTIVE;
+            d.kind = (V.nsplit_rows > 0 || V.long_tpr || !V.binned_rp.p) ? -1 : LK_ADAPTIVE;
             d.alaunch = V.alaunch;
             d.rows = V.bin_rows.as<int32_t>();
+            // the rows' entries from the plan's copy in binned order
+            d.rp = V.binned_rp.as<int32_t>();
+            d.col = V.binned_col.as<int32_t>();
+            d.val = V.binned_val.p;
             d.tile_rows = 1;
             ntiles = V.alaunch.first[8];
             break;
@@ -442,6 +453,8 @@ extern "C" spmv_status spmv_batch_create(const spmv_plan_t *plans, int32_t nplan
     }
     spmv_status st = B->desc.alloc(sizeof(LevelDesc) * std::max<size_t>(1, descs.size()));
     if (st != SPMV_OK) return st;
+    st = B->xy.alloc(2 * sizeof(void *) * std::max<size_t>(1, descs.size()));
+    if (st != SPMV_OK) return st;
     if (!descs.empty())
         SMAT_HIP(hipMemcpy(B->desc.p, descs.data(), sizeof(LevelDesc) * descs.size(),
                            hipMemcpyHostToDevice));
@@ -487,12 +500,21 @@ extern "C" spmv_status spmv_batch_run(spmv_batch_t B, const void *const *xs, voi
         SMAT_HIP(hipGraphLaunch(B->exec, s));
         return SPMV_OK;
     }
-    Ptrs P{};
-    int k = 0;
-    for (int l : B->persistent_levels) {
-        P.x[k] = xs[l];
-        P.y[k] = ys[l];
-        ++k;
+    {
+        // the persistent levels' vectors, uploaded when they change (the
+        // upload waits for the copy, so that a later change cannot race it)
+        const size_t np = B->persistent_levels.size();
+        std::vector<const void *> v(2 * np);
+        for (size_t k = 0; k < np; ++k) {
+            v[k] = xs[B->persistent_levels[k]];
+            v[np + k] = ys[B->persistent_levels[k]];
+        }
+        if (np && v != B->xy_host) {
+            SMAT_HIP(hipMemcpyAsync(B->xy.p, v.data(), sizeof(void *) * v.size(),
+                                    hipMemcpyHostToDevice, s));
+            SMAT_HIP(hipStreamSynchronize(s));
+            B->xy_host = v;
+        }
     }
     for (int i = 0; i < B->split; ++i) {
         const int l = B->persistent_levels[i];
@@ -509,7 +531,8 @@ extern "C" spmv_status spmv_batch_run(spmv_batch_t B, const void *const *xs, voi
         const int nl = (int)B->persistent_levels.size();
         const int64_t tot = B->total_tiles;
 #define SMAT_PERSISTENT(T, K)                                                                \
-    k_batch_persistent<T, K><<<grid, kPBlock, B->lds_bytes, s>>>(L, nl, base, tot, P)
+    k_batch_persistent<T, K><<<grid, kPBlock, B->lds_bytes, s>>>(L, nl, base, tot,         \
+                                                                 B->xy.as<const void *>())
 #define SMAT_PERSISTENT_SET(T)                                                               \
     do {                                                                                     \
         if ((kinds & ~kKindsRow) == 0)                                                       \

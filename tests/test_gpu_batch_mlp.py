@@ -150,8 +150,11 @@ def test_gather_probe_sums():
 def test_graph_batch_of_many_mixed_plans():
     """Graph mode takes many plans of both dtypes and every kernel class
     (column panels, COO, BCSR, segmented plans included): each replay gives
-    every plan's own result bit for bit, also after the vectors change;
-    persistent mode keeps its limits (16 plans, one dtype)."""
+    every plan's own result bit for bit, also after the vectors change.
+    Persistent mode takes the 20 plans of each dtype in one launch (the
+    kinds it does not hold -- column panels, COO, long rows by tiles --
+    after it, on the same stream), with the same bits and after a change of
+    vectors; it refuses plans of two dtypes."""
     import torch
     from paper_1210_2536_amd.spmv import Batch, Plan
     mats = [S.stencil_7pt(12), S.blocks_g3(np.random.default_rng([72, 0]), 4000),
@@ -192,7 +195,20 @@ def test_graph_batch_of_many_mixed_plans():
             for y in ys:
                 y.fill_(float("nan"))
     B.close()
-    with pytest.raises(capi.SpmvError):
-        Batch(plans[:17], mode=0)
+    for dt in (torch.float64, torch.float32):
+        idx = [i for i, x in enumerate(xs) if x.dtype == dt]
+        note(f"[batch] persistent mode, {len(idx)} plans of {dt}")
+        B = Batch([plans[i] for i in idx], mode=0)
+        for rep in range(2):
+            ys = [torch.full((plans[i].m,), float("nan"), dtype=dt, device="cuda") for i in idx]
+            for _ in range(2):
+                B.run([xs[i] for i in idx], ys)
+                torch.cuda.synchronize()
+                for y, i in zip(ys, idx):
+                    assert np.array_equal(y.cpu().numpy().view(np.uint8),
+                                          refs[i].view(np.uint8)), (rep, i)
+                for y in ys:
+                    y.fill_(float("nan"))
+        B.close()
     with pytest.raises(capi.SpmvError):
         Batch([plans[0], plans[2]], mode=0)   # float64 and float32
