@@ -4,9 +4,11 @@
 A step is one pass of the tuned SpMV (spmv_run of every plan) over the
 workload, with matrices, x and y resident in HBM, issued in the fastest of
 the step modes a short trial compares (back to back, one captured graph,
-the multilevel persistent launch, or concurrent: the dominant kernel's
-plans alone first, then the SpMVs under 50 us on side streams beside the
-larger ones on the main stream).  Plans (validation,
+the multilevel persistent launch, batched: the dominant kernel's plans alone
+first, then the SpMVs under 50 us in one persistent batch launch per value
+type and the larger ones back to back, or concurrent: the dominant
+kernel's plans alone first, then the SpMVs under 50 us on side streams
+beside the larger ones on the main stream).  Plans (validation,
 features, selection, conversion) are built before the timed region; their
 cost is reported separately, in milliseconds and in plain-CSR SpMV units
 (the paper's Table 6 measure).
