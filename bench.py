@@ -146,8 +146,8 @@ def parse():
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on exactly one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is described but not built)"}))
+        print(json.dumps({"error": "the library runs on one GPU only; --gpus must be 1 "
+                                   "(row-block sharding over several GPUs is not implemented)"}))
         sys.exit(2)
     import torch
 
