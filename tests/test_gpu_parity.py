@@ -516,3 +516,33 @@ def test_long_rows_default_mode():
                 assert info["params"]["long_lds"] == want, (A.name, k, info["params"]["long_lds"])
                 assert info["long_rows"] == (2100 if want == 3 else 0)
                 assert_parity(p.run(vec(x, dt)).cpu().numpy(), A, x, dt)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_panel_short_bins_direct(dtype):
+    """Column panels with the shortest length bins summed by the binned
+    kernel without panels (params.panel_direct_max): rows of at most 4, 16
+    or 64 entries direct, the others in the panels (one launch or one per
+    panel), the longest ones by tiles or x chunks; on the 7-point stencil
+    every row is direct from 16 on and the panel launch is empty.  Each
+    output matches the oracle and repeats bit for bit."""
+    from paper_1210_2536_amd.spmv import Plan
+    mats = [S.zipf_g2(np.random.default_rng([88, 0]), 30_000),
+            S.uniform_g1(np.random.default_rng([88, 1]), 12_000),
+            S.stencil_7pt(16)]
+    for i, A in enumerate(mats):
+        x = np.random.default_rng([89, i]).uniform(-1, 1, A.n)
+        rp, col, val = dev(A, dtype)
+        xd = vec(x, dtype)
+        for d in (4, 16, 64):
+            for extra in ({"panel_kib": 16}, {"panel_kib": 16, "panel_xcd": 2},
+                          {"panel_kib": 16, "long_lds": 3, "adaptive_wg_min": 64}):
+                prm = dict(extra, panel_direct_max=d)
+                note(f"[panel direct] {A.name} {np.dtype(dtype).name} {prm}")
+                p = Plan(rp, col, val, n=A.n, selector="csr_panel", params=prm)
+                assert p.info()["params"]["panel_direct_max"] == d
+                y = p.run(xd).cpu().numpy()
+                assert_parity(y, A, x, dtype)
+                y2 = p.run(xd).cpu().numpy()
+                assert np.array_equal(y.view(np.uint8), y2.view(np.uint8))
+                p.close()
