@@ -6,7 +6,8 @@ workload, with matrices, x and y resident in HBM, issued in the fastest of
 the step modes a short trial compares (back to back, one captured graph,
 the multilevel persistent launch, batched: the dominant kernel's plans alone
 first, then the SpMVs under 50 us in one persistent batch launch per value
-type and the larger ones back to back, or concurrent: the dominant
+type, or per value type and kernel family, and the larger ones back to
+back, or concurrent: the dominant
 kernel's plans alone first, then the SpMVs under 50 us on side streams
 beside the larger ones on the main stream).  Plans (validation,
 features, selection, conversion) are built before the timed region; their
@@ -372,20 +373,37 @@ def main():
     # (spmv_batch mode 0; the kinds it does not hold run right after it on
     # the same stream), each on a side stream or all on the current one,
     # beside the larger SpMVs back to back on the current stream.
-    small_batches = []
-    if small_recs and not a.no_batch:
+    # The same SpMVs may instead go into one persistent launch per value
+    # type and kernel family (CSR rows, ELL, DIA, BCSR): the persistent
+    # kernel is compiled for the set of kinds it holds, and a launch that
+    # carries fewer kinds needs fewer registers and keeps more waves in
+    # flight (the gather-bound ELL and CSR families gain the most).
+    def family(r):
+        k = r["rec"]["kernel"]
+        if k in ("csr_scalar", "csr_vector", "csr_adaptive"):
+            return "csr"
+        return {"dia_direct": "dia"}.get(k, k)
+
+    def make_batches(key):
         from paper_1210_2536_amd.spmv import Batch as _Batch
-        by_dtype = {}
+        groups = {}
         for r in small_recs:
-            by_dtype.setdefault(r["tuned"].dtype, []).append(r)
-        for rs in by_dtype.values():
+            groups.setdefault(key(r), []).append(r)
+        out = []
+        for rs in groups.values():
             b = _Batch([r["tuned"] for r in rs], mode=0)
             bx, by = [r["x"] for r in rs], [r["y"] for r in rs]
             b.tune(bx, by)
-            small_batches.append((b, bx, by))
+            out.append((b, bx, by))
+        return out
+
+    small_batches, small_batches_kind = [], []
+    if small_recs and not a.no_batch:
+        small_batches = make_batches(lambda r: r["tuned"].dtype)
+        small_batches_kind = make_batches(lambda r: (r["tuned"].dtype, family(r)))
     batch_evs = [torch.cuda.Event() for _ in small_batches]
 
-    def batched_rest(on_side):
+    def batched_rest(on_side, kinds=False):
         main = torch.cuda.current_stream()
         if on_side:
             fork_ev.record(main)
@@ -394,7 +412,7 @@ def main():
                 b.run(bx, by, stream=st)
                 ev.record(st)
         else:
-            for b, bx, by in small_batches:
+            for b, bx, by in (small_batches_kind if kinds else small_batches):
                 b.run(bx, by)
         for r in rest_recs:
             r["tuned"].run(r["x"], r["y"])
@@ -447,12 +465,15 @@ def main():
             ml["streams"] = {"side_streams": len(side), "small_ms": SMALL_MS,
                              "small_plans": len(small_recs)}
         if small_batches:
-            for name, on_side in (("batched", False), ("batched_streams", True)):
-                def bstep(on_side=on_side):
+            for name, on_side, kinds in (("batched", False, False),
+                                         ("batched_streams", True, False),
+                                         ("batched_kinds", False, True)):
+                def bstep(on_side=on_side, kinds=kinds):
                     for r in dom_recs:
                         r["tuned"].run(r["x"], r["y"])
-                    batched_rest(on_side)
+                    batched_rest(on_side, kinds)
                 ml["trial_ms"][name] = trial(bstep)
+            ml["batched_kinds"] = {"launches": len(small_batches_kind)}
         ml["mode"] = min(ml["trial_ms"], key=ml["trial_ms"].get)
         if replay_step:
             ml["mode"] = replay_step  # profile the recorded run's step, not this trial's pick
@@ -462,14 +483,15 @@ def main():
     # ---- timed region: K steps of every tuned SpMV
     def steps(which, K, events=False):
         evs = []
-        if which == "tuned" and step_mode in ("streams", "batched", "batched_streams"):
+        if which == "tuned" and step_mode in ("streams", "batched", "batched_streams",
+                                              "batched_kinds"):
             pairs = event_pairs(K * len(dom_recs)) if events else None
             for _ in range(K):
                 evs += per_plan(which, 1, events, dom_recs, pairs)
                 if step_mode == "streams":
                     concurrent_rest()
                 else:
-                    batched_rest(step_mode == "batched_streams")
+                    batched_rest(step_mode == "batched_streams", step_mode == "batched_kinds")
             return evs
         if which == "tuned" and step_mode != "separate":
             # a batch launch hides the levels' kernels from stream events
