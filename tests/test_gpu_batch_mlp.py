@@ -212,3 +212,32 @@ def test_graph_batch_of_many_mixed_plans():
         B.close()
     with pytest.raises(capi.SpmvError):
         Batch([plans[0], plans[2]], mode=0)   # float64 and float32
+
+
+@pytest.mark.parametrize("mode", [0, 1], ids=["persistent", "graph"])
+def test_batch_at_its_plan_limit(mode):
+    """A batch holds up to 4096 plans in either mode (here one plan 4096
+    times, each entry with its own x and y): every output equals the plan's
+    own run bit for bit; a 4097th plan is refused."""
+    import torch
+    from paper_1210_2536_amd.spmv import Batch, Plan
+    A = S.stencil_5pt(6)
+    n = 4096
+    rp, col, val = dev(A, np.float64)
+    p = Plan(rp, col, val, n=A.n, selector="csr_vector")
+    X = torch.from_numpy(np.random.default_rng(74).uniform(-1, 1, (n, A.n))).cuda()
+    Y = torch.full((n, A.m), float("nan"), dtype=torch.float64, device="cuda")
+    xs, ys = [X[i] for i in range(n)], [Y[i] for i in range(n)]
+    note(f"[batch] mode {mode}, {n} plans")
+    B = Batch([p] * n, mode=mode)
+    B.run(xs, ys)
+    torch.cuda.synchronize()
+    R = torch.full_like(Y, float("nan"))
+    for i in range(n):
+        p.run(xs[i], R[i])
+    torch.cuda.synchronize()
+    assert torch.equal(Y.view(torch.int64), R.view(torch.int64))
+    assert_parity(Y[n - 1].cpu().numpy(), A, X[n - 1].cpu().numpy(), np.float64)
+    B.close()
+    with pytest.raises(capi.SpmvError):
+        Batch([p] * (n + 1), mode=mode)
