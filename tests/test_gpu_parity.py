@@ -389,6 +389,35 @@ def test_plan_memory_from_the_callers_allocator():
         q.close()
 
 
+
+def test_plan_closed_while_another_stream_runs_it():
+    """A plan built on the current stream runs on a side stream; closing it
+    while those launches are still queued hands its blocks back to PyTorch's
+    caching allocator only once the device is idle, so a tensor allocated
+    and overwritten right after the close (it may take the same blocks)
+    cannot change what the queued runs read."""
+    import torch
+    from paper_1210_2536_amd.spmv import Plan
+    A = S.zipf_g2(np.random.default_rng([91, 0]), 200_000)
+    x = np.random.default_rng([91, 1]).uniform(-1, 1, A.n)
+    rp, col, val = dev(A, np.float64)
+    xd = vec(x, np.float64)
+    side = torch.cuda.Stream()
+    for k in ("csr_adaptive", "coo", "csr_panel"):
+        note(f"[side stream] {k}")
+        p = Plan(rp, col, val, n=A.n, selector=k)
+        held = p.info()["device_bytes"]
+        ys = [torch.empty(A.m, dtype=torch.float64, device="cuda") for _ in range(16)]
+        side.wait_stream(torch.cuda.current_stream())
+        for y in ys:
+            p.run(xd, y, stream=side)
+        p.close()
+        junk = torch.full((held // 8 + 4096,), float("nan"), dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        for y in ys:
+            assert_parity(y.cpu().numpy(), A, x, np.float64)
+        del junk
+
 def test_long_rows_through_lds():
     """float64 rows of the longest bin taken by the kernel that streams x
     through LDS in column chunks (several chunks and a partial one, rows
