@@ -305,6 +305,9 @@ def main():
         if k == "csr_vector":
             return f"k_csr_vector<{t}, {p['vector_lanes']}, {nt}>"
         if k == "csr_adaptive":   # rows read from the plan's copy in binned order
+            if rec.get("long_lanes") and p.get("long_lds") == 3:
+                # the tiles first, then the short rows with the tiles' sums
+                return f"k_long_tiles<{t}> + k_csr_adaptive_tiles<{t}, {nt}, true>"
             return f"k_csr_adaptive{rest}<{t}, {nt}, true>{long}"
         v = (16 // (8 if t == "double" else 4)) if p["wide_loads"] == 1 else 1
         if k == "ell":

@@ -1207,15 +1207,29 @@ spmv_status run_variant(const spmv_plan_s &P, const Variant &V, const void *x, v
         return run_csr_vector(elt, nt, V.prm.vector_lanes, m, P.rp.as<int32_t>(),
                               P.col.as<int32_t>(), P.val.p, x, y, V.prm.block, s);
     case SPMV_K_CSR_ADAPTIVE: {
-        SMAT_TRY(run_csr_adaptive(elt, nt, V.long_tpr != 0, V.long_tpr ? V.arest : V.alaunch,
-                                  V.bin_rows.as<int32_t>(), V.binned_rp.as<int32_t>(),
-                                  V.binned_col.as<int32_t>(), V.binned_val.p, x, y, s, true));
+        if (V.long_tiles) {
+            // the tiles first, then the short rows and the tiles' sums in
+            // one launch
+            SMAT_TRY(run_long_tiles(elt, V.n_long, V.tile_P, V.tile_nb,
+                                    V.tile_blocks.as<int32_t>(), V.tile_pk.as<int32_t>(),
+                                    V.long_rows.as<int32_t>(), V.tile_off.as<uint16_t>(),
+                                    V.tile_val.p, x, P.n, V.tile_part.as<double>(), y, s, false));
+            SMAT_TRY(run_csr_adaptive_tiles(elt, nt, V.arest, V.bin_rows.as<int32_t>(),
+                                            V.binned_rp.as<int32_t>(), V.binned_col.as<int32_t>(),
+                                            V.binned_val.p, x, y, V.n_long, V.tile_P,
+                                            V.long_rows.as<int32_t>(), V.tile_part.as<double>(),
+                                            s));
+        } else {
+            SMAT_TRY(run_csr_adaptive(elt, nt, V.long_tpr != 0, V.long_tpr ? V.arest : V.alaunch,
+                                      V.bin_rows.as<int32_t>(), V.binned_rp.as<int32_t>(),
+                                      V.binned_col.as<int32_t>(), V.binned_val.p, x, y, s, true));
+            if (V.long_tpr) SMAT_TRY(run_long_rows(P, V, x, y, s));
+        }
         if (V.nsplit_rows)
             SMAT_TRY(run_csr_split(elt, V.nsplit_segs, V.split_segs.as<int64_t>(),
                                    V.split_partials.as<double>(), V.nsplit_rows,
                                    V.split_begin.as<int64_t>(), V.split_rows.as<int32_t>(),
                                    P.col.as<int32_t>(), P.val.p, x, y, s));
-        if (V.long_tpr) SMAT_TRY(run_long_rows(P, V, x, y, s));
         return SPMV_OK;
     }
     case SPMV_K_CSR_PANEL: {

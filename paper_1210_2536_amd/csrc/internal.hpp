@@ -192,10 +192,19 @@ spmv_status launch_long_tile_pack(int64_t n7, int64_t P, int64_t W, const int32_
                                   const int32_t *rp, const int32_t *col, const void *val, int elt,
                                   const int32_t *seg, const int32_t *kb, const int32_t *pk,
                                   uint16_t *off, void *pval, hipStream_t s);
+// reduce false: the tiles' partials only, added later by
+// run_csr_adaptive_tiles.
 spmv_status run_long_tiles(int elt, int64_t n7, int64_t P, int64_t nblocks,
                            const int32_t *blocks, const int32_t *pk, const int32_t *rows,
                            const uint16_t *off, const void *val, const void *x, int64_t n,
-                           double *part, void *y, hipStream_t s);
+                           double *part, void *y, hipStream_t s, bool reduce = true);
+// After run_long_tiles(..., reduce = false): the binned launch `a` of the
+// short rows (entries from the binned-order copy) and the sums of the n7
+// long rows' P panel partials `part` into y[lrows[r]], in one launch.
+spmv_status run_csr_adaptive_tiles(int elt, bool nt, const AdaptiveLaunch &a, const int32_t *rows,
+                                   const int32_t *rp, const int32_t *col, const void *val,
+                                   const void *x, void *y, int64_t n7, int64_t P,
+                                   const int32_t *lrows, const double *part, hipStream_t s);
 // Build column panels of width w from a CSR matrix whose rows are visited in
 // the binned order `rows`.  cnt: P*(m+1) ints; prow: P*(m+1)+1 ints; inv: m
 // ints; scan: P*(m+1)/4096+1 unsigned.

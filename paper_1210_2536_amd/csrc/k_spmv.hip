@@ -587,20 +587,33 @@ __global__ __launch_bounds__(kTileThreads) void k_long_tiles(
 // A long row's result: its panel partials added in a fixed order, rounded
 // once.  A workgroup takes 32 rows; thread (g, i) adds the partials of panels
 // g, g + 8, g + 16, ... of row i in that order (32 neighbouring rows per
-// load, eight loads in flight per row), and the eight group sums are added
-// in group order.
+// load, four of a thread's loads issued before their additions), and the
+// eight group sums are added in group order.  Workgroup `bid` of such a
+// reduction; every thread of the 256 calls it.
 constexpr int kReduceRows = 32, kReduceGroups = 8;
 
 template <typename T>
-__global__ __launch_bounds__(kReduceRows * kReduceGroups) void k_long_tiles_reduce(
-    int64_t n7, int64_t P, const int32_t *__restrict__ rows, const double *__restrict__ part,
-    T *__restrict__ y) {
-    __shared__ double gs[kReduceGroups][kReduceRows];
+__device__ __forceinline__ void tiles_reduce_block(unsigned bid, int64_t n7, int64_t P,
+                                                   const int32_t *__restrict__ rows,
+                                                   const double *__restrict__ part,
+                                                   T *__restrict__ y,
+                                                   double (*gs)[kReduceRows]) {
     const int i = threadIdx.x % kReduceRows, g = threadIdx.x / kReduceRows;
-    const int64_t r = (int64_t)blockIdx.x * kReduceRows + i;
+    const int64_t r = (int64_t)bid * kReduceRows + i;
     double acc = 0.0;
-    if (r < n7)
-        for (int64_t p = g; p < P; p += kReduceGroups) acc += part[p * n7 + r];
+    if (r < n7) {
+        constexpr int G = kReduceGroups;
+        int64_t p = g;
+        for (; p + 3 * G < P; p += 4 * G) {
+            const double v0 = part[p * n7 + r], v1 = part[(p + G) * n7 + r];
+            const double v2 = part[(p + 2 * G) * n7 + r], v3 = part[(p + 3 * G) * n7 + r];
+            acc += v0;
+            acc += v1;
+            acc += v2;
+            acc += v3;
+        }
+        for (; p < P; p += G) acc += part[p * n7 + r];
+    }
     gs[g][i] = acc;
     __syncthreads();
     if (g == 0 && r < n7) {
@@ -609,6 +622,36 @@ __global__ __launch_bounds__(kReduceRows * kReduceGroups) void k_long_tiles_redu
         for (int k = 1; k < kReduceGroups; ++k) s += gs[k][i];
         y[rows[r]] = (T)s;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kReduceRows * kReduceGroups) void k_long_tiles_reduce(
+    int64_t n7, int64_t P, const int32_t *__restrict__ rows, const double *__restrict__ part,
+    T *__restrict__ y) {
+    __shared__ double gs[kReduceGroups][kReduceRows];
+    tiles_reduce_block<T>(blockIdx.x, n7, P, rows, part, y, gs);
+}
+
+// The short rows of a binned-CSR plan whose long rows are in tiles, launched
+// after k_long_tiles: workgroups [0, rg) add the long rows' panel partials
+// (as k_long_tiles_reduce), the others are the binned launch of the short
+// rows; the two write disjoint rows of y.  One launch fewer per SpMV, and
+// the partials' loads overlap the short rows' work.
+static_assert(kReduceRows * kReduceGroups == kAdaptBlock, "one workgroup size for both parts");
+
+template <typename T, bool NT, bool PK>
+__global__ __launch_bounds__(kAdaptBlock) void k_csr_adaptive_tiles(
+    AdaptiveLaunch a, const int32_t *__restrict__ rows, const int32_t *__restrict__ rp,
+    const int32_t *__restrict__ col, const T *__restrict__ val, const T *__restrict__ x,
+    T *__restrict__ y, unsigned rg, int64_t n7, int64_t P, const int32_t *__restrict__ lrows,
+    const double *__restrict__ part) {
+    __shared__ double sp[kAdaptBlock / kWave];
+    __shared__ double gs[kReduceGroups][kReduceRows];
+    if (blockIdx.x < rg) {
+        tiles_reduce_block<T>(blockIdx.x, n7, P, lrows, part, y, gs);
+        return;
+    }
+    adaptive_block<T, NT, PK>(a, blockIdx.x - rg, rows, rp, col, val, x, y, sp);
 }
 
 // Segment starts of the long rows in the x panels: seg[p * n7 + r] is the
@@ -1216,7 +1259,7 @@ spmv_status launch_long_tile_pack(int64_t n7, int64_t P, int64_t W, const int32_
 spmv_status run_long_tiles(int elt, int64_t n7, int64_t P, int64_t nblocks,
                            const int32_t *blocks, const int32_t *pk, const int32_t *rows,
                            const uint16_t *off, const void *val, const void *x, int64_t n,
-                           double *part, void *y, hipStream_t s) {
+                           double *part, void *y, hipStream_t s, bool reduce) {
     if (n7 == 0) return SPMV_OK;
     if (P < 1 || P > 65535 || nblocks < 1 || nblocks > INT_MAX || (elt != 4 && elt != 8)) {
         set_error("long-row tiles: %lld panels, %lld row blocks", (long long)P,
@@ -1230,21 +1273,52 @@ spmv_status run_long_tiles(int elt, int64_t n7, int64_t P, int64_t nblocks,
     }
     const unsigned grid = (unsigned)(P * nblocks);
     const unsigned rg = (unsigned)((n7 + kReduceRows - 1) / kReduceRows);
-    if (elt == 8) {
+    if (elt == 8)
         k_long_tiles<double><<<grid, kTileThreads, kTileBytes, s>>>(
             n7, W, P, blocks, pk, off, (const double *)val, (const double *)x, n, part);
-        SMAT_LAUNCHED("long_tiles");
-        k_long_tiles_reduce<double><<<rg, kReduceRows * kReduceGroups, 0, s>>>(n7, P, rows, part,
-                                                                              (double *)y);
-    } else {
+    else
         k_long_tiles<float><<<grid, kTileThreads, kTileBytes, s>>>(
             n7, W, P, blocks, pk, off, (const float *)val, (const float *)x, n, part);
-        SMAT_LAUNCHED("long_tiles");
+    SMAT_LAUNCHED("long_tiles");
+    if (!reduce) return SPMV_OK;
+    if (elt == 8)
+        k_long_tiles_reduce<double><<<rg, kReduceRows * kReduceGroups, 0, s>>>(n7, P, rows, part,
+                                                                              (double *)y);
+    else
         k_long_tiles_reduce<float><<<rg, kReduceRows * kReduceGroups, 0, s>>>(n7, P, rows, part,
                                                                              (float *)y);
-    }
     SMAT_LAUNCHED("long_tiles_reduce");
     return SPMV_OK;
+}
+
+template <typename T>
+spmv_status adaptive_tiles_dispatch(bool nt, const AdaptiveLaunch &a, const int32_t *rows,
+                                    const int32_t *rp, const int32_t *col, const T *val,
+                                    const T *x, T *y, int64_t n7, int64_t P,
+                                    const int32_t *lrows, const double *part, hipStream_t s) {
+    const unsigned rg = (unsigned)((n7 + kReduceRows - 1) / kReduceRows);
+    const unsigned grid = rg + a.first[8];
+    if (grid == 0) return SPMV_OK;
+    if (nt)
+        k_csr_adaptive_tiles<T, true, true><<<grid, kAdaptBlock, 0, s>>>(a, rows, rp, col, val, x,
+                                                                         y, rg, n7, P, lrows, part);
+    else
+        k_csr_adaptive_tiles<T, false, true><<<grid, kAdaptBlock, 0, s>>>(
+            a, rows, rp, col, val, x, y, rg, n7, P, lrows, part);
+    SMAT_LAUNCHED("csr_adaptive_tiles");
+    return SPMV_OK;
+}
+
+spmv_status run_csr_adaptive_tiles(int elt, bool nt, const AdaptiveLaunch &a, const int32_t *rows,
+                                   const int32_t *rp, const int32_t *col, const void *val,
+                                   const void *x, void *y, int64_t n7, int64_t P,
+                                   const int32_t *lrows, const double *part, hipStream_t s) {
+    if (elt == 8)
+        return adaptive_tiles_dispatch<double>(nt, a, rows, rp, col, (const double *)val,
+                                               (const double *)x, (double *)y, n7, P, lrows, part,
+                                               s);
+    return adaptive_tiles_dispatch<float>(nt, a, rows, rp, col, (const float *)val,
+                                          (const float *)x, (float *)y, n7, P, lrows, part, s);
 }
 
 spmv_status run_csr_split(int elt, int64_t nseg, const int64_t *segs, double *partials,
