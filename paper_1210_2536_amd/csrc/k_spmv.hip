@@ -473,8 +473,9 @@ __global__ __launch_bounds__(kLongThreads) void k_long_rows_lds(
 // lane t of the row's TPR lanes takes the segment's entries t, t + TPR, ...
 // in order, TPR being set per block so that short and long segments both
 // keep the lanes busy.  The lane sums are added by xor shuffles into one
-// float64 partial per (row, panel), and k_long_tiles_reduce adds a row's
-// partials in panel order and rounds once.  A row's float64 chain is at most
+// float64 partial per (row, panel), and k_long_tiles_reduce (or, in binned
+// CSR, the first workgroups of k_csr_adaptive_tiles) adds a row's partials
+// in panel order and rounds once.  A row's float64 chain is at most
 // (longest segment) / TPR + log2 TPR + panels long.
 //
 // The entries come packed in workgroup order (row block, panel, row; see
