@@ -11,7 +11,6 @@ so the oracle always answers in float64.
 from __future__ import annotations
 
 import ctypes
-import os
 
 import numpy as np
 

@@ -147,7 +147,6 @@ def _bad_csr_cases():
 
 
 def test_invalid_csr_is_rejected():
-    import torch
     from paper_1210_2536_amd import capi as C
     from paper_1210_2536_amd.spmv import Plan
     good, cases = _bad_csr_cases()
